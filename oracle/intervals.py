@@ -1,0 +1,116 @@
+"""Destination elementary intervals and exact candidate lists.  TEST INFRASTRUCTURE.
+
+Not in the paper: the learned index is this project's addition on top of the
+paper's scan.  Everything here is written from set definitions, with no
+blocking, splitting or truncation tricks, so a reader can check it by eye:
+
+* a rule's destination prefix (base, len) covers the addresses whose top
+  ``len`` bits equal the base's: the range [lo, hi] with
+  lo = base with its low 32-len bits cleared and hi = lo + 2**(32-len) - 1;
+* the boundary set B is {0} together with every lo and every hi + 1 that
+  still fits in 32 bits, sorted and de-duplicated;
+* elementary interval j is [B[j], B[j+1] - 1] (the last ends at 2**32 - 1),
+  and an address x lies in the interval j with B[j] <= x < B[j+1];
+* the candidate list C_j holds, in ascending rule order, every rule whose
+  destination range contains the whole interval j.
+
+Because every lo and every hi + 1 is a boundary, each destination range is a
+union of whole intervals, so a packet whose destination lies in interval j
+matches rule r's destination field exactly when r is in C_j.  The first match
+over C_j therefore equals the first match over the whole list.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+TOP = 2**32 - 1
+
+
+def dst_ranges(rules):
+    """Per-rule destination range [lo, hi] as Python-int-safe uint64 arrays."""
+    base = np.asarray(rules.dst_ip, dtype=np.uint64)
+    plen = np.asarray(rules.dst_plen, dtype=np.uint64)
+    span = np.left_shift(np.uint64(1), np.uint64(32) - plen)        # 2**(32-len)
+    lo = (base // span) * span                                       # clear low bits
+    hi = lo + span - np.uint64(1)
+    return lo, hi
+
+
+def boundaries(rules) -> np.ndarray:
+    """Sorted unique boundary set B (uint32)."""
+    lo, hi = dst_ranges(rules)
+    ends = hi[hi < TOP] + np.uint64(1)
+    b = np.unique(np.concatenate([np.zeros(1, np.uint64), lo, ends]))
+    return b.astype(np.uint32)
+
+
+def interval_of(B: np.ndarray, x) -> np.ndarray:
+    """Index j of the interval holding each address: the largest j with B[j] <= x."""
+    return np.searchsorted(B.astype(np.uint64), np.asarray(x, dtype=np.uint64),
+                           side="right") - 1
+
+
+def interval_end(B: np.ndarray) -> np.ndarray:
+    """Last address of each interval (uint64)."""
+    b = B.astype(np.uint64)
+    return np.concatenate([b[1:] - np.uint64(1), np.array([TOP], np.uint64)])
+
+
+def candidates(rules, B: np.ndarray):
+    """C_j for every interval j: list of int64 arrays of rule indices, ascending."""
+    lo, hi = dst_ranges(rules)
+    start = B.astype(np.uint64)
+    end = interval_end(B)
+    out = []
+    for j in range(B.shape[0]):
+        cover = (lo <= start[j]) & (end[j] <= hi)
+        out.append(np.nonzero(cover)[0])
+    return out
+
+
+def full_match_in_interval(rules) -> np.ndarray:
+    """Rules that match every packet whose destination they cover.
+
+    Such a rule leaves source, both ports and protocol unspecified (source
+    prefix length 0, both port ranges [0, 65535], any protocol).  Once a
+    candidate list reaches one, later entries can never be a first match.
+    """
+    return ((np.asarray(rules.src_plen) == 0)
+            & (np.asarray(rules.sport_lo) == 0) & (np.asarray(rules.sport_hi) == 65535)
+            & (np.asarray(rules.dport_lo) == 0) & (np.asarray(rules.dport_hi) == 65535)
+            & (np.asarray(rules.proto_any) != 0))
+
+
+def truncated(cand: np.ndarray, full: np.ndarray) -> np.ndarray:
+    """The list up to and including its first full-match entry (the rest is unreachable)."""
+    hit = np.nonzero(full[cand])[0]
+    return cand if hit.size == 0 else cand[: hit[0] + 1]
+
+
+def _field_match(rules, r, src, sport, dport, proto) -> bool:
+    """Source, port and protocol tests of rule r (destination is implied by the list)."""
+    plen = int(rules.src_plen[r])
+    if plen and ((int(src) ^ int(rules.src_ip[r])) >> (32 - plen)) != 0:
+        return False
+    if not (int(rules.sport_lo[r]) <= int(sport) <= int(rules.sport_hi[r])):
+        return False
+    if not (int(rules.dport_lo[r]) <= int(dport) <= int(rules.dport_hi[r])):
+        return False
+    return bool(rules.proto_any[r]) or int(rules.proto[r]) == int(proto)
+
+
+def first_match_via_candidates(rules, B, cand, packets):
+    """Per packet: locate its interval, then the first rule of C_j whose other fields match.
+
+    Pure-Python loops: for small inputs only.
+    """
+    j = interval_of(B, packets.dst_ip)
+    out = np.full(len(j), -1, dtype=np.int32)
+    for i in range(len(j)):
+        for r in cand[j[i]]:
+            if _field_match(rules, r, packets.src_ip[i], packets.sport[i],
+                            packets.dport[i], packets.proto[i]):
+                out[i] = r
+                break
+    return out
