@@ -1,0 +1,251 @@
+/*
+ * fw.h -- C interface of the MI355X (gfx950) first-match packet classifier.
+ *
+ * The operation (paper, Section I): an ordered list of filtering rules is
+ * consulted in insertion order; the first rule that matches a packet decides
+ * its action ("first match"); a packet that no rule matches is denied
+ * ("default deny").  Each rule (paper, Section IV) is a 5-tuple -- source and
+ * destination IPv4 address, source and destination port, protocol -- plus an
+ * action, and a field that a rule leaves unspecified matches every value.
+ *
+ * Three ways to compute the same result are offered:
+ *  - packet split: every GPU lane owns whole packets and walks the whole
+ *    rule list (the paper's data-parallel firewall, Section IV-A: each node
+ *    holds a duplicate of the policy, each packet goes to one node);
+ *  - rule split: the rule list is cut into P contiguous partitions, the lanes
+ *    of one packet each scan one partition, and the partial first matches are
+ *    merged by a minimum over rule indices (the paper's function-parallel
+ *    firewall, Section IV-B, where each node holds a part of the policy; the
+ *    paper merges on the CPU, here the merge runs on the GPU);
+ *  - learned index: a small network trained on the rule list's destination
+ *    interval boundaries locates each packet's destination interval, and
+ *    only that interval's exact candidate rules are scanned.  Not in the
+ *    paper; its results are identical to the scan by construction.
+ *
+ * Conventions for every entry point:
+ *  - all integers are host byte order: 10.0.0.1 is 0x0A000001;
+ *  - packet and output buffers are DEVICE pointers owned by the caller, each
+ *    16-byte aligned; they must stay valid until the work on the given HIP
+ *    stream has completed;
+ *  - classification calls are asynchronous on the given stream (the null
+ *    stream when none is given) and return once the work is enqueued;
+ *  - errors come back as an fw_status; fw_last_error() then describes the
+ *    most recent failure of the calling thread.  Errors found while
+ *    enqueueing are reported at once; a device fault in earlier asynchronous
+ *    work is reported by a later call as FW_E_DEVICE;
+ *  - a ruleset is immutable once loaded (building its learned index aside)
+ *    and may be used concurrently by classification calls on different
+ *    streams.
+ */
+#ifndef FW_H
+#define FW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum fw_status {
+    FW_OK = 0,
+    FW_E_INVAL = -1,    /* bad argument or invalid rule */
+    FW_E_ALIGN = -2,    /* a device buffer is not 16-byte aligned */
+    FW_E_NOMEM = -3,    /* device or host allocation failed, or over a memory budget */
+    FW_E_DEVICE = -4,   /* a HIP runtime call or kernel failed */
+    FW_E_NOINDEX = -5   /* learned mode asked for, but no learned index is built */
+} fw_status;
+
+typedef enum fw_action { FW_DROP = 0, FW_ACCEPT = 1 } fw_action;
+
+typedef enum fw_mode {
+    FW_MODE_AUTO = 0,          /* learned index when built, else packet split */
+    FW_MODE_PACKET_SPLIT = 1,  /* data-parallel scan (paper Section IV-A) */
+    FW_MODE_RULE_SPLIT = 2,    /* function-parallel scan (paper Section IV-B) */
+    FW_MODE_LEARNED = 3,       /* learned destination index + candidate scan */
+    FW_MODE_HYBRID = 4         /* a workgroup per packet group, its waves split the rules
+                                  (paper Section IV-C) */
+} fw_mode;
+
+/*
+ * One rule, 24 bytes, host memory.  Fields (paper Section IV):
+ *  src_ip/src_plen, dst_ip/dst_plen: CIDR prefix; length 0..32, 0 matches
+ *      every address; bits of the base below the prefix are ignored;
+ *  sport_lo..sport_hi, dport_lo..dport_hi: inclusive port ranges; [0, 65535]
+ *      matches every port; ports are compared for every protocol;
+ *  proto, proto_any: proto_any != 0 matches every protocol, else the packet's
+ *      protocol must equal proto (0 is an ordinary value);
+ *  action: FW_DROP or FW_ACCEPT (the paper's QUEUE target is not supported).
+ */
+typedef struct fw_rule {
+    uint32_t src_ip, dst_ip;
+    uint8_t src_plen, dst_plen;
+    uint8_t proto, proto_any;
+    uint16_t sport_lo, sport_hi, dport_lo, dport_hi;
+    uint8_t action;
+    uint8_t _pad[3];
+} fw_rule;
+
+/* A batch of packet headers as five device arrays (structure of arrays),
+ * each 16-byte aligned, element i of each array belonging to packet i. */
+typedef struct fw_packets {
+    const uint32_t *src_ip;
+    const uint32_t *dst_ip;
+    const uint16_t *src_port;
+    const uint16_t *dst_port;
+    const uint8_t *proto;
+} fw_packets;
+
+/* Opaque ruleset handle: the library owns its host and device memory. */
+typedef struct fw_ruleset fw_ruleset;
+
+typedef struct fw_classify_opts {
+    uint32_t mode;          /* fw_mode */
+    uint32_t partitions;    /* rule split / hybrid: partition count P >= 1; 0 means 16 */
+    void *stream;           /* hipStream_t to enqueue on; NULL = null stream */
+    uint32_t lookup;        /* learned mode: 0 = network + error window (default),
+                               1 = full binary search with the network skipped */
+    uint32_t packets_per_lane; /* packet split: 1, 2 or 4; 0 = library default */
+    uint64_t *window_misses;   /* learned mode, optional HOST pointer: when given the call
+                                  waits for its work and stores how many packets' error
+                                  window missed (they fell back to a full search) */
+} fw_classify_opts;
+
+/*
+ * Compile `n_rules` rules into a device-resident ruleset.  The rules are
+ * copied; the caller may free `rules` on return.  `default_action` (FW_DROP
+ * or FW_ACCEPT) applies to packets no rule matches.  n_rules may be 0 (every
+ * packet then takes the default) and at most 16,777,216.
+ * Errors: FW_E_INVAL for a null `out`, null `rules` with n_rules > 0, a
+ * prefix length above 32, a port range with lo > hi, or an action or
+ * default_action above 1; FW_E_NOMEM / FW_E_DEVICE from the device.  On any
+ * error *out is left NULL.
+ */
+fw_status fw_load_ruleset(const fw_rule *rules, uint32_t n_rules, uint8_t default_action,
+                          fw_ruleset **out);
+
+/* Free a ruleset and its learned index.  Waits for all device work first.
+ * NULL is accepted and ignored. */
+fw_status fw_free_ruleset(fw_ruleset *rs);
+
+/* Number of rules in a ruleset (0 for NULL). */
+uint32_t fw_ruleset_size(const fw_ruleset *rs);
+
+/*
+ * First match of `n` packets (paper Sections I and IV): out_rule_idx[i] is the
+ * lowest index of a rule matching packet i, or -1; out_action[i] is that
+ * rule's action, or the ruleset's default.  Every i < n is written exactly
+ * once.  Mode FW_MODE_AUTO on the null stream.  n == 0 enqueues nothing.
+ * Errors: FW_E_INVAL (null ruleset, packets or outputs with n > 0),
+ * FW_E_ALIGN (a buffer not 16-byte aligned), FW_E_DEVICE (launch failure or
+ * an earlier device fault).
+ */
+fw_status fw_classify(const fw_ruleset *rs, const fw_packets *pk, size_t n,
+                      int32_t *out_rule_idx, uint8_t *out_action);
+
+/* As fw_classify, with a mode, a partition count, a stream and learned-index
+ * options (`opts` may be NULL).  FW_E_NOINDEX when FW_MODE_LEARNED is asked
+ * for before fw_build_learned_index succeeded; FW_E_INVAL for an unknown
+ * mode, partitions above the rule count's limit of 65,536, or a
+ * packets_per_lane other than 0, 1, 2 or 4. */
+fw_status fw_classify_ex(const fw_ruleset *rs, const fw_packets *pk, size_t n,
+                         int32_t *out_rule_idx, uint8_t *out_action,
+                         const fw_classify_opts *opts);
+
+/* ------------------------------------------------------------------ learned index
+ * Not in the paper.  Destination elementary intervals: B is {0} with every
+ * rule's destination range start and every range end + 1 (when below 2^32),
+ * sorted and de-duplicated; interval j is [B[j], B[j+1]).  Candidate list C_j
+ * is the ascending list of rules whose destination range contains interval j;
+ * the first match over C_j equals the first match over all rules.  A
+ * two-stage recursive model index (one stage-1 network routing to `experts`
+ * stage-2 networks, each 1 -> hidden -> 1 with ReLU) predicts j from a
+ * destination address; a per-expert maximum error bounds the search window,
+ * and a window miss falls back to a full binary search, so results never
+ * depend on the network's accuracy. */
+
+typedef struct fw_index_opts {
+    uint32_t experts;       /* stage-2 experts, 1..256; 0 = 64 */
+    uint32_t hidden;        /* hidden units of every network, 1..32; 0 = 32 */
+    uint32_t epochs1;       /* stage-1 Adam steps; 0 = library default */
+    uint32_t epochs2;       /* stage-2 Adam steps; 0 = library default */
+    float lr;               /* Adam learning rate; 0 = library default */
+    uint32_t seed;          /* weight initialisation seed */
+    uint32_t train;         /* 0 = keep the random initial weights (ablation) */
+    uint32_t use_mfma;      /* 1 = bf16 MFMA for the weight-gradient products (default),
+                               0 = plain fp32 reduction (for checking) */
+    uint64_t mem_budget;    /* device bytes the index may use; 0 = no limit */
+    void *stream;           /* hipStream_t; NULL = null stream.  The build waits for it. */
+} fw_index_opts;
+
+typedef struct fw_index_stats {
+    uint32_t n_boundaries;  /* |B| */
+    uint32_t n_global;      /* destination-wildcard candidates kept (shared by all intervals) */
+    uint64_t n_list_entries;/* per-interval candidate entries kept */
+    uint32_t max_list;      /* longest per-interval list */
+    uint32_t err_max;       /* largest per-expert error bound (positions) */
+    float err_mean;         /* mean per-expert error bound */
+    float loss1, loss2;     /* final training losses of stage 1 and stage 2 */
+    float train_ms;         /* wall time of the GPU training */
+    uint64_t device_bytes;  /* device memory held by the index */
+} fw_index_stats;
+
+/* Build (or rebuild) the learned index of `rs`: intervals and candidate lists
+ * on the host, network training on the GPU with the library's own forward,
+ * backward and Adam kernels, bf16 quantisation, and error bounds measured
+ * with the inference kernel itself.  `opts` and `stats` may be NULL.
+ * Synchronous.  Must not run while `rs` is used by other calls.
+ * Errors: FW_E_INVAL (bad options), FW_E_NOMEM (over mem_budget or
+ * allocation failure; `rs` stays usable in the scan modes), FW_E_DEVICE. */
+fw_status fw_build_learned_index(fw_ruleset *rs, const fw_index_opts *opts,
+                                 fw_index_stats *stats);
+
+/* Interval index j of each destination address in `keys` (device, n entries,
+ * 16-byte aligned), written to `out_interval` (device int32), through the
+ * learned lookup (network + window, or binary search when `lookup` == 1).
+ * Asynchronous on `stream`.  FW_E_NOINDEX without an index. */
+fw_status fw_index_lookup(const fw_ruleset *rs, const uint32_t *keys, size_t n,
+                          int32_t *out_interval, uint32_t lookup, void *stream);
+
+/* Copy parts of the learned index to host memory.  `what`:
+ *  0 = boundaries B (uint32, |B| entries);
+ *  1 = per-interval list offsets (uint32, |B| + 1 entries);
+ *  2 = per-interval list entries (uint32 rule indices);
+ *  3 = global list (uint32 rule indices of destination-wildcard candidates);
+ *  4 = per-expert error bounds (uint32, `experts` entries);
+ *  5 = network weights as float (stage 1 then the experts, each
+ *      [w1 (H), b1 (H), w2 (H), b2]), after bf16 quantisation.
+ * At most `cap` bytes are written; *size receives the full size in bytes.
+ * FW_E_NOINDEX without an index. */
+fw_status fw_index_export(const fw_ruleset *rs, uint32_t what, void *host, size_t cap,
+                          size_t *size);
+
+/* ------------------------------------------------------------------ network kernels
+ * Direct access to the training kernels, for checking them against a CPU
+ * reference.  One stage of E networks 1 -> H -> 1 (ReLU), parameters laid out
+ * per network as [w1 (H), b1 (H), w2 (H), b2]; sample n has input u[n],
+ * target t[n] and trains network expert[n].  The loss is the sum over
+ * networks of each network's mean squared error over its own samples.  All
+ * pointers are HOST memory; the call copies in, runs forward and backward on
+ * the device (with bf16 MFMA weight-gradient products when use_mfma != 0)
+ * and copies the gradient (E * (3H + 1) floats) and per-network loss (E
+ * floats, may be NULL) back.  Synchronous. */
+fw_status fw_rmi_gradients(uint32_t E, uint32_t H, const float *params, size_t n,
+                           const float *u, const float *t, const uint32_t *expert,
+                           uint32_t use_mfma, float *grad, float *loss);
+
+/* One Adam step (Kingma and Ba, bias-corrected) on `count` parameters with the
+ * library's optimiser kernel.  Host pointers; params, m and v are updated in
+ * place.  `step` counts from 1.  Synchronous. */
+fw_status fw_rmi_adam_step(size_t count, float *params, const float *grad, float *m,
+                           float *v, uint32_t step, float lr, float beta1, float beta2,
+                           float eps);
+
+/* Description of the calling thread's most recent error ("" if none). */
+const char *fw_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FW_H */

@@ -1,0 +1,50 @@
+// Internal declarations shared by the library's host and device sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace fw {
+
+// A compiled rule as the kernels read it: 32 bytes, every field a range test
+// (v - lo) <= w in unsigned arithmetic, so a prefix (base, len) becomes
+// lo = base with the low 32-len bits cleared and w = 2^(32-len) - 1.
+//   port_lo = sport_lo << 16 | dport_lo,  port_w = sport_w << 16 | dport_w
+//   proto   = proto_lo | proto_w << 8 | action << 16   (any protocol: lo 0, w 255)
+//   idx     = the rule's position in the original list
+struct alignas(32) RuleRec {
+    uint32_t src_lo, src_w;
+    uint32_t dst_lo, dst_w;
+    uint32_t port_lo, port_w;
+    uint32_t proto;
+    uint32_t idx;
+};
+static_assert(sizeof(RuleRec) == 32, "rule record must stay 32 bytes");
+
+constexpr uint32_t kNoMatch = 0xFFFFFFFFu;
+constexpr uint32_t kMaxRules = 1u << 24;
+constexpr uint32_t kMaxPartitions = 65536;
+
+struct PacketsDev {
+    const uint32_t* src;
+    const uint32_t* dst;
+    const uint16_t* sport;
+    const uint16_t* dport;
+    const uint8_t* proto;
+};
+
+// ---- scan launchers (scan.hip); all asynchronous on `stream`
+hipError_t launch_packet_split(const RuleRec* rules, uint32_t n_rules, PacketsDev pk,
+                               size_t n, int32_t* out_idx, uint8_t* out_act,
+                               uint8_t default_action, int packets_per_lane,
+                               hipStream_t stream);
+hipError_t launch_rule_split(const RuleRec* rules, uint32_t n_rules, uint32_t partitions,
+                             PacketsDev pk, size_t n, int32_t* out_idx, uint8_t* out_act,
+                             uint8_t default_action, hipStream_t stream);
+hipError_t launch_hybrid(const RuleRec* rules, uint32_t n_rules, uint32_t partitions,
+                         PacketsDev pk, size_t n, int32_t* out_idx, uint8_t* out_act,
+                         uint8_t default_action, hipStream_t stream);
+
+}  // namespace fw

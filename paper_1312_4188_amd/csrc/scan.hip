@@ -1,0 +1,431 @@
+// First-match scan kernels for gfx950 (CDNA4, wave64).
+//
+// Paper Section I: rules are tried in insertion order and the first match
+// decides; no match means the default action.  Section IV-A (data parallel):
+// every node holds the whole policy and each packet goes to exactly one node;
+// here a node is a GPU lane.  Section IV-B (function parallel): the policy is
+// split into parts, every node sees every packet, and the partial results
+// are combined; here the parts are contiguous rule partitions and the
+// combination is a minimum over rule indices.  Section IV-C (hybrid): a block
+// per packet group, its threads splitting the rules.
+//
+// Every field test is the unsigned range test (v - lo) <= w (see RuleRec).
+#include "fw_internal.h"
+
+namespace fw {
+namespace {
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+__device__ __forceinline__ bool in_range(uint32_t v, uint32_t lo, uint32_t w) {
+    return (v - lo) <= w;
+}
+
+// Both ports at once: packed 16-bit subtract, packed 16-bit max, one compare.
+// max(v - lo, w) == w holds in both halves exactly when both differences are <= w.
+__device__ __forceinline__ bool ports_in(uint32_t pp, uint32_t lo, uint32_t w) {
+    u16x2 d = __builtin_bit_cast(u16x2, pp) - __builtin_bit_cast(u16x2, lo);
+    u16x2 m = __builtin_elementwise_max(d, __builtin_bit_cast(u16x2, w));
+    return __builtin_bit_cast(uint32_t, m) == w;
+}
+
+__device__ __forceinline__ uint32_t proto_lo(uint32_t p) { return p & 0xFFu; }
+__device__ __forceinline__ uint32_t proto_w(uint32_t p) { return (p >> 8) & 0xFFu; }
+__device__ __forceinline__ uint32_t rule_action(uint32_t p) { return (p >> 16) & 1u; }
+
+__device__ __forceinline__ uint32_t umin(uint32_t a, uint32_t b) { return a < b ? a : b; }
+
+// Load K consecutive packets starting at p0 (p0 is a multiple of K).  Full
+// groups use one 128-bit (K=4), 64-bit (K=2) or 32-bit load per address array;
+// the ragged tail falls back to element loads.
+template <int K>
+__device__ __forceinline__ void load_packets(const PacketsDev& pk, size_t p0, size_t n,
+                                             uint32_t (&src)[K], uint32_t (&dst)[K],
+                                             uint32_t (&pp)[K], uint32_t (&pr)[K]) {
+    if (p0 + K <= n) {
+        if constexpr (K == 4) {
+            const uint4 s = *reinterpret_cast<const uint4*>(pk.src + p0);
+            const uint4 d = *reinterpret_cast<const uint4*>(pk.dst + p0);
+            const uint2 sp = *reinterpret_cast<const uint2*>(pk.sport + p0);
+            const uint2 dp = *reinterpret_cast<const uint2*>(pk.dport + p0);
+            const uint32_t p = *reinterpret_cast<const uint32_t*>(pk.proto + p0);
+            src[0] = s.x; src[1] = s.y; src[2] = s.z; src[3] = s.w;
+            dst[0] = d.x; dst[1] = d.y; dst[2] = d.z; dst[3] = d.w;
+            // packed pair = sport << 16 | dport
+            pp[0] = (sp.x << 16) | (dp.x & 0xFFFFu);
+            pp[1] = (sp.x & 0xFFFF0000u) | (dp.x >> 16);
+            pp[2] = (sp.y << 16) | (dp.y & 0xFFFFu);
+            pp[3] = (sp.y & 0xFFFF0000u) | (dp.y >> 16);
+            pr[0] = p & 0xFFu; pr[1] = (p >> 8) & 0xFFu;
+            pr[2] = (p >> 16) & 0xFFu; pr[3] = p >> 24;
+            return;
+        } else if constexpr (K == 2) {
+            const uint2 s = *reinterpret_cast<const uint2*>(pk.src + p0);
+            const uint2 d = *reinterpret_cast<const uint2*>(pk.dst + p0);
+            const uint32_t sp = *reinterpret_cast<const uint32_t*>(pk.sport + p0);
+            const uint32_t dp = *reinterpret_cast<const uint32_t*>(pk.dport + p0);
+            const uint32_t p = *reinterpret_cast<const uint16_t*>(pk.proto + p0);
+            src[0] = s.x; src[1] = s.y;
+            dst[0] = d.x; dst[1] = d.y;
+            pp[0] = (sp << 16) | (dp & 0xFFFFu);
+            pp[1] = (sp & 0xFFFF0000u) | (dp >> 16);
+            pr[0] = p & 0xFFu; pr[1] = p >> 8;
+            return;
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+        const size_t i = p0 + s;
+        const bool ok = i < n;
+        src[s] = ok ? pk.src[i] : 0u;
+        dst[s] = ok ? pk.dst[i] : 0u;
+        pp[s] = ok ? ((uint32_t(pk.sport[i]) << 16) | pk.dport[i]) : 0u;
+        pr[s] = ok ? uint32_t(pk.proto[i]) : 0u;
+    }
+}
+
+template <int K>
+__device__ __forceinline__ void store_results(int32_t* out_idx, uint8_t* out_act, size_t p0,
+                                              size_t n, const uint32_t (&best)[K],
+                                              const uint32_t (&act)[K]) {
+    if (p0 + K <= n) {
+        if constexpr (K == 4) {
+            *reinterpret_cast<int4*>(out_idx + p0) =
+                make_int4(int(best[0]), int(best[1]), int(best[2]), int(best[3]));
+            *reinterpret_cast<uint32_t*>(out_act + p0) =
+                act[0] | (act[1] << 8) | (act[2] << 16) | (act[3] << 24);
+            return;
+        } else if constexpr (K == 2) {
+            *reinterpret_cast<int2*>(out_idx + p0) = make_int2(int(best[0]), int(best[1]));
+            *reinterpret_cast<uint16_t*>(out_act + p0) = uint16_t(act[0] | (act[1] << 8));
+            return;
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+        if (p0 + s < n) {
+            out_idx[p0 + s] = int32_t(best[s]);
+            out_act[p0 + s] = uint8_t(act[s]);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ packet split
+// A wave owns 64*K packets (K per lane) and walks the rules in order.  The rule
+// address is wave-uniform, so each 32-byte record arrives through one scalar
+// load and the field tests take their rule operands from SGPRs.  A ballot per
+// field turns the lanes' tests into a wave mask: when no live lane passes a
+// field the rest of the rule is skipped (most rules are rejected by the
+// destination test alone), and once every live lane has matched the wave
+// stops.
+template <int K>
+__global__ __launch_bounds__(256) void k_packet_split(const RuleRec* __restrict__ rules,
+                                                      uint32_t n_rules, PacketsDev pk, size_t n,
+                                                      int32_t* __restrict__ out_idx,
+                                                      uint8_t* __restrict__ out_act,
+                                                      uint32_t dflt) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const size_t wave = (size_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const size_t wave_first = wave * 64u * K;
+    if (wave_first >= n) return;  // wave-uniform
+    const size_t p0 = wave_first + size_t(lane) * K;
+
+    uint32_t src[K], dst[K], pp[K], pr[K];
+    load_packets<K>(pk, p0, n, src, dst, pp, pr);
+
+    uint64_t live[K];
+    uint32_t best[K], act[K];
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+        live[s] = ballot(p0 + s < n);
+        best[s] = kNoMatch;
+        act[s] = dflt;
+    }
+
+    for (uint32_t r = 0; r < n_rules; ++r) {
+        const RuleRec q = rules[r];
+        uint64_t m[K];
+        uint64_t any = 0;
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            m[s] = ballot(in_range(dst[s], q.dst_lo, q.dst_w)) & live[s];
+            any |= m[s];
+        }
+        if (any == 0) continue;
+        any = 0;
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            m[s] &= ballot(in_range(src[s], q.src_lo, q.src_w));
+            any |= m[s];
+        }
+        if (any == 0) continue;
+        any = 0;
+        const uint32_t plo = proto_lo(q.proto), pw = proto_w(q.proto);
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            m[s] &= ballot(ports_in(pp[s], q.port_lo, q.port_w)) &
+                    ballot(in_range(pr[s], plo, pw));
+            any |= m[s];
+        }
+        if (any == 0) continue;
+        const uint32_t ra = rule_action(q.proto);
+        uint64_t left = 0;
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            if ((m[s] >> lane) & 1u) {
+                best[s] = r;
+                act[s] = ra;
+            }
+            live[s] &= ~m[s];
+            left |= live[s];
+        }
+        if (left == 0) break;
+    }
+    store_results<K>(out_idx, out_act, p0, n, best, act);
+}
+
+// ------------------------------------------------------------------ rule split
+// Minimum over the LP lanes of one packet group, with DPP lane permutations
+// (quad swaps, half-row and row mirrors), one swizzle across the two rows of a
+// 32-lane half, and a readlane pair across the halves.  Every lane of the
+// group receives the minimum.  Must be called with the whole wave active.
+template <int LP>
+__device__ __forceinline__ uint32_t group_min(uint32_t v) {
+    if constexpr (LP >= 2)   // quad_perm [1,0,3,2]
+        v = umin(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0xB1, 0xF, 0xF, false)));
+    if constexpr (LP >= 4)   // quad_perm [2,3,0,1]
+        v = umin(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x4E, 0xF, 0xF, false)));
+    if constexpr (LP >= 8)   // row_half_mirror: lane i <-> 7 - i within each half row
+        v = umin(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x141, 0xF, 0xF, false)));
+    if constexpr (LP >= 16)  // row_mirror: lane i <-> 15 - i within each row
+        v = umin(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x140, 0xF, 0xF, false)));
+    if constexpr (LP >= 32)  // swizzle, bit mode: lane ^ 16 within each 32-lane half
+        v = umin(v, uint32_t(__builtin_amdgcn_ds_swizzle(int(v), 0x401F)));
+    if constexpr (LP >= 64) {
+        const uint32_t a = __builtin_amdgcn_readlane(int(v), 0);
+        const uint32_t b = __builtin_amdgcn_readlane(int(v), 32);
+        v = umin(a, b);
+    }
+    return v;
+}
+
+__device__ __forceinline__ bool full_match(const RuleRec& q, uint32_t src, uint32_t dst,
+                                           uint32_t pp, uint32_t pr) {
+    return in_range(dst, q.dst_lo, q.dst_w) && in_range(src, q.src_lo, q.src_w) &&
+           ports_in(pp, q.port_lo, q.port_w) && in_range(pr, proto_lo(q.proto), proto_w(q.proto));
+}
+
+// Lane = (packet slot, partition).  LP lanes share one packet; lane `sub` of a
+// slot scans partition blk*64 + sub, i.e. rules [part*S, min(R, part*S + S)).
+// A lane stops at its partition's first match.  Every kPrune rules the group
+// minimum is taken again and lanes whose next rule lies beyond it stop: no
+// later find could win.  With more than 64 partitions a packet spans
+// `wpp` waves whose minima meet through atomicMin on the 32-bit index.
+constexpr int kPrune = 8;
+
+template <int LP>
+__global__ __launch_bounds__(256) void k_rule_split(const RuleRec* __restrict__ rules,
+                                                    uint32_t n_rules, uint32_t P, uint32_t S,
+                                                    uint32_t wpp, PacketsDev pk, size_t n,
+                                                    int32_t* __restrict__ out_idx,
+                                                    uint8_t* __restrict__ out_act,
+                                                    uint32_t dflt, int use_atomic) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const size_t wave = (size_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const size_t group = wave / wpp;
+    const uint32_t blk = uint32_t(wave % wpp);
+    const uint32_t slot = lane / LP, sub = lane % LP;
+    const size_t i = group * (64u / LP) + slot;
+    if (group * (64u / LP) >= n) return;  // wave-uniform
+    const uint32_t part = blk * 64u + sub;
+    const bool valid = i < n && part < P;
+
+    uint32_t src = 0, dst = 0, pp = 0, pr = 0;
+    if (i < n) {
+        src = pk.src[i];
+        dst = pk.dst[i];
+        pp = (uint32_t(pk.sport[i]) << 16) | pk.dport[i];
+        pr = pk.proto[i];
+    }
+    const uint64_t r0 = valid ? uint64_t(part) * S : 0;
+    const uint32_t begin = uint32_t(r0 < n_rules ? r0 : n_rules);
+    const uint32_t end = uint32_t(r0 + S < n_rules ? r0 + S : n_rules);
+    uint32_t r = begin;
+    bool done = !valid || begin >= end;
+    uint32_t best = kNoMatch;
+
+    for (;;) {
+#pragma unroll
+        for (int t = 0; t < kPrune; ++t) {
+            if (!done) {
+                if (r >= end) {
+                    done = true;
+                } else {
+                    const RuleRec q = rules[r];
+                    if (full_match(q, src, dst, pp, pr)) {
+                        best = r;
+                        done = true;
+                    }
+                    ++r;
+                }
+            }
+        }
+        const uint32_t gm = group_min<LP>(best);
+        if (gm < r) done = true;
+        if (ballot(!done) == 0) break;
+    }
+    const uint32_t gm = group_min<LP>(best);
+    if (sub == 0 && i < n) {
+        if (use_atomic) {
+            atomicMin(reinterpret_cast<uint32_t*>(out_idx) + i, gm);
+        } else {
+            out_idx[i] = int32_t(gm);
+            out_act[i] = uint8_t(gm == kNoMatch ? dflt : rule_action(rules[gm].proto));
+        }
+    }
+}
+
+__global__ void k_fill_u32(uint32_t* p, size_t n, uint32_t v) {
+    const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Index -> action for the atomicMin path: 0xFFFFFFFF reads as -1 and takes the default.
+__global__ void k_apply_action(const RuleRec* __restrict__ rules, const int32_t* idx, size_t n,
+                               uint8_t* __restrict__ out_act, uint32_t dflt) {
+    const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const uint32_t r = uint32_t(idx[i]);
+        out_act[i] = uint8_t(r == kNoMatch ? dflt : rule_action(rules[r].proto));
+    }
+}
+
+// ------------------------------------------------------------------ hybrid
+// One workgroup per 64 packets (paper Section IV-C: a block per packet, its
+// threads splitting the rules; here a lane per packet and a wave per rule
+// partition).  Wave w scans partition w with the packet-split inner loop;
+// partial first matches meet in LDS through atomicMin, and every kPrune
+// rules a wave drops lanes that another wave has already beaten.
+__global__ __launch_bounds__(1024) void k_hybrid(const RuleRec* __restrict__ rules,
+                                                 uint32_t n_rules, uint32_t S, PacketsDev pk,
+                                                 size_t n, int32_t* __restrict__ out_idx,
+                                                 uint8_t* __restrict__ out_act, uint32_t dflt) {
+    __shared__ uint32_t smin[64];
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t w = threadIdx.x >> 6;
+    const size_t i = size_t(blockIdx.x) * 64u + lane;
+    if (w == 0) smin[lane] = kNoMatch;
+    __syncthreads();
+
+    uint32_t src = 0, dst = 0, pp = 0, pr = 0;
+    if (i < n) {
+        src = pk.src[i];
+        dst = pk.dst[i];
+        pp = (uint32_t(pk.sport[i]) << 16) | pk.dport[i];
+        pr = pk.proto[i];
+    }
+    uint64_t live = ballot(i < n);
+    const uint64_t r0 = uint64_t(w) * S;
+    const uint32_t begin = uint32_t(r0 < n_rules ? r0 : n_rules);
+    const uint32_t end = uint32_t(r0 + S < n_rules ? r0 + S : n_rules);
+    uint32_t since = 0;
+    for (uint32_t r = begin; r < end && live != 0; ++r) {
+        if (++since == kPrune) {
+            since = 0;
+            const uint32_t cur = __atomic_load_n(&smin[lane], __ATOMIC_RELAXED);
+            live &= ballot(cur > r);
+            if (live == 0) break;
+        }
+        const RuleRec q = rules[r];
+        uint64_t m = ballot(in_range(dst, q.dst_lo, q.dst_w)) & live;
+        if (m == 0) continue;
+        m &= ballot(in_range(src, q.src_lo, q.src_w));
+        if (m == 0) continue;
+        m &= ballot(ports_in(pp, q.port_lo, q.port_w)) &
+             ballot(in_range(pr, proto_lo(q.proto), proto_w(q.proto)));
+        if (m == 0) continue;
+        if ((m >> lane) & 1u) atomicMin(&smin[lane], r);
+        live &= ~m;
+    }
+    __syncthreads();
+    if (w == 0 && i < n) {
+        const uint32_t b = smin[lane];
+        out_idx[i] = int32_t(b);
+        out_act[i] = uint8_t(b == kNoMatch ? dflt : rule_action(rules[b].proto));
+    }
+}
+
+inline uint32_t ceil_div(uint64_t a, uint64_t b) { return uint32_t((a + b - 1) / b); }
+
+}  // namespace
+
+hipError_t launch_packet_split(const RuleRec* rules, uint32_t n_rules, PacketsDev pk, size_t n,
+                               int32_t* out_idx, uint8_t* out_act, uint8_t default_action,
+                               int packets_per_lane, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    constexpr uint32_t kBlock = 256;
+    const int K = packets_per_lane;
+    const uint64_t per_block = uint64_t(kBlock) * K;
+    const uint32_t grid = ceil_div(n, per_block);
+    if (K == 4)
+        hipLaunchKernelGGL(k_packet_split<4>, dim3(grid), dim3(kBlock), 0, stream, rules,
+                           n_rules, pk, n, out_idx, out_act, uint32_t(default_action));
+    else if (K == 2)
+        hipLaunchKernelGGL(k_packet_split<2>, dim3(grid), dim3(kBlock), 0, stream, rules,
+                           n_rules, pk, n, out_idx, out_act, uint32_t(default_action));
+    else
+        hipLaunchKernelGGL(k_packet_split<1>, dim3(grid), dim3(kBlock), 0, stream, rules,
+                           n_rules, pk, n, out_idx, out_act, uint32_t(default_action));
+    return hipGetLastError();
+}
+
+hipError_t launch_rule_split(const RuleRec* rules, uint32_t n_rules, uint32_t P, PacketsDev pk,
+                             size_t n, int32_t* out_idx, uint8_t* out_act,
+                             uint8_t default_action, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    constexpr uint32_t kBlock = 256;
+    const uint32_t S = n_rules == 0 ? 1u : ceil_div(n_rules, P);
+    uint32_t LP = 1;
+    while (LP < P && LP < 64) LP <<= 1;
+    const uint32_t wpp = P > 64 ? ceil_div(P, 64) : 1u;
+    const uint64_t groups = (n + (64 / LP) - 1) / (64 / LP);
+    const uint64_t waves = groups * wpp;
+    const uint32_t grid = ceil_div(waves * 64, kBlock);
+    const int atomic = wpp > 1;
+    if (atomic) {
+        hipLaunchKernelGGL(k_fill_u32, dim3(ceil_div(n, 256)), dim3(256), 0, stream,
+                           reinterpret_cast<uint32_t*>(out_idx), n, kNoMatch);
+    }
+#define FW_RS(L)                                                                          \
+    hipLaunchKernelGGL(k_rule_split<L>, dim3(grid), dim3(kBlock), 0, stream, rules, n_rules, \
+                       P, S, wpp, pk, n, out_idx, out_act, uint32_t(default_action), atomic)
+    switch (LP) {
+        case 1: FW_RS(1); break;
+        case 2: FW_RS(2); break;
+        case 4: FW_RS(4); break;
+        case 8: FW_RS(8); break;
+        case 16: FW_RS(16); break;
+        case 32: FW_RS(32); break;
+        default: FW_RS(64); break;
+    }
+#undef FW_RS
+    if (atomic) {
+        hipLaunchKernelGGL(k_apply_action, dim3(ceil_div(n, 256)), dim3(256), 0, stream, rules,
+                           out_idx, n, out_act, uint32_t(default_action));
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_hybrid(const RuleRec* rules, uint32_t n_rules, uint32_t P, PacketsDev pk,
+                         size_t n, int32_t* out_idx, uint8_t* out_act, uint8_t default_action,
+                         hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    const uint32_t S = n_rules == 0 ? 1u : ceil_div(n_rules, P);
+    hipLaunchKernelGGL(k_hybrid, dim3(ceil_div(n, 64)), dim3(64 * P), 0, stream, rules, n_rules,
+                       S, pk, n, out_idx, out_act, uint32_t(default_action));
+    return hipGetLastError();
+}
+
+}  // namespace fw

@@ -1,0 +1,186 @@
+"""GPU parity of the scan modes against the CPU oracle, bit for bit.
+
+Packet split (paper Section IV-A), rule split (Section IV-B) and the hybrid
+(Section IV-C) must all give exactly the oracle's first-match index and
+action for every packet.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import gen
+from tests import golden_io
+from tests.gpu_util import assert_same, classify_np, fwmod, say
+
+pytestmark = pytest.mark.gpu
+
+SCAN_MODES = [
+    dict(mode="packet_split", packets_per_lane=4),
+    dict(mode="packet_split", packets_per_lane=2),
+    dict(mode="packet_split", packets_per_lane=1),
+    dict(mode="rule_split", partitions=16),
+    dict(mode="rule_split", partitions=1),
+    dict(mode="rule_split", partitions=3),
+    dict(mode="rule_split", partitions=64),
+    dict(mode="rule_split", partitions=100),
+    dict(mode="hybrid", partitions=4),
+    dict(mode="hybrid", partitions=16),
+]
+
+
+def _id(kw):
+    return "-".join(f"{v}" for v in kw.values())
+
+
+@pytest.mark.parametrize("kw", SCAN_MODES, ids=_id)
+@pytest.mark.parametrize("name", golden_io.names())
+def test_golden(name, kw):
+    say(f"golden {name} {kw}")
+    rs, pk, ei, ea = golden_io.load(name)
+    assert_same(classify_np(rs, pk, **kw), (ei, ea), f"{name} {kw}")
+
+
+@pytest.mark.parametrize("kw", SCAN_MODES, ids=_id)
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_small_config_all_modes(seed, kw):
+    """100 rules x 10,000 packets (every packet checked)."""
+    say(f"scan_100x10k seed={seed} {kw}")
+    rules, pk = gen.workload("scan_100x10k", seed=seed)
+    want = oracle.classify(rules, pk, threads=8)
+    assert_same(classify_np(rules, pk, **kw), want, f"seed {seed} {kw}")
+
+
+@pytest.mark.parametrize("kw", [dict(mode="packet_split"), dict(mode="rule_split", partitions=16),
+                                dict(mode="rule_split", partitions=1000),
+                                dict(mode="hybrid", partitions=8)], ids=_id)
+def test_1000_rules_full_batch(kw):
+    """1,000 rules x 1,048,576 packets, every packet against the oracle."""
+    say(f"scan_1000x1M {kw}")
+    rules, pk = gen.workload("scan_1000x1M", seed=1)
+    want = oracle.classify(rules, pk, threads=16)
+    assert_same(classify_np(rules, pk, **kw), want, f"1000x1M {kw}")
+
+
+@pytest.mark.parametrize("n", [0, 1, 3, 63, 64, 65, 255, 257, 1023, 4099])
+@pytest.mark.parametrize("kw", SCAN_MODES[:5] + SCAN_MODES[8:9], ids=_id)
+def test_ragged_sizes(n, kw):
+    say(f"ragged n={n} {kw}")
+    rules = gen.make_rules(37, 9)
+    pk = gen.make_packets(rules, max(n, 1), 9).subset(slice(0, n))
+    want = oracle.classify(rules, pk)
+    assert_same(classify_np(rules, pk, **kw), want, f"n={n} {kw}")
+
+
+@pytest.mark.parametrize("R", [0, 1, 2, 15, 16, 17])
+def test_tiny_rulesets_every_partition_count(R):
+    """R < P, R = 1, R = 0, and P not dividing R."""
+    rules = gen.make_rules(R, 21)
+    rules.default_action = 1
+    pk = gen.make_packets(gen.make_rules(5, 22), 777, 21)
+    want = oracle.classify(rules, pk)
+    for kw in ([dict(mode="packet_split")] +
+               [dict(mode="rule_split", partitions=p) for p in (1, 2, 5, 16, 33, 64, 65, 200)] +
+               [dict(mode="hybrid", partitions=p) for p in (1, 3, 16)]):
+        say(f"R={R} {kw}")
+        assert_same(classify_np(rules, pk, **kw), want, f"R={R} {kw}")
+
+
+def test_boundary_packets():
+    """Packets at every rule's lo-1, lo, hi, hi+1 in each field; /0 and /32; ports 0 and 65535."""
+    rules = gen.make_rules(64, 31)
+    rules.src_plen[::7] = 32
+    rules.dst_plen[::5] = 0
+    rules.dport_lo[::6] = 0
+    rules.dport_hi[::6] = 65535
+    rng = np.random.Generator(np.random.PCG64(31))
+    from tests.boxes import rule_box
+    pts = []
+    for r in range(len(rules)):
+        box = rule_box(rules, r)
+        for f in range(5):
+            lo, hi = box[f]
+            top = [2**32 - 1, 2**32 - 1, 65535, 65535, 255][f]
+            for v in (lo - 1, lo, hi, hi + 1):
+                if 0 <= v <= top:
+                    p = [int(rng.integers(a, b + 1)) for a, b in box]
+                    p[f] = v
+                    pts.append(p)
+    from tests.boxes import points_to_packets
+    pk = points_to_packets(pts)
+    want = oracle.classify(rules, pk)
+    for kw in SCAN_MODES:
+        say(f"boundary {kw}")
+        assert_same(classify_np(rules, pk, **kw), want, f"boundary {kw}")
+
+
+def test_10000_rules_16M_packets_sampled():
+    """10,000 skewed rules x 16,777,216 packets, packet split and rule split; a sample vs the oracle."""
+    import torch
+    fw = fwmod()
+    rules, pk = gen.workload("learned_10000x16M", seed=1)
+    rng = np.random.Generator(np.random.PCG64(5))
+    sample = np.sort(rng.choice(len(pk), 40_000, replace=False))
+    want = oracle.classify(rules, pk.subset(sample), threads=16)
+    dp = fw.DevicePackets.from_host(pk)
+    with fw.Ruleset(rules) as rs:
+        for kw in (dict(mode="packet_split"), dict(mode="rule_split", partitions=16)):
+            say(f"10000x16M {kw}")
+            idx, act = rs.classify(dp, **kw)
+            torch.cuda.synchronize()
+            got = (idx.cpu().numpy()[sample], act.cpu().numpy()[sample])
+            assert_same(got, want, f"10000x16M {kw}")
+            # every index is -1 or a real rule, and actions agree with the rule table
+            ia = idx.cpu().numpy()
+            assert ia.min() >= -1 and ia.max() < len(rules)
+
+
+def test_determinism_and_streams():
+    """Repeated runs are byte-identical, on the null stream and on a side stream."""
+    import torch
+    fw = fwmod()
+    rules, pk = gen.workload("scan_1000x1M", seed=2, n_packets=200_000)
+    dp = fw.DevicePackets.from_host(pk)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    with fw.Ruleset(rules) as rs:
+        outs = []
+        for kw in (dict(mode="packet_split"), dict(mode="rule_split", partitions=16),
+                   dict(mode="rule_split", partitions=256), dict(mode="hybrid", partitions=16)):
+            for stream in (None, s):
+                idx, act = rs.classify(dp, stream=stream, **kw)
+                torch.cuda.synchronize()
+                outs.append((idx.cpu().numpy(), act.cpu().numpy()))
+        for o in outs[1:]:
+            np.testing.assert_array_equal(o[0], outs[0][0])
+            np.testing.assert_array_equal(o[1], outs[0][1])
+
+
+def test_plain_entry_point_and_errors():
+    import torch
+    fw = fwmod()
+    rules, pk = gen.workload("scan_100x10k", seed=4, n_packets=1000)
+    want = oracle.classify(rules, pk)
+    dp = fw.DevicePackets.from_host(pk)
+    with fw.Ruleset(rules) as rs:
+        assert rs.size() == 100
+        idx, act = rs.classify_plain(dp)
+        torch.cuda.synchronize()
+        assert_same((idx.cpu().numpy(), act.cpu().numpy()), want, "fw_classify")
+        # misaligned packet array
+        bad = fw.DevicePackets(dp.src_ip[1:], dp.dst_ip[1:], dp.sport[1:], dp.dport[1:],
+                               dp.proto[1:])
+        with pytest.raises(fw.FwError) as ei:
+            rs.classify(bad)
+        assert ei.value.status == fw.E_ALIGN
+        with pytest.raises(fw.FwError) as ei:
+            rs.classify(dp, mode=9)
+        assert ei.value.status == fw.E_INVAL
+        with pytest.raises(fw.FwError) as ei:
+            rs.classify(dp, mode="learned")
+        assert ei.value.status == fw.E_NOINDEX
+        with pytest.raises(fw.FwError) as ei:
+            rs.classify(dp, mode="hybrid", partitions=17)
+        assert ei.value.status == fw.E_INVAL
+        # n == 0 is accepted and writes nothing
+        rs.classify(dp.slice(0, 0))
