@@ -174,6 +174,8 @@ typedef struct fw_index_opts {
     uint32_t train;         /* 0 = keep the random initial weights (ablation) */
     uint32_t use_mfma;      /* 1 = bf16 MFMA for the weight-gradient products (default),
                                0 = plain fp32 reduction (for checking) */
+    uint32_t zero_error_bounds; /* testing only: store every error bound as 0, so most
+                                   lookups miss their window and take the full search */
     uint64_t mem_budget;    /* device bytes the index may use; 0 = no limit */
     void *stream;           /* hipStream_t; NULL = null stream.  The build waits for it. */
 } fw_index_opts;

@@ -28,3 +28,64 @@ fw_status index_export(const LearnedIndex* ix, uint32_t what, void* host, size_t
                        size_t* size);
 
 }  // namespace fw
+
+namespace fw {
+
+// Per-expert data of the second stage (32 bytes).
+struct ExpertMeta {
+    uint32_t key_lo;    // smallest training key routed to the expert
+    float inv_span;     // 1 / (largest key - key_lo + 1)
+    int32_t pos_lo;     // smallest / largest target position of its keys
+    int32_t pos_hi;
+    float pos_span;     // pos_hi - pos_lo
+    uint32_t err;       // max |predicted - true position| over its keys
+    uint32_t pad[2];
+};
+static_assert(sizeof(ExpertMeta) == 32, "expert record must stay 32 bytes");
+
+constexpr uint32_t kMaxHidden = 32;
+constexpr uint32_t kMaxExperts = 256;
+constexpr uint32_t kGradCols = 128;      // padded column count of the gradient product
+constexpr uint32_t kNoExpert = 0xFFFFFFFFu;
+
+// Everything the lookup kernel reads.
+struct LookupArgs {
+    const uint32_t* B;        // M boundaries
+    uint32_t M;
+    const float* w1;          // stage 1, 3H+1 floats (bf16 values, widened)
+    const uint16_t* w2;       // stage 2, E experts x stride2 bf16
+    uint32_t stride2;         // per-expert stride in w2 (multiple of 8)
+    const ExpertMeta* meta;   // E
+    uint32_t E, H;
+    const uint32_t* off;      // M + 1 per-interval list offsets
+    const RuleRec* L;         // per-interval candidate records
+    const RuleRec* G;         // global (destination-wildcard) candidate records
+    uint32_t nG;
+    uint32_t use_net;         // 0: full binary search only
+    unsigned long long* miss; // optional window-miss counter
+};
+
+// ---- training kernels (rmi.hip)
+hipError_t launch_fwd_bwd(const float* params, uint32_t H, const float* u, const float* t,
+                          const uint32_t* ex, const float* inv_count, size_t n, size_t n_pad,
+                          void* at, bool bf16, hipStream_t s);
+hipError_t launch_grad_mfma(const uint16_t* at, const uint32_t* ex, size_t n_pad, uint32_t E,
+                            float* partial, hipStream_t s);
+uint32_t grad_mfma_chunks(size_t n_pad);
+hipError_t launch_grad_reduce(const float* partial, uint32_t chunks, uint32_t E, uint32_t H,
+                              float* grad, float* loss, hipStream_t s);
+hipError_t launch_grad_fp32(const float* at, size_t n_pad, const uint32_t* seg, uint32_t E,
+                            uint32_t H, float* grad, float* loss, hipStream_t s);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, size_t count, float lr,
+                       float b1, float b2, float eps, float bc1, float bc2, hipStream_t s);
+hipError_t launch_route(const float* w1, uint32_t H, uint32_t E, const uint32_t* keys, size_t n,
+                        uint32_t* expert, hipStream_t s);
+hipError_t launch_err_bound(const LookupArgs& a, const uint32_t* keys, const int32_t* pos,
+                            size_t n, uint32_t* err, hipStream_t s);
+hipError_t launch_learned(const LookupArgs& a, PacketsDev pk, size_t n, int32_t* out_idx,
+                          uint8_t* out_act, uint32_t dflt, const uint32_t* keys,
+                          int32_t* out_interval, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
+size_t learned_lds_bytes(const LookupArgs& a, bool b_in_lds);
+
+}  // namespace fw

@@ -1,0 +1,516 @@
+// Learned destination index on gfx950: training kernels for the two-stage
+// network, the shared inference routine, and the lookup + candidate-scan
+// kernel.
+//
+// Every network maps one input to one output through H ReLU units:
+//   f(u) = sum_k w2[k] * relu(w1[k] * u + b1[k]) + b2,
+// parameters laid out [w1 (H), b1 (H), w2 (H), b2].  A stage of E such
+// networks minimises the sum of each network's mean squared error over its
+// own samples; Adam (Kingma and Ba) updates the fp32 master weights.
+//
+// Weight gradients are segmented sums over samples: for network e and
+// parameter c, g[e][c] = sum over samples n of network e of A[n][c], where A
+// holds each sample's per-parameter contributions.  With the one-hot
+// expert-membership matrix S (S[n][e] = 1 when sample n trains e) this is the
+// product S^T * A, which runs on the matrix cores as bf16 x bf16 -> fp32 MFMA
+// (S is exact in bf16).  A plain fp32 reduction computes the same sums for
+// checking.
+#include "device_util.h"
+#include "fw_internal.h"
+#include "index.h"
+
+namespace fw {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr uint32_t kChunk = 512;   // samples per MFMA work-group (32 steps of K = 16)
+
+__device__ __forceinline__ float bf16_to_f32(uint32_t b) { return __uint_as_float(b << 16); }
+
+// Round to nearest even (inputs here are finite).
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+    uint32_t b = __float_as_uint(f);
+    b += 0x7FFFu + ((b >> 16) & 1u);
+    return uint16_t(b >> 16);
+}
+
+// ------------------------------------------------------------------ forward + backward
+// One thread per sample: forward pass of the sample's network, dL/dy, and the
+// sample's contribution to every parameter's gradient, written as column c of
+// the transposed sample matrix AT[c][n]:
+//   c in [0, H): dz_k * u      (w1)     c in [H, 2H): dz_k      (b1)
+//   c in [2H, 3H): relu(z_k) d (w2)     c = 3H: d               (b2)
+//   c = 3H + 1: (y - t)^2 / N_e (loss)
+// with d = 2 (y - t) / N_e and dz_k = d * w2[k] * [z_k > 0].
+template <bool BF16>
+__global__ __launch_bounds__(256) void k_fwd_bwd(const float* __restrict__ params, uint32_t H,
+                                                 const float* __restrict__ u,
+                                                 const float* __restrict__ t,
+                                                 const uint32_t* __restrict__ ex,
+                                                 const float* __restrict__ inv_count, size_t n,
+                                                 size_t n_pad, void* __restrict__ at_) {
+    const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n_pad) return;
+    auto put = [&](uint32_t c, float v) {
+        if constexpr (BF16)
+            static_cast<uint16_t*>(at_)[size_t(c) * n_pad + i] = f32_to_bf16(v);
+        else
+            static_cast<float*>(at_)[size_t(c) * n_pad + i] = v;
+    };
+    const uint32_t e = i < n ? ex[i] : kNoExpert;
+    if (e == kNoExpert) {
+        for (uint32_t c = 0; c < 3 * H + 2; ++c) put(c, 0.0f);
+        return;
+    }
+    const uint32_t P = 3 * H + 1;
+    const float* p = params + size_t(e) * P;
+    const float x = u[i], target = t[i], inv = inv_count[e];
+    float z[kMaxHidden];
+    float y = p[3 * H];
+#pragma unroll
+    for (uint32_t k = 0; k < kMaxHidden; ++k) {
+        if (k < H) {
+            z[k] = fmaf(p[k], x, p[H + k]);
+            y = fmaf(p[2 * H + k], fmaxf(z[k], 0.0f), y);
+        }
+    }
+    const float r = y - target;
+    const float d = 2.0f * r * inv;
+#pragma unroll
+    for (uint32_t k = 0; k < kMaxHidden; ++k) {
+        if (k < H) {
+            const float dz = z[k] > 0.0f ? d * p[2 * H + k] : 0.0f;
+            put(k, dz * x);
+            put(H + k, dz);
+            put(2 * H + k, fmaxf(z[k], 0.0f) * d);
+        }
+    }
+    put(3 * H, d);
+    put(3 * H + 1, r * r * inv);
+}
+
+// ------------------------------------------------------------------ S^T * A on MFMA
+// Grid (chunks, E_pad / 32); four waves, wave w computing output columns
+// [32w, 32w + 32) of the 32 experts of its row tile over the chunk's kChunk
+// samples.  v_mfma_f32_32x32x16_bf16: lane l supplies A-operand row l % 32,
+// k = 8 (l / 32) + 0..7, and B-operand column l % 32 with the same k; it
+// holds output rows 8 (r / 4) + 4 (l / 32) + r % 4 of column l % 32 in acc[r].
+__global__ __launch_bounds__(256) void k_grad_mfma(const uint16_t* __restrict__ at,
+                                                   const uint32_t* __restrict__ ex, size_t n_pad,
+                                                   uint32_t E_pad, float* __restrict__ partial) {
+    const uint32_t chunk = blockIdx.x, mtile = blockIdx.y;
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    const uint32_t m = mtile * 32u + (lane & 31u);
+    const uint32_t c = wave * 32u + (lane & 31u);
+    const uint32_t kq = (lane >> 5) * 8u;
+    f32x16 acc = {};
+    const uint16_t* col = at + size_t(c) * n_pad;
+    for (uint32_t ks = 0; ks < kChunk; ks += 16) {
+        const size_t s0 = size_t(chunk) * kChunk + ks + kq;
+        const uint4 e0 = *reinterpret_cast<const uint4*>(ex + s0);
+        const uint4 e1 = *reinterpret_cast<const uint4*>(ex + s0 + 4);
+        const unsigned short one = 0x3F80;  // 1.0 in bf16
+        u16x8 a;
+        a[0] = e0.x == m ? one : 0; a[1] = e0.y == m ? one : 0;
+        a[2] = e0.z == m ? one : 0; a[3] = e0.w == m ? one : 0;
+        a[4] = e1.x == m ? one : 0; a[5] = e1.y == m ? one : 0;
+        a[6] = e1.z == m ? one : 0; a[7] = e1.w == m ? one : 0;
+        const u16x8 b = *reinterpret_cast<const u16x8*>(col + s0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                      __builtin_bit_cast(bf16x8, b), acc, 0, 0,
+                                                      0);
+    }
+    float* out = partial + size_t(chunk) * E_pad * kGradCols;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const uint32_t row = mtile * 32u + 8u * (r / 4) + 4u * (lane >> 5) + (r % 4);
+        out[size_t(row) * kGradCols + c] = acc[r];
+    }
+}
+
+// Sum the per-chunk partial products in chunk order (deterministic).
+__global__ void k_grad_reduce(const float* __restrict__ partial, uint32_t chunks, uint32_t E,
+                              uint32_t E_pad, uint32_t H, float* __restrict__ grad,
+                              float* __restrict__ loss) {
+    const uint32_t P = 3 * H + 1;
+    const uint32_t o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= E * (P + 1)) return;
+    const uint32_t e = o / (P + 1), c = o % (P + 1);
+    float s = 0.0f;
+    for (uint32_t k = 0; k < chunks; ++k) s += partial[(size_t(k) * E_pad + e) * kGradCols + c];
+    if (c < P)
+        grad[size_t(e) * P + c] = s;
+    else if (loss)
+        loss[e] = s;
+}
+
+// fp32 reference path: samples sorted by network, seg[e]..seg[e+1] belong to e;
+// one thread per (network, column) sums its column in sample order.
+__global__ void k_grad_fp32(const float* __restrict__ at, size_t n_pad,
+                            const uint32_t* __restrict__ seg, uint32_t H,
+                            float* __restrict__ grad, float* __restrict__ loss) {
+    const uint32_t e = blockIdx.x, c = threadIdx.x;
+    const uint32_t P = 3 * H + 1;
+    if (c > P) return;
+    float s = 0.0f;
+    const float* col = at + size_t(c) * n_pad;
+    for (uint32_t k = seg[e]; k < seg[e + 1]; ++k) s += col[k];
+    if (c < P)
+        grad[size_t(e) * P + c] = s;
+    else if (loss)
+        loss[e] = s;
+}
+
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, size_t count, float lr, float b1, float b2,
+                       float eps, float bc1, float bc2) {
+    const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+__global__ void k_fill(uint32_t* p, size_t n, uint32_t v) {
+    const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ------------------------------------------------------------------ inference
+// Stage 1 (fp32 copy of the bf16 weights): u = x / 2^32 -> expert index.
+__device__ __forceinline__ uint32_t route(const float* w1, uint32_t H, uint32_t E, uint32_t x) {
+    const float u = float(x) * 0x1p-32f;
+    float y = w1[3 * H];
+    for (uint32_t k = 0; k < H; ++k) y = fmaf(w1[2 * H + k], fmaxf(fmaf(w1[k], u, w1[H + k]), 0.0f), y);
+    const float s = y * float(E);
+    // NaN and negatives go to expert 0, overflow to the last expert
+    return s >= 1.0f ? (s < float(E) ? uint32_t(s) : E - 1u) : 0u;
+}
+
+// Stage 2 (bf16 weights): position estimate of x inside expert e's range.
+__device__ __forceinline__ int32_t position(const uint16_t* w2e, uint32_t H,
+                                            const ExpertMeta& m, uint32_t x) {
+    const float v = x >= m.key_lo ? fminf(float(x - m.key_lo) * m.inv_span, 1.0f) : 0.0f;
+    float y = bf16_to_f32(w2e[3 * H]);
+    for (uint32_t k = 0; k < H; ++k) {
+        const float z = fmaf(bf16_to_f32(w2e[k]), v, bf16_to_f32(w2e[H + k]));
+        y = fmaf(bf16_to_f32(w2e[2 * H + k]), fmaxf(z, 0.0f), y);
+    }
+    const float q = fminf(fmaxf(y * m.pos_span, 0.0f), m.pos_span);  // NaN -> 0
+    return m.pos_lo + int32_t(rintf(q));
+}
+
+// Largest j in [lo, hi] with B[j] <= x, assuming B[lo] <= x.
+__device__ __forceinline__ uint32_t search_le(const uint32_t* B, uint32_t lo, uint32_t hi,
+                                              uint32_t x) {
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1u) >> 1;
+        if (B[mid] <= x)
+            lo = mid;
+        else
+            hi = mid - 1u;
+    }
+    return lo;
+}
+
+// Interval of x: the window [p - err, p + err] of the predicted position first,
+// checked by B[j] <= x < B[j+1]; a miss falls back to the full range.
+__device__ __forceinline__ uint32_t locate(const uint32_t* B, uint32_t M, const float* w1,
+                                           const uint16_t* w2, uint32_t stride2,
+                                           const ExpertMeta* meta, uint32_t E, uint32_t H,
+                                           uint32_t use_net, uint32_t x, bool* miss) {
+    if (use_net) {
+        const uint32_t e = route(w1, H, E, x);
+        const ExpertMeta m = meta[e];
+        const int32_t p = position(w2 + size_t(e) * stride2, H, m, x);
+        const int64_t lo = int64_t(p) - int64_t(m.err), hi = int64_t(p) + int64_t(m.err);
+        const uint32_t l = uint32_t(lo < 0 ? 0 : (lo >= int64_t(M) ? M - 1 : lo));
+        const uint32_t h = uint32_t(hi < int64_t(l) ? l : (hi >= int64_t(M) ? M - 1 : hi));
+        if (B[l] <= x) {
+            const uint32_t j = search_le(B, l, h, x);
+            if (j + 1u == M || x < B[j + 1u]) {
+                *miss = false;
+                return j;
+            }
+        }
+        *miss = true;
+    } else {
+        *miss = false;
+    }
+    return search_le(B, 0, M - 1u, x);
+}
+
+__global__ void k_route(const float* __restrict__ w1, uint32_t H, uint32_t E,
+                        const uint32_t* __restrict__ keys, size_t n, uint32_t* __restrict__ out) {
+    const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = route(w1, H, E, keys[i]);
+}
+
+// Per-expert maximum |predicted - true position| over the training keys,
+// with exactly the arithmetic the lookup kernel uses.
+__global__ void k_err_bound(LookupArgs a, const uint32_t* __restrict__ keys,
+                            const int32_t* __restrict__ pos, size_t n, uint32_t* __restrict__ err) {
+    const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t x = keys[i];
+    const uint32_t e = route(a.w1, a.H, a.E, x);
+    const int32_t p = position(a.w2 + size_t(e) * a.stride2, a.H, a.meta[e], x);
+    const int32_t d = p - pos[i];
+    atomicMax(err + e, uint32_t(d < 0 ? -d : d));
+}
+
+// ------------------------------------------------------------------ lookup + candidate scan
+// Persistent work-groups of 16 waves.  Each stages the stage-1 weights (fp32),
+// the experts' records and bf16 weights, and (when it fits) the boundary
+// array into LDS once, then its waves stride over 64-packet tiles:
+//   1. locate the destination interval j (network + window, else full search);
+//   2. scan j's own candidate list per lane (ascending, stop at the first match);
+//   3. scan the shared destination-wildcard list with wave-uniform records,
+//      dropping lanes whose best index is already below the current record's;
+//   4. write the index and action.
+// With CLASSIFY false only step 1 runs and j is written.
+constexpr uint32_t kLearnedBlock = 1024;
+constexpr uint32_t kW1Slots = 3 * kMaxHidden + 4;   // floats reserved for stage 1
+
+__host__ __device__ inline size_t lds_layout(uint32_t E, uint32_t stride2, uint32_t M, bool b_lds,
+                                             size_t* off_meta, size_t* off_w2, size_t* off_b) {
+    size_t o = kW1Slots * sizeof(float);
+    *off_meta = o;
+    o += size_t(E) * sizeof(ExpertMeta);
+    *off_w2 = o;
+    o += size_t(E) * stride2 * sizeof(uint16_t);
+    o = (o + 15) & ~size_t(15);
+    *off_b = o;
+    if (b_lds) o += size_t(M) * sizeof(uint32_t);
+    return o;
+}
+
+template <bool B_LDS, bool CLASSIFY>
+__global__ __launch_bounds__(kLearnedBlock) void k_learned(LookupArgs a, PacketsDev pk, size_t n,
+                                                           int32_t* __restrict__ out_idx,
+                                                           uint8_t* __restrict__ out_act,
+                                                           uint32_t dflt,
+                                                           const uint32_t* __restrict__ keys,
+                                                           int32_t* __restrict__ out_interval) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    size_t o_meta, o_w2, o_b;
+    lds_layout(a.E, a.stride2, a.M, B_LDS, &o_meta, &o_w2, &o_b);
+    float* s_w1 = reinterpret_cast<float*>(smem);
+    ExpertMeta* s_meta = reinterpret_cast<ExpertMeta*>(smem + o_meta);
+    uint16_t* s_w2 = reinterpret_cast<uint16_t*>(smem + o_w2);
+    uint32_t* s_b = reinterpret_cast<uint32_t*>(smem + o_b);
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t k = tid; k < 3 * a.H + 1; k += blockDim.x) s_w1[k] = a.w1[k];
+    for (uint32_t k = tid; k < a.E * 8u; k += blockDim.x)
+        reinterpret_cast<uint32_t*>(s_meta)[k] = reinterpret_cast<const uint32_t*>(a.meta)[k];
+    for (uint32_t k = tid; k < a.E * a.stride2 / 2u; k += blockDim.x)
+        reinterpret_cast<uint32_t*>(s_w2)[k] = reinterpret_cast<const uint32_t*>(a.w2)[k];
+    if constexpr (B_LDS)
+        for (uint32_t k = tid; k < a.M; k += blockDim.x) s_b[k] = a.B[k];
+    __syncthreads();
+    const uint32_t* B = B_LDS ? s_b : a.B;
+
+    const uint32_t lane = tid & 63u;
+    const size_t waves = size_t(gridDim.x) * (blockDim.x >> 6);
+    const size_t wave0 = size_t(blockIdx.x) * (blockDim.x >> 6) + (tid >> 6);
+    for (size_t base = wave0 * 64u; base < n; base += waves * 64u) {
+        const size_t i = base + lane;
+        const bool valid = i < n;
+        const uint32_t x = valid ? (CLASSIFY ? pk.dst[i] : keys[i]) : 0u;
+        bool miss = false;
+        const uint32_t j = locate(B, a.M, s_w1, s_w2, a.stride2, s_meta, a.E, a.H, a.use_net,
+                                  x, &miss);
+        if (a.miss) {
+            const uint64_t mm = ballot(valid && miss);
+            if (lane == 0 && mm) atomicAdd(a.miss, (unsigned long long)__popcll(mm));
+        }
+        if constexpr (!CLASSIFY) {
+            if (valid) out_interval[i] = int32_t(j);
+            continue;
+        }
+        uint32_t src = 0, pp = 0, pr = 0;
+        if (valid) {
+            src = pk.src[i];
+            pp = (uint32_t(pk.sport[i]) << 16) | pk.dport[i];
+            pr = pk.proto[i];
+        }
+        uint32_t best = kNoMatch, act = dflt;
+        if (valid) {
+            const uint32_t kb = a.off[j], ke = a.off[j + 1u];
+            for (uint32_t k = kb; k < ke; ++k) {
+                const RuleRec q = a.L[k];
+                if (match_no_dst(q, src, pp, pr)) {
+                    best = q.idx;
+                    act = rule_action(q.proto);
+                    break;
+                }
+            }
+        }
+        uint64_t live = ballot(valid);
+        for (uint32_t g = 0; g < a.nG && live != 0; ++g) {
+            const RuleRec q = a.G[g];
+            if ((g & 7u) == 0) {
+                live &= ballot(best > q.idx);
+                if (live == 0) break;
+            }
+            uint64_t m = ballot(in_range(src, q.src_lo, q.src_w)) & live;
+            if (m == 0) continue;
+            m &= ballot(ports_in(pp, q.port_lo, q.port_w)) &
+                 ballot(in_range(pr, proto_lo(q.proto), proto_w(q.proto)));
+            if (m == 0) continue;
+            m &= ballot(best > q.idx);
+            if ((m >> lane) & 1u) {
+                best = q.idx;
+                act = rule_action(q.proto);
+            }
+            live &= ~m;
+        }
+        if (valid) {
+            out_idx[i] = int32_t(best);
+            out_act[i] = uint8_t(act);
+        }
+    }
+}
+
+inline uint32_t blocks_for(size_t n, uint32_t per) { return uint32_t((n + per - 1) / per); }
+
+struct LearnedLaunchCache {
+    int device = -1;
+    int cus = 0;
+};
+thread_local LearnedLaunchCache g_cache;
+
+template <bool B_LDS, bool CLASSIFY>
+hipError_t launch_learned_t(const LookupArgs& a, PacketsDev pk, size_t n, int32_t* out_idx,
+                            uint8_t* out_act, uint32_t dflt, const uint32_t* keys,
+                            int32_t* out_interval, size_t lds, hipStream_t s) {
+    auto kern = k_learned<B_LDS, CLASSIFY>;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    if (e != hipSuccess) return e;
+    int per_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kLearnedBlock, lds);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) return hipErrorInvalidConfiguration;
+    const size_t tiles = (n + 63) / 64;
+    const size_t want = (tiles + (kLearnedBlock / 64) - 1) / (kLearnedBlock / 64);
+    size_t grid = size_t(per_cu) * size_t(g_cache.cus);
+    if (grid > want) grid = want;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(kern, dim3(uint32_t(grid)), dim3(kLearnedBlock), lds, s, a, pk, n,
+                       out_idx, out_act, dflt, keys, out_interval);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+uint32_t grad_mfma_chunks(size_t n_pad) { return uint32_t(n_pad / kChunk); }
+
+hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fwd_bwd(const float* params, uint32_t H, const float* u, const float* t,
+                          const uint32_t* ex, const float* inv_count, size_t n, size_t n_pad,
+                          void* at, bool bf16, hipStream_t s) {
+    if (bf16)
+        hipLaunchKernelGGL(k_fwd_bwd<true>, dim3(blocks_for(n_pad, 256)), dim3(256), 0, s, params,
+                           H, u, t, ex, inv_count, n, n_pad, at);
+    else
+        hipLaunchKernelGGL(k_fwd_bwd<false>, dim3(blocks_for(n_pad, 256)), dim3(256), 0, s,
+                           params, H, u, t, ex, inv_count, n, n_pad, at);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_mfma(const uint16_t* at, const uint32_t* ex, size_t n_pad, uint32_t E,
+                            float* partial, hipStream_t s) {
+    const uint32_t E_pad = (E + 31u) & ~31u;
+    hipLaunchKernelGGL(k_grad_mfma, dim3(grad_mfma_chunks(n_pad), E_pad / 32u), dim3(256), 0, s,
+                       at, ex, n_pad, E_pad, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_reduce(const float* partial, uint32_t chunks, uint32_t E, uint32_t H,
+                              float* grad, float* loss, hipStream_t s) {
+    const uint32_t E_pad = (E + 31u) & ~31u;
+    const uint32_t total = E * (3 * H + 2);
+    hipLaunchKernelGGL(k_grad_reduce, dim3(blocks_for(total, 256)), dim3(256), 0, s, partial,
+                       chunks, E, E_pad, H, grad, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_fp32(const float* at, size_t n_pad, const uint32_t* seg, uint32_t E,
+                            uint32_t H, float* grad, float* loss, hipStream_t s) {
+    hipLaunchKernelGGL(k_grad_fp32, dim3(E), dim3(kGradCols), 0, s, at, n_pad, seg, H, grad,
+                       loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, size_t count, float lr,
+                       float b1, float b2, float eps, float bc1, float bc2, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_adam, dim3(blocks_for(count, 256)), dim3(256), 0, s, p, g, m, v, count,
+                       lr, b1, b2, eps, bc1, bc2);
+    return hipGetLastError();
+}
+
+hipError_t launch_route(const float* w1, uint32_t H, uint32_t E, const uint32_t* keys, size_t n,
+                        uint32_t* expert, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_route, dim3(blocks_for(n, 256)), dim3(256), 0, s, w1, H, E, keys, n,
+                       expert);
+    return hipGetLastError();
+}
+
+hipError_t launch_err_bound(const LookupArgs& a, const uint32_t* keys, const int32_t* pos,
+                            size_t n, uint32_t* err, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_err_bound, dim3(blocks_for(n, 256)), dim3(256), 0, s, a, keys, pos, n,
+                       err);
+    return hipGetLastError();
+}
+
+size_t learned_lds_bytes(const LookupArgs& a, bool b_in_lds) {
+    size_t o1, o2, o3;
+    return lds_layout(a.E, a.stride2, a.M, b_in_lds, &o1, &o2, &o3);
+}
+
+hipError_t launch_learned(const LookupArgs& a, PacketsDev pk, size_t n, int32_t* out_idx,
+                          uint8_t* out_act, uint32_t dflt, const uint32_t* keys,
+                          int32_t* out_interval, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (g_cache.device != dev) {
+        e = hipDeviceGetAttribute(&g_cache.cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        g_cache.device = dev;
+    }
+    int max_lds = 0;
+    e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess) return e;
+    const size_t with_b = learned_lds_bytes(a, true);
+    const bool b_lds = with_b <= size_t(max_lds) && with_b <= 80u * 1024u;
+    const size_t lds = b_lds ? with_b : learned_lds_bytes(a, false);
+    const bool classify = keys == nullptr;
+    if (b_lds)
+        return classify ? launch_learned_t<true, true>(a, pk, n, out_idx, out_act, dflt, keys,
+                                                       out_interval, lds, s)
+                        : launch_learned_t<true, false>(a, pk, n, out_idx, out_act, dflt, keys,
+                                                        out_interval, lds, s);
+    return classify ? launch_learned_t<false, true>(a, pk, n, out_idx, out_act, dflt, keys,
+                                                    out_interval, lds, s)
+                    : launch_learned_t<false, false>(a, pk, n, out_idx, out_act, dflt, keys,
+                                                     out_interval, lds, s);
+}
+
+}  // namespace fw

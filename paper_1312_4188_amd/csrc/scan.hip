@@ -10,32 +10,11 @@
 // per packet group, its threads splitting the rules.
 //
 // Every field test is the unsigned range test (v - lo) <= w (see RuleRec).
+#include "device_util.h"
 #include "fw_internal.h"
 
 namespace fw {
 namespace {
-
-typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
-
-__device__ __forceinline__ bool in_range(uint32_t v, uint32_t lo, uint32_t w) {
-    return (v - lo) <= w;
-}
-
-// Both ports at once: packed 16-bit subtract, packed 16-bit max, one compare.
-// max(v - lo, w) == w holds in both halves exactly when both differences are <= w.
-__device__ __forceinline__ bool ports_in(uint32_t pp, uint32_t lo, uint32_t w) {
-    u16x2 d = __builtin_bit_cast(u16x2, pp) - __builtin_bit_cast(u16x2, lo);
-    u16x2 m = __builtin_elementwise_max(d, __builtin_bit_cast(u16x2, w));
-    return __builtin_bit_cast(uint32_t, m) == w;
-}
-
-__device__ __forceinline__ uint32_t proto_lo(uint32_t p) { return p & 0xFFu; }
-__device__ __forceinline__ uint32_t proto_w(uint32_t p) { return (p >> 8) & 0xFFu; }
-__device__ __forceinline__ uint32_t rule_action(uint32_t p) { return (p >> 16) & 1u; }
-
-__device__ __forceinline__ uint32_t umin(uint32_t a, uint32_t b) { return a < b ? a : b; }
 
 // Load K consecutive packets starting at p0 (p0 is a multiple of K).  Full
 // groups use one 128-bit (K=4), 64-bit (K=2) or 32-bit load per address array;

@@ -50,7 +50,8 @@ class IndexOpts(ctypes.Structure):
     _fields_ = [("experts", ctypes.c_uint32), ("hidden", ctypes.c_uint32),
                 ("epochs1", ctypes.c_uint32), ("epochs2", ctypes.c_uint32),
                 ("lr", ctypes.c_float), ("seed", ctypes.c_uint32), ("train", ctypes.c_uint32),
-                ("use_mfma", ctypes.c_uint32), ("mem_budget", ctypes.c_uint64),
+                ("use_mfma", ctypes.c_uint32), ("zero_error_bounds", ctypes.c_uint32),
+                ("mem_budget", ctypes.c_uint64),
                 ("stream", ctypes.c_void_p)]
 
 
@@ -237,9 +238,11 @@ class Ruleset:
         return out_idx, out_act
 
     def build_learned_index(self, experts=0, hidden=0, epochs1=0, epochs2=0, lr=0.0, seed=1,
-                            train=True, use_mfma=True, mem_budget=0, stream=None) -> dict:
+                            train=True, use_mfma=True, mem_budget=0, stream=None,
+                            zero_error_bounds=False) -> dict:
         opts = IndexOpts(experts, hidden, epochs1, epochs2, lr, seed, int(bool(train)),
-                         int(bool(use_mfma)), int(mem_budget), _stream_ptr(stream))
+                         int(bool(use_mfma)), int(bool(zero_error_bounds)), int(mem_budget),
+                         _stream_ptr(stream))
         st = IndexStats()
         _check(load_library().fw_build_learned_index(self._h, ctypes.byref(opts),
                                                      ctypes.byref(st)))

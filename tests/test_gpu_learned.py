@@ -1,0 +1,211 @@
+"""GPU tests of the learned destination index.
+
+The index structure is checked against the oracle's set definitions
+(oracle.intervals), the interval lookup against the textbook upper_bound,
+classifications against the sequential oracle bit for bit, and the training
+kernels' gradients and Adam step against the float64 reference
+(oracle.rmi).
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import intervals as iv
+from oracle import rmi
+from synth import gen
+from tests.gpu_util import assert_same, fwmod, say
+
+pytestmark = pytest.mark.gpu
+
+FAST = dict(epochs1=300, epochs2=600)
+
+
+def _learned_np(rules, pk, build_kw=None, **kw):
+    import torch
+    fw = fwmod()
+    with fw.Ruleset(rules) as rs:
+        stats = rs.build_learned_index(**(build_kw or FAST))
+        dp = fw.DevicePackets.from_host(pk)
+        idx, act, miss = rs.classify(dp, mode="learned", count_misses=True, **kw)
+        torch.cuda.synchronize()
+        return (idx.cpu().numpy(), act.cpu().numpy()), miss, stats
+
+
+@pytest.mark.parametrize("seed,skew,R", [(1, False, 100), (2, True, 300), (3, True, 1000)])
+def test_index_structure_matches_definition(seed, skew, R):
+    fw = fwmod()
+    rules = gen.make_rules(R, seed, skew=skew)
+    say(f"structure seed={seed} R={R}")
+    with fw.Ruleset(rules) as rs:
+        st = rs.build_learned_index(**FAST)
+        B = rs.export(0)
+        off = rs.export(1)
+        L = rs.export(2)
+        G = rs.export(3)
+    want_B = iv.boundaries(rules)
+    np.testing.assert_array_equal(B, want_B)
+    assert st["n_boundaries"] == len(B)
+    assert off[0] == 0 and off[-1] == len(L) and np.all(np.diff(off.astype(np.int64)) >= 0)
+    C = iv.candidates(rules, want_B)
+    full = iv.full_match_in_interval(rules)
+    Gs = set(G.tolist())
+    assert list(G) == sorted(G)
+    for j in range(len(B)):
+        U = Gs | set(L[off[j]:off[j + 1]].tolist())
+        Cj = set(C[j].tolist())
+        Tj = set(iv.truncated(C[j], full).tolist())
+        assert Tj <= U <= Cj, j
+        lj = L[off[j]:off[j + 1]]
+        assert np.all(np.diff(lj.astype(np.int64)) > 0)
+
+
+@pytest.mark.parametrize("lookup", [0, 1])
+def test_interval_lookup_matches_upper_bound(lookup):
+    import torch
+    fw = fwmod()
+    rules = gen.make_rules(2000, 4, skew=True)
+    with fw.Ruleset(rules) as rs:
+        rs.build_learned_index(**FAST)
+        B = rs.export(0).astype(np.int64)
+        rng = np.random.Generator(np.random.PCG64(4))
+        probe = np.concatenate([B - 1, B, B + 1, rng.integers(0, 2**32, 50_000), [0, 2**32 - 1]])
+        probe = probe[(probe >= 0) & (probe < 2**32)].astype(np.uint32)
+        keys = torch.from_numpy(probe.view(np.int32)).cuda()
+        say(f"interval lookup {lookup} n={len(probe)}")
+        got = rs.lookup_intervals(keys, lookup=lookup)
+        torch.cuda.synchronize()
+        want = np.searchsorted(B, probe.astype(np.int64), side="right") - 1
+        np.testing.assert_array_equal(got.cpu().numpy(), want)
+
+
+@pytest.mark.parametrize("wl,seed", [("scan_100x10k", 1), ("scan_100x10k", 2),
+                                     ("scan_1000x1M", 1), ("scan_1000x1M", 3)])
+def test_learned_classify_matches_oracle(wl, seed):
+    rules, pk = gen.workload(wl, seed=seed)
+    say(f"learned {wl} seed={seed}")
+    want = oracle.classify(rules, pk, threads=16)
+    for lookup in (0, 1):
+        got, miss, st = _learned_np(rules, pk, lookup=lookup)
+        assert_same(got, want, f"learned {wl} seed {seed} lookup {lookup}")
+        if lookup == 1:
+            assert miss == 0
+
+
+def test_learned_10000_rules_sampled():
+    """10,000 skewed rules x 16,777,216 packets; the full batch runs, a sample is checked."""
+    import torch
+    fw = fwmod()
+    rules, pk = gen.workload("learned_10000x16M", seed=1)
+    rng = np.random.Generator(np.random.PCG64(9))
+    sample = np.sort(rng.choice(len(pk), 40_000, replace=False))
+    want = oracle.classify(rules, pk.subset(sample), threads=16)
+    dp = fw.DevicePackets.from_host(pk)
+    with fw.Ruleset(rules) as rs:
+        say("learned 10000x16M build")
+        st = rs.build_learned_index()
+        say(f"  stats {st}")
+        for lookup in (0, 1):
+            idx, act, miss = rs.classify(dp, mode="learned", lookup=lookup, count_misses=True)
+            torch.cuda.synchronize()
+            got = (idx.cpu().numpy()[sample], act.cpu().numpy()[sample])
+            assert_same(got, want, f"learned 10000x16M lookup {lookup}")
+            say(f"  lookup {lookup}: window misses {miss} of {len(pk)}")
+        # the scan agrees on the whole batch
+        si, sa = rs.classify(dp, mode="packet_split")
+        torch.cuda.synchronize()
+        assert np.array_equal(si.cpu().numpy(), idx.cpu().numpy())
+        assert np.array_equal(sa.cpu().numpy(), act.cpu().numpy())
+
+
+@pytest.mark.parametrize("n", [1, 63, 65, 1000, 4097])
+def test_learned_ragged_and_edge_rulesets(n):
+    for R, seed in ((0, 1), (1, 2), (7, 3), (300, 4)):
+        rules = gen.make_rules(R, seed, skew=True)
+        pk = gen.make_packets(gen.make_rules(20, seed + 50), n, seed)
+        say(f"learned ragged n={n} R={R}")
+        want = oracle.classify(rules, pk)
+        got, _, _ = _learned_np(rules, pk)
+        assert_same(got, want, f"learned n={n} R={R}")
+
+
+def test_forced_window_miss_stays_exact():
+    """Error bounds forced to 0, and an untrained network: every answer still exact."""
+    rules, pk = gen.workload("scan_1000x1M", seed=5, n_packets=200_000)
+    want = oracle.classify(rules, pk, threads=16)
+    got, miss, st = _learned_np(rules, pk, build_kw=dict(FAST, zero_error_bounds=True))
+    assert_same(got, want, "zero error bounds")
+    assert st["err_max"] == 0 and miss > len(pk) // 4
+    got, miss2, st2 = _learned_np(rules, pk, build_kw=dict(FAST, train=False))
+    assert_same(got, want, "untrained network")
+
+
+def test_network_gain():
+    """What training buys: narrower windows than the untrained network and than a full search."""
+    fw = fwmod()
+    rules = gen.make_rules(10_000, 1, skew=True)
+    with fw.Ruleset(rules) as rs:
+        tr = rs.build_learned_index(seed=3)
+        un = rs.build_learned_index(seed=3, train=False)
+    M = tr["n_boundaries"]
+    say(f"gain: trained err mean {tr['err_mean']:.1f} max {tr['err_max']}; "
+        f"untrained mean {un['err_mean']:.1f} max {un['err_max']}; M = {M}")
+    assert tr["err_mean"] * 4 < un["err_mean"]
+    # binary-search steps in the mean window against a search over all M boundaries
+    assert np.log2(2 * tr["err_mean"] + 1) < 0.6 * np.log2(M)
+
+
+@pytest.mark.parametrize("E,H,n", [(1, 32, 1000), (3, 7, 777), (64, 32, 5000), (5, 32, 0)])
+@pytest.mark.parametrize("mfma", [False, True])
+def test_gradients_match_float64(E, H, n, mfma):
+    fw = fwmod()
+    rng = np.random.Generator(np.random.PCG64(E * 100 + H))
+    params = rng.normal(0, 1, (E, 3 * H + 1)).astype(np.float32)
+    u = rng.random(n).astype(np.float32)
+    t = rng.random(n).astype(np.float32)
+    ex = rng.integers(0, E, n).astype(np.uint32)
+    if E == 64:
+        ex[ex == 7] = 8               # an expert with no samples
+    say(f"gradients E={E} H={H} n={n} mfma={mfma}")
+    g, loss = fw.rmi_gradients(params, u, t, ex, H, use_mfma=mfma)
+    want = rmi.stage_grad(params.astype(np.float64), u, t, ex, H)
+    scale = max(np.max(np.abs(want)), 1e-30)
+    tol = 2e-2 if mfma else 1e-4
+    assert np.max(np.abs(g - want)) / scale <= tol
+    want_loss = np.array([rmi.loss(params[e].astype(np.float64), u[ex == e], t[ex == e], H)
+                          for e in range(E)])
+    np.testing.assert_allclose(loss, want_loss, rtol=tol, atol=1e-6)
+    if E == 64:
+        assert np.all(g[7] == 0)
+
+
+def test_adam_step_matches_float64():
+    fw = fwmod()
+    rng = np.random.Generator(np.random.PCG64(8))
+    p = rng.normal(size=500)
+    g = rng.normal(size=500)
+    m = rng.normal(size=500) * 0.1
+    v = rng.random(500) * 0.1
+    for step in (1, 2, 50):
+        got = fw.rmi_adam_step(p, g, m, v, step, 0.01)
+        want = rmi.adam(p, g, m, v, step, 0.01)
+        for a, b in zip(got, want):
+            np.testing.assert_allclose(a, b, rtol=1e-5, atol=1e-6)
+
+
+def test_memory_budget_leaves_scan_usable():
+    import torch
+    fw = fwmod()
+    rules, pk = gen.workload("scan_100x10k", seed=6)
+    want = oracle.classify(rules, pk)
+    dp = fw.DevicePackets.from_host(pk)
+    with fw.Ruleset(rules) as rs:
+        with pytest.raises(fw.FwError) as ei:
+            rs.build_learned_index(mem_budget=1024)
+        assert ei.value.status == fw.E_NOMEM
+        with pytest.raises(fw.FwError) as ei:
+            rs.classify(dp, mode="learned")
+        assert ei.value.status == fw.E_NOINDEX
+        idx, act = rs.classify(dp)          # AUTO falls back to the scan
+        torch.cuda.synchronize()
+        assert_same((idx.cpu().numpy(), act.cpu().numpy()), want, "auto after failed build")
