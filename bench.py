@@ -34,6 +34,40 @@ VALU_INT32_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # (one subtract, one unsigned compare); deeper field tests are not counted.
 OPS_PER_CHECK = 2
 BYTES_PER_PACKET = 13 + 5          # 5-tuple in (4+4+2+2+1), index + action out (4+1)
+RECORD_BYTES = 32                  # one compiled rule record
+
+
+def learned_work(rs, pk, idx, hidden: int = 32):
+    """Exact algorithmic work of the learned path for every packet of the batch.
+
+    Candidate checks of packet p: the entries of its interval's merged list
+    (shared destination-wildcard list plus its own list) up to and including
+    its first match, or all of them when nothing matches.  Lane-ops: 2 per
+    candidate check (one subtract, one compare: the first field test), 6H per
+    packet for the two networks (per hidden unit a multiply-add, a max and a
+    multiply-add, in each stage) and 2 per binary-search probe of the mean
+    error window.  Bytes: the packet in, the result out, and a 32-byte record
+    gathered per check of the packet's own list.
+    """
+    B = rs.export(0).astype(np.int64)
+    off = rs.export(1).astype(np.int64)
+    L = rs.export(2).astype(np.int64)
+    G = rs.export(3).astype(np.int64)
+    err = rs.export(4).astype(np.float64)
+    M = len(B)
+    dst = pk.dst_ip.astype(np.int64)
+    j = np.searchsorted(B, dst, side="right") - 1
+    ans = np.where(idx < 0, 1 << 40, idx.astype(np.int64))
+    n_g = np.searchsorted(G, ans, side="right")
+    owner = np.repeat(np.arange(M, dtype=np.int64), np.diff(off))
+    key = owner * (1 << 41) + L
+    n_l = np.searchsorted(key, j * (1 << 41) + ans, side="right") - off[j]
+    checks = int(n_g.sum() + n_l.sum())
+    probes = math.ceil(math.log2(2.0 * float(err.mean()) + 1.0)) + 1
+    ops = 2 * checks + len(pk) * (6 * hidden + 2 * probes)
+    nbytes = len(pk) * BYTES_PER_PACKET + int(n_l.sum()) * RECORD_BYTES
+    return {"candidate_checks": checks, "own_list_checks": int(n_l.sum()),
+            "lane_ops": ops, "bytes": nbytes, "probes_per_packet": probes}
 
 
 def log(msg: str):
@@ -105,6 +139,10 @@ def main():
     ap.add_argument("--latency-batches", type=int, default=2000)
     ap.add_argument("--cpu-sample", type=int, default=4_194_304)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--modes", default="",
+                    help="comma list of modes to time (default: all); the first is the headline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the packet-split "
@@ -126,44 +164,84 @@ def main():
     torch.cuda.synchronize()
 
     rs = fw.Ruleset(rules)
-    modes = {"packet_split": dict(mode="packet_split"),
-             "rule_split_p16": dict(mode="rule_split", partitions=16)}
+    log("building the learned index (trained)")
+    t0 = time.perf_counter()
+    index_stats = rs.build_learned_index(seed=args.seed)
+    index_stats["build_s"] = time.perf_counter() - t0
+    rs_un = fw.Ruleset(rules)
+    log("building the learned index (untrained network)")
+    untrained_stats = rs_un.build_learned_index(seed=args.seed, train=False)
+    modes = {"learned": (rs, dict(mode="learned")),
+             "learned_binary_search": (rs, dict(mode="learned", lookup=1)),
+             "learned_untrained": (rs_un, dict(mode="learned")),
+             "packet_split": (rs, dict(mode="packet_split")),
+             "rule_split_p16": (rs, dict(mode="rule_split", partitions=16)),
+             "hybrid_p16": (rs, dict(mode="hybrid", partitions=16))}
+    if args.modes:
+        keep = args.modes.split(",")
+        modes = {k: modes[k] for k in keep}
     results = {}
     ref = None
-    for name, kw in modes.items():
+    for name, (ruleset, kw) in modes.items():
         log(f"timing {name}")
-        ms, wall = time_steps(lambda: rs.classify(dp, stream=stream, out_idx=out_i,
-                                                  out_act=out_a, **kw),
+        ms, wall = time_steps(lambda: ruleset.classify(dp, stream=stream, out_idx=out_i,
+                                                       out_act=out_a, **kw),
                               args.steps, args.warmup, stream)
         idx = out_i.cpu().numpy()
+        act = out_a.cpu().numpy()
         if ref is None:
-            ref = idx.copy()
-        agree = bool(np.array_equal(idx, ref))
-        checks = int(np.where(idx < 0, R, idx.astype(np.int64) + 1).sum())
-        results[name] = {"ms": ms, "mpps": n / ms / 1e3,
-                         "rule_checks_per_s": checks / (ms * 1e-3),
-                         "same_as_packet_split": agree, "wall_s": wall}
+            ref = (idx.copy(), act.copy())
+        agree = bool(np.array_equal(idx, ref[0]) and np.array_equal(act, ref[1]))
+        results[name] = {"ms": ms, "mpps": n / ms / 1e3, "same_as_learned": agree,
+                         "wall_s": wall}
+        if kw["mode"] == "learned":
+            _, _, miss = ruleset.classify(dp, stream=stream, out_idx=out_i, out_act=out_a,
+                                          count_misses=True, **kw)
+            results[name]["window_misses"] = miss
         log(f"  {name}: {ms:.3f} ms/step, {n / ms / 1e3:.1f} Mpps")
-
+    ref = ref[0]
     checks = int(np.where(ref < 0, R, ref.astype(np.int64) + 1).sum())
+    for name in [m for m in ("packet_split", "rule_split_p16", "hybrid_p16") if m in results]:
+        results[name]["rule_checks_per_s"] = checks / (results[name]["ms"] * 1e-3)
     full = ((rules.src_plen == 0) & (rules.dst_plen == 0) & (rules.proto_any != 0) &
             (rules.sport_lo == 0) & (rules.sport_hi == 65535) &
             (rules.dport_lo == 0) & (rules.dport_hi == 65535))
     k_star = int(np.argmax(full)) if full.any() else None   # first catch-all rule
 
     latency = {}
-    for name, kw in modes.items():
+    for name in [m for m in ("learned", "packet_split", "rule_split_p16", "hybrid_p16")
+                 if m in modes and args.latency_batches > 0]:
+        ruleset, kw = modes[name]
         log(f"latency {name}")
-        p50, p99 = closed_loop_latency(rs, dp, kw, args.seed, args.latency_batches, stream)
+        p50, p99 = closed_loop_latency(ruleset, dp, kw, args.seed, args.latency_batches, stream)
         latency[name] = {"p50_us": p50, "p99_us": p99}
 
-    head = "packet_split"
+    head = next(iter(modes))
     ms = results[head]["ms"]
-    achieved_tops = checks * OPS_PER_CHECK / (ms * 1e-3) / 1e12
+    work = learned_work(rs, pk, ref)
+    achieved_tops = work["lane_ops"] / (ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": achieved_tops, "peak": VALU_INT32_PEAK_TOPS,
                 "unit": "Tops/s", "frac": achieved_tops / VALU_INT32_PEAK_TOPS,
-                "traffic": None, "kernel": "k_packet_split<4>",
-                "hbm_gbs": n * BYTES_PER_PACKET / (ms * 1e-3) / 1e9}
+                "traffic": None, "kernel": "k_learned<true,true>",
+                "algorithmic_lane_ops": work["lane_ops"], "algorithmic_bytes": work["bytes"],
+                "hbm_gbs": work["bytes"] / (ms * 1e-3) / 1e9,
+                "hbm_frac": work["bytes"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    scan_roofline = None
+    if "packet_split" in results:
+        scan_ms = results["packet_split"]["ms"]
+        scan_ops = checks * OPS_PER_CHECK
+        scan_roofline = {"bound": "alu", "kernel": "k_packet_split<4>",
+                         "achieved": scan_ops / (scan_ms * 1e-3) / 1e12,
+                         "frac": scan_ops / (scan_ms * 1e-3) / 1e12 / VALU_INT32_PEAK_TOPS,
+                         "hbm_gbs": n * BYTES_PER_PACKET / (scan_ms * 1e-3) / 1e9}
+    if args.copy_calibration:
+        log("copy calibration: 256 MiB device-to-device")
+        a = torch.empty(64 << 20, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
 
     cpu = None
     if not args.no_cpu:
@@ -178,11 +256,18 @@ def main():
         "data": "synthetic (seeded generators)",
         "config": {"workload": args.workload, "rules": R, "packets": n, "seed": args.seed,
                    "path": head, "k_star": k_star},
+        "scan_mpps": results["packet_split"]["mpps"] if "packet_split" in results else None,
+        "speedup_vs_scan": (results["packet_split"]["ms"] / ms
+                            if "packet_split" in results else None),
+        "p99_us": latency.get(head, {}).get("p99_us"),
+        "p50_us": latency.get(head, {}).get("p50_us"),
         "modes": results, "latency": latency,
-        "rule_checks_per_s": checks / (ms * 1e-3),
-        "roofline": roofline, "cpu_baseline": cpu,
+        "scan_rule_checks": checks, "learned_candidate_checks": work["candidate_checks"],
+        "index": index_stats, "index_untrained": untrained_stats,
+        "roofline": roofline, "scan_roofline": scan_roofline, "cpu_baseline": cpu,
     }
     rs.close()
+    rs_un.close()
     print(json.dumps(line), flush=True)
 
 

@@ -243,6 +243,111 @@ fw_status fw_rmi_adam_step(size_t count, float *params, const float *grad, float
                            float *v, uint32_t step, float lr, float beta1, float beta2,
                            float eps);
 
+/* ------------------------------------------------------------------ many chains
+ * Not in the paper.  Many independent rulesets ("chains"), each with its own
+ * packet batch, classified in one persistent launch: work items (tiles of a
+ * chain's packets) are handed out from a device work queue, the most
+ * expensive chains first.  Results are exactly those of fw_classify on each
+ * chain alone. */
+
+typedef struct fw_chain_batch {
+    const fw_ruleset *rs;
+    fw_packets pk;           /* device arrays, 16-byte aligned */
+    size_t n;
+    int32_t *out_rule_idx;   /* device, 16-byte aligned */
+    uint8_t *out_action;     /* device, 16-byte aligned */
+} fw_chain_batch;
+
+typedef struct fw_multi_opts {
+    void *stream;              /* hipStream_t; NULL = null stream */
+    uint32_t packets_per_lane; /* 1, 2 or 4; 0 = tuned choice for this batch shape, else 4 */
+    uint32_t placement;        /* 0 = tuned (else scalar), 1 = rules through the scalar
+                                  cache, 2 = rules staged in LDS tiles */
+    uint32_t rule_tile;        /* LDS tile in rules: 256 or 1024; 0 = tuned or 1024 */
+    uint32_t _reserved;
+} fw_multi_opts;
+
+/* Classify every chain's batch in one persistent launch (asynchronous on the
+ * stream).  Chains with n == 0 are skipped.  Errors: FW_E_INVAL (NULL
+ * ruleset or buffer, bad option), FW_E_ALIGN, FW_E_DEVICE. */
+fw_status fw_classify_multi(const fw_chain_batch *batches, uint32_t n_chains,
+                            const fw_multi_opts *opts);
+
+/* Time every packets-per-lane x placement configuration on these batches
+ * (each run really classifies them), remember the fastest for this batch
+ * shape (rule and packet counts of every chain) so later calls with tuned
+ * options use it, and report it in *best (may be NULL) with its time in
+ * *best_ms (may be NULL).  Synchronous. */
+fw_status fw_autotune_multi(const fw_chain_batch *batches, uint32_t n_chains, void *stream,
+                            fw_multi_opts *best, float *best_ms);
+
+/* ------------------------------------------------------------------ serving
+ * Not in the paper (its Section V names asynchronous launches as future
+ * work).  A server keeps rulesets resident and classifies packet batches that
+ * arrive over time with continuous batching: up to `slots` requests are in
+ * flight at once, each on its own HIP stream, and a request is admitted as
+ * soon as a slot is free and its device memory fits in the server's budget;
+ * queued requests are admitted in arrival order.  Each request's result is the
+ * same as classifying it alone. */
+
+typedef struct fw_server fw_server;
+
+typedef struct fw_server_opts {
+    uint32_t slots;         /* requests in flight at once, 1..64; 0 = 8 */
+    uint32_t mode;          /* fw_mode used for every request (AUTO picks per chain) */
+    uint32_t partitions;    /* for rule split / hybrid; 0 = 16 */
+    uint32_t _reserved;
+    uint64_t mem_budget;    /* device bytes for in-flight packets and results; 0 = 256 MiB */
+} fw_server_opts;
+
+/* A batch of packet headers in HOST memory (structure of arrays).  Page-locked
+ * memory (hipHostMalloc) gives asynchronous copies; pageable memory works. */
+typedef struct fw_host_packets {
+    const uint32_t *src_ip;
+    const uint32_t *dst_ip;
+    const uint16_t *src_port;
+    const uint16_t *dst_port;
+    const uint8_t *proto;
+} fw_host_packets;
+
+/* Timestamps of one request, seconds on a monotonic clock. */
+typedef struct fw_request_times {
+    double submit, admit, done;
+} fw_request_times;
+
+/* Start a server over `n_chains` loaded rulesets (they must outlive it; a
+ * learned index built before the server starts is used by mode AUTO/LEARNED).
+ * Errors: FW_E_INVAL (no chains, NULL chain, bad options), FW_E_NOMEM,
+ * FW_E_DEVICE. */
+fw_status fw_server_create(fw_ruleset *const *chains, uint32_t n_chains,
+                           const fw_server_opts *opts, fw_server **out);
+
+/* Queue `n` packets (host memory) for chain `chain`; results go to the HOST
+ * arrays out_rule_idx / out_action.  All buffers must stay valid until
+ * fw_server_wait returns for *ticket.  FW_E_NOMEM if the request alone
+ * exceeds the memory budget (it could never be admitted). */
+fw_status fw_server_submit(fw_server *sv, uint32_t chain, const fw_host_packets *pk, size_t n,
+                           int32_t *out_rule_idx, uint8_t *out_action, uint64_t *ticket);
+
+/* Block until request `ticket` has completed; `times` may be NULL.  Returns
+ * the request's own status (a failed launch is reported here). */
+fw_status fw_server_wait(fw_server *sv, uint64_t ticket, fw_request_times *times);
+
+/* Wait for every request, stop the server and free its resources. */
+fw_status fw_server_destroy(fw_server *sv);
+
+/* Load generator: replay an arrival trace against a server.  Request k is
+ * submitted at t0 + arrival_s[k] (t0 = when the call starts; arrival_s
+ * non-decreasing) for chain[k], with packets [offset[k], offset[k] + n[k]) of
+ * the HOST pool arrays and results written at the same offsets of out_idx and
+ * out_action.  Returns once every request has completed; times[k] (may be
+ * NULL) receives the request's scheduled arrival as `submit`, so queueing
+ * behind a late generator still counts toward its latency. */
+fw_status fw_server_replay(fw_server *sv, uint32_t n_req, const double *arrival_s,
+                           const uint32_t *chain, const size_t *offset, const size_t *n,
+                           const fw_host_packets *pool, int32_t *out_idx, uint8_t *out_action,
+                           fw_request_times *times);
+
 /* Description of the calling thread's most recent error ("" if none). */
 const char *fw_last_error(void);
 

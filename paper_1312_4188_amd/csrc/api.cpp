@@ -17,6 +17,7 @@ struct fw_ruleset {
     uint8_t default_action = FW_DROP;
     int device = 0;
     fw::RuleRec* d_rules = nullptr;          // n_rules records (at least one allocated)
+    uint2* d_pairs = nullptr;                // (dst_lo, dst_w) per rule, + kPairPadding
     std::vector<fw::RuleRec> h_rules;        // host copy of the compiled records
     std::vector<fw_rule> source;             // the rules as given
     fw::LearnedIndex* index = nullptr;       // null until built
@@ -24,7 +25,7 @@ struct fw_ruleset {
 
 namespace fw {
 
-thread_local std::string g_last_error;
+thread_local std::string g_last_error;  // read by fw_last_error()
 
 fw_status fail(fw_status st, const char* fmt, ...) {
     char buf[512];
@@ -84,6 +85,14 @@ PacketsDev to_dev(const fw_packets* pk) {
     return PacketsDev{pk->src_ip, pk->dst_ip, pk->src_port, pk->dst_port, pk->proto};
 }
 
+void ruleset_view(const fw_ruleset* rs, const RuleRec** rules, const uint2** pairs,
+                  uint32_t* n_rules, uint8_t* default_action) {
+    *rules = rs->d_rules;
+    *pairs = rs->d_pairs;
+    *n_rules = rs->n_rules;
+    *default_action = rs->default_action;
+}
+
 // A device fault in earlier asynchronous work is sticky; report it before new work.
 static fw_status check_device_state() {
     const hipError_t e = hipGetLastError();
@@ -124,14 +133,22 @@ fw_status fw_load_ruleset(const fw_rule* rules, uint32_t n_rules, uint8_t defaul
     for (uint32_t i = 0; i < n_rules; ++i) rs->h_rules[i] = compile_rule(rules[i], i);
     rs->n_rules = n_rules;
     rs->default_action = default_action;
+    std::vector<uint2> pairs(size_t(n_rules) + kPairPadding, uint2{0u, 0u});
+    for (uint32_t i = 0; i < n_rules; ++i)
+        pairs[i] = uint2{rs->h_rules[i].dst_lo, rs->h_rules[i].dst_w};
     hipError_t e = hipGetDevice(&rs->device);
     if (e == hipSuccess)
         e = hipMalloc(&rs->d_rules, sizeof(RuleRec) * (n_rules ? n_rules : 1));
+    if (e == hipSuccess) e = hipMalloc(&rs->d_pairs, sizeof(uint2) * pairs.size());
     if (e == hipSuccess && n_rules)
         e = hipMemcpy(rs->d_rules, rs->h_rules.data(), sizeof(RuleRec) * n_rules,
                       hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(rs->d_pairs, pairs.data(), sizeof(uint2) * pairs.size(),
+                      hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         if (rs->d_rules) (void)hipFree(rs->d_rules);
+        if (rs->d_pairs) (void)hipFree(rs->d_pairs);
         delete rs;
         return hip_fail(e, "uploading the ruleset");
     }
@@ -144,8 +161,9 @@ fw_status fw_free_ruleset(fw_ruleset* rs) {
     hipError_t e = hipDeviceSynchronize();
     destroy_index(rs->index);
     rs->index = nullptr;
-    if (rs->d_rules) {
-        const hipError_t e2 = hipFree(rs->d_rules);
+    for (void* p : {static_cast<void*>(rs->d_rules), static_cast<void*>(rs->d_pairs)}) {
+        if (!p) continue;
+        const hipError_t e2 = hipFree(p);
         if (e == hipSuccess) e = e2;
     }
     delete rs;
@@ -185,7 +203,8 @@ fw_status fw_classify_ex(const fw_ruleset* rs, const fw_packets* pk, size_t n,
     hipError_t e = hipSuccess;
     switch (mode) {
         case FW_MODE_PACKET_SPLIT:
-            e = launch_packet_split(rs->d_rules, rs->n_rules, pd, n, out_rule_idx, out_action,
+            e = launch_packet_split(rs->d_pairs, rs->d_rules, rs->n_rules, pd, n, out_rule_idx,
+                                    out_action,
                                     rs->default_action,
                                     o.packets_per_lane ? int(o.packets_per_lane) : 4, stream);
             break;
@@ -194,7 +213,8 @@ fw_status fw_classify_ex(const fw_ruleset* rs, const fw_packets* pk, size_t n,
                                   rs->default_action, stream);
             break;
         case FW_MODE_HYBRID:
-            e = launch_hybrid(rs->d_rules, rs->n_rules, P, pd, n, out_rule_idx, out_action,
+            e = launch_hybrid(rs->d_pairs, rs->d_rules, rs->n_rules, P, pd, n, out_rule_idx,
+                              out_action,
                               rs->default_action, stream);
             break;
         case FW_MODE_LEARNED:

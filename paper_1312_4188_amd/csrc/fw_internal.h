@@ -8,6 +8,10 @@
 
 namespace fw {
 
+// Extra first-test pairs allocated past the end of every pair array, so a
+// scan can fetch the block after the last one without a bounds test.
+constexpr uint32_t kPairPadding = 8;
+
 // A compiled rule as the kernels read it: 32 bytes, every field a range test
 // (v - lo) <= w in unsigned arithmetic, so a prefix (base, len) becomes
 // lo = base with the low 32-len bits cleared and w = 2^(32-len) - 1.
@@ -36,14 +40,16 @@ struct PacketsDev {
 };
 
 // ---- scan launchers (scan.hip); all asynchronous on `stream`
-hipError_t launch_packet_split(const RuleRec* rules, uint32_t n_rules, PacketsDev pk,
+hipError_t launch_packet_split(const uint2* pairs, const RuleRec* rules, uint32_t n_rules,
+                               PacketsDev pk,
                                size_t n, int32_t* out_idx, uint8_t* out_act,
                                uint8_t default_action, int packets_per_lane,
                                hipStream_t stream);
 hipError_t launch_rule_split(const RuleRec* rules, uint32_t n_rules, uint32_t partitions,
                              PacketsDev pk, size_t n, int32_t* out_idx, uint8_t* out_act,
                              uint8_t default_action, hipStream_t stream);
-hipError_t launch_hybrid(const RuleRec* rules, uint32_t n_rules, uint32_t partitions,
+hipError_t launch_hybrid(const uint2* pairs, const RuleRec* rules, uint32_t n_rules,
+                         uint32_t partitions,
                          PacketsDev pk, size_t n, int32_t* out_idx, uint8_t* out_act,
                          uint8_t default_action, hipStream_t stream);
 

@@ -18,6 +18,7 @@
 #include "device_util.h"
 #include "fw_internal.h"
 #include "index.h"
+#include "scan_core.h"
 
 namespace fw {
 namespace {
@@ -352,24 +353,15 @@ __global__ __launch_bounds__(kLearnedBlock) void k_learned(LookupArgs a, Packets
                 }
             }
         }
-        uint64_t live = ballot(valid);
-        for (uint32_t g = 0; g < a.nG && live != 0; ++g) {
-            const RuleRec q = a.G[g];
-            if ((g & 7u) == 0) {
-                live &= ballot(best > q.idx);
-                if (live == 0) break;
-            }
-            uint64_t m = ballot(in_range(src, q.src_lo, q.src_w)) & live;
-            if (m == 0) continue;
-            m &= ballot(ports_in(pp, q.port_lo, q.port_w)) &
-                 ballot(in_range(pr, proto_lo(q.proto), proto_w(q.proto)));
-            if (m == 0) continue;
-            m &= ballot(best > q.idx);
-            if ((m >> lane) & 1u) {
-                best = q.idx;
-                act = rule_action(q.proto);
-            }
-            live &= ~m;
+        // shared list: wave-uniform records, source tested first (the
+        // destination test is implied); the two partial first matches meet
+        // in a minimum
+        WaveScan<1> w;
+        w.init_values(src, x, pp, pr, valid, dflt);
+        w.template scan<FirstField::Src, true>(a.Gpairs, a.G, a.nG, 0u);
+        if (w.best[0] < best) {
+            best = w.best[0];
+            act = w.act[0];
         }
         if (valid) {
             out_idx[i] = int32_t(best);

@@ -12,157 +12,24 @@
 // Every field test is the unsigned range test (v - lo) <= w (see RuleRec).
 #include "device_util.h"
 #include "fw_internal.h"
+#include "scan_core.h"
 
 namespace fw {
 namespace {
 
-// Load K consecutive packets starting at p0 (p0 is a multiple of K).  Full
-// groups use one 128-bit (K=4), 64-bit (K=2) or 32-bit load per address array;
-// the ragged tail falls back to element loads.
-template <int K>
-__device__ __forceinline__ void load_packets(const PacketsDev& pk, size_t p0, size_t n,
-                                             uint32_t (&src)[K], uint32_t (&dst)[K],
-                                             uint32_t (&pp)[K], uint32_t (&pr)[K]) {
-    if (p0 + K <= n) {
-        if constexpr (K == 4) {
-            const uint4 s = *reinterpret_cast<const uint4*>(pk.src + p0);
-            const uint4 d = *reinterpret_cast<const uint4*>(pk.dst + p0);
-            const uint2 sp = *reinterpret_cast<const uint2*>(pk.sport + p0);
-            const uint2 dp = *reinterpret_cast<const uint2*>(pk.dport + p0);
-            const uint32_t p = *reinterpret_cast<const uint32_t*>(pk.proto + p0);
-            src[0] = s.x; src[1] = s.y; src[2] = s.z; src[3] = s.w;
-            dst[0] = d.x; dst[1] = d.y; dst[2] = d.z; dst[3] = d.w;
-            // packed pair = sport << 16 | dport
-            pp[0] = (sp.x << 16) | (dp.x & 0xFFFFu);
-            pp[1] = (sp.x & 0xFFFF0000u) | (dp.x >> 16);
-            pp[2] = (sp.y << 16) | (dp.y & 0xFFFFu);
-            pp[3] = (sp.y & 0xFFFF0000u) | (dp.y >> 16);
-            pr[0] = p & 0xFFu; pr[1] = (p >> 8) & 0xFFu;
-            pr[2] = (p >> 16) & 0xFFu; pr[3] = p >> 24;
-            return;
-        } else if constexpr (K == 2) {
-            const uint2 s = *reinterpret_cast<const uint2*>(pk.src + p0);
-            const uint2 d = *reinterpret_cast<const uint2*>(pk.dst + p0);
-            const uint32_t sp = *reinterpret_cast<const uint32_t*>(pk.sport + p0);
-            const uint32_t dp = *reinterpret_cast<const uint32_t*>(pk.dport + p0);
-            const uint32_t p = *reinterpret_cast<const uint16_t*>(pk.proto + p0);
-            src[0] = s.x; src[1] = s.y;
-            dst[0] = d.x; dst[1] = d.y;
-            pp[0] = (sp << 16) | (dp & 0xFFFFu);
-            pp[1] = (sp & 0xFFFF0000u) | (dp >> 16);
-            pr[0] = p & 0xFFu; pr[1] = p >> 8;
-            return;
-        }
-    }
-#pragma unroll
-    for (int s = 0; s < K; ++s) {
-        const size_t i = p0 + s;
-        const bool ok = i < n;
-        src[s] = ok ? pk.src[i] : 0u;
-        dst[s] = ok ? pk.dst[i] : 0u;
-        pp[s] = ok ? ((uint32_t(pk.sport[i]) << 16) | pk.dport[i]) : 0u;
-        pr[s] = ok ? uint32_t(pk.proto[i]) : 0u;
-    }
-}
-
-template <int K>
-__device__ __forceinline__ void store_results(int32_t* out_idx, uint8_t* out_act, size_t p0,
-                                              size_t n, const uint32_t (&best)[K],
-                                              const uint32_t (&act)[K]) {
-    if (p0 + K <= n) {
-        if constexpr (K == 4) {
-            *reinterpret_cast<int4*>(out_idx + p0) =
-                make_int4(int(best[0]), int(best[1]), int(best[2]), int(best[3]));
-            *reinterpret_cast<uint32_t*>(out_act + p0) =
-                act[0] | (act[1] << 8) | (act[2] << 16) | (act[3] << 24);
-            return;
-        } else if constexpr (K == 2) {
-            *reinterpret_cast<int2*>(out_idx + p0) = make_int2(int(best[0]), int(best[1]));
-            *reinterpret_cast<uint16_t*>(out_act + p0) = uint16_t(act[0] | (act[1] << 8));
-            return;
-        }
-    }
-#pragma unroll
-    for (int s = 0; s < K; ++s) {
-        if (p0 + s < n) {
-            out_idx[p0 + s] = int32_t(best[s]);
-            out_act[p0 + s] = uint8_t(act[s]);
-        }
-    }
-}
-
 // ------------------------------------------------------------------ packet split
-// A wave owns 64*K packets (K per lane) and walks the rules in order.  The rule
-// address is wave-uniform, so each 32-byte record arrives through one scalar
-// load and the field tests take their rule operands from SGPRs.  A ballot per
-// field turns the lanes' tests into a wave mask: when no live lane passes a
-// field the rest of the rule is skipped (most rules are rejected by the
-// destination test alone), and once every live lane has matched the wave
-// stops.
+// The packet-split kernel: each wave classifies 64*K packets with scan_wave.
 template <int K>
-__global__ __launch_bounds__(256) void k_packet_split(const RuleRec* __restrict__ rules,
+__global__ __launch_bounds__(256) void k_packet_split(const uint2* __restrict__ pairs,
+                                                      const RuleRec* __restrict__ rules,
                                                       uint32_t n_rules, PacketsDev pk, size_t n,
                                                       int32_t* __restrict__ out_idx,
                                                       uint8_t* __restrict__ out_act,
                                                       uint32_t dflt) {
-    const uint32_t lane = threadIdx.x & 63u;
     const size_t wave = (size_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
     const size_t wave_first = wave * 64u * K;
     if (wave_first >= n) return;  // wave-uniform
-    const size_t p0 = wave_first + size_t(lane) * K;
-
-    uint32_t src[K], dst[K], pp[K], pr[K];
-    load_packets<K>(pk, p0, n, src, dst, pp, pr);
-
-    uint64_t live[K];
-    uint32_t best[K], act[K];
-#pragma unroll
-    for (int s = 0; s < K; ++s) {
-        live[s] = ballot(p0 + s < n);
-        best[s] = kNoMatch;
-        act[s] = dflt;
-    }
-
-    for (uint32_t r = 0; r < n_rules; ++r) {
-        const RuleRec q = rules[r];
-        uint64_t m[K];
-        uint64_t any = 0;
-#pragma unroll
-        for (int s = 0; s < K; ++s) {
-            m[s] = ballot(in_range(dst[s], q.dst_lo, q.dst_w)) & live[s];
-            any |= m[s];
-        }
-        if (any == 0) continue;
-        any = 0;
-#pragma unroll
-        for (int s = 0; s < K; ++s) {
-            m[s] &= ballot(in_range(src[s], q.src_lo, q.src_w));
-            any |= m[s];
-        }
-        if (any == 0) continue;
-        any = 0;
-        const uint32_t plo = proto_lo(q.proto), pw = proto_w(q.proto);
-#pragma unroll
-        for (int s = 0; s < K; ++s) {
-            m[s] &= ballot(ports_in(pp[s], q.port_lo, q.port_w)) &
-                    ballot(in_range(pr[s], plo, pw));
-            any |= m[s];
-        }
-        if (any == 0) continue;
-        const uint32_t ra = rule_action(q.proto);
-        uint64_t left = 0;
-#pragma unroll
-        for (int s = 0; s < K; ++s) {
-            if ((m[s] >> lane) & 1u) {
-                best[s] = r;
-                act[s] = ra;
-            }
-            live[s] &= ~m[s];
-            left |= live[s];
-        }
-        if (left == 0) break;
-    }
-    store_results<K>(out_idx, out_act, p0, n, best, act);
+    scan_wave<K>(pairs, rules, n_rules, pk, wave_first, n, out_idx, out_act, dflt);
 }
 
 // ------------------------------------------------------------------ rule split
@@ -282,53 +149,41 @@ __global__ void k_apply_action(const RuleRec* __restrict__ rules, const int32_t*
 }
 
 // ------------------------------------------------------------------ hybrid
-// One workgroup per 64 packets (paper Section IV-C: a block per packet, its
+// One work-group per 64 packets (paper Section IV-C: a block per packet, its
 // threads splitting the rules; here a lane per packet and a wave per rule
-// partition).  Wave w scans partition w with the packet-split inner loop;
-// partial first matches meet in LDS through atomicMin, and every kPrune
-// rules a wave drops lanes that another wave has already beaten.
-__global__ __launch_bounds__(1024) void k_hybrid(const RuleRec* __restrict__ rules,
+// partition).  Wave w scans partition w with the packet-split wave scan, in
+// chunks of kHybridChunk rules; after each chunk its lanes' first matches go
+// into LDS through atomicMin, and lanes that another wave has already beaten
+// (an LDS minimum below the next rule index) drop out.
+constexpr uint32_t kHybridChunk = 64;
+
+__global__ __launch_bounds__(1024) void k_hybrid(const uint2* __restrict__ pairs,
+                                                 const RuleRec* __restrict__ rules,
                                                  uint32_t n_rules, uint32_t S, PacketsDev pk,
                                                  size_t n, int32_t* __restrict__ out_idx,
                                                  uint8_t* __restrict__ out_act, uint32_t dflt) {
     __shared__ uint32_t smin[64];
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t w = threadIdx.x >> 6;
-    const size_t i = size_t(blockIdx.x) * 64u + lane;
+    const size_t first = size_t(blockIdx.x) * 64u;
     if (w == 0) smin[lane] = kNoMatch;
     __syncthreads();
 
-    uint32_t src = 0, dst = 0, pp = 0, pr = 0;
-    if (i < n) {
-        src = pk.src[i];
-        dst = pk.dst[i];
-        pp = (uint32_t(pk.sport[i]) << 16) | pk.dport[i];
-        pr = pk.proto[i];
-    }
-    uint64_t live = ballot(i < n);
+    WaveScan<1> ws;
+    ws.init(pk, first, n, dflt);
     const uint64_t r0 = uint64_t(w) * S;
     const uint32_t begin = uint32_t(r0 < n_rules ? r0 : n_rules);
     const uint32_t end = uint32_t(r0 + S < n_rules ? r0 + S : n_rules);
-    uint32_t since = 0;
-    for (uint32_t r = begin; r < end && live != 0; ++r) {
-        if (++since == kPrune) {
-            since = 0;
-            const uint32_t cur = __atomic_load_n(&smin[lane], __ATOMIC_RELAXED);
-            live &= ballot(cur > r);
-            if (live == 0) break;
-        }
-        const RuleRec q = rules[r];
-        uint64_t m = ballot(in_range(dst, q.dst_lo, q.dst_w)) & live;
-        if (m == 0) continue;
-        m &= ballot(in_range(src, q.src_lo, q.src_w));
-        if (m == 0) continue;
-        m &= ballot(ports_in(pp, q.port_lo, q.port_w)) &
-             ballot(in_range(pr, proto_lo(q.proto), proto_w(q.proto)));
-        if (m == 0) continue;
-        if ((m >> lane) & 1u) atomicMin(&smin[lane], r);
-        live &= ~m;
+    for (uint32_t c = begin; c < end && ws.any_live(); c += kHybridChunk) {
+        const uint32_t cnt = min(kHybridChunk, end - c);
+        ws.template scan<FirstField::Dst>(pairs + c, rules + c, cnt, c);
+        if (ws.best[0] != kNoMatch) atomicMin(&smin[lane], ws.best[0]);
+        const uint32_t cur = *reinterpret_cast<volatile uint32_t*>(&smin[lane]);
+        ws.live[0] &= ballot(cur > c + cnt);
+        ws.live_any = ws.live[0];
     }
     __syncthreads();
+    const size_t i = first + lane;
     if (w == 0 && i < n) {
         const uint32_t b = smin[lane];
         out_idx[i] = int32_t(b);
@@ -340,7 +195,8 @@ inline uint32_t ceil_div(uint64_t a, uint64_t b) { return uint32_t((a + b - 1) /
 
 }  // namespace
 
-hipError_t launch_packet_split(const RuleRec* rules, uint32_t n_rules, PacketsDev pk, size_t n,
+hipError_t launch_packet_split(const uint2* pairs, const RuleRec* rules, uint32_t n_rules,
+                               PacketsDev pk, size_t n,
                                int32_t* out_idx, uint8_t* out_act, uint8_t default_action,
                                int packets_per_lane, hipStream_t stream) {
     if (n == 0) return hipSuccess;
@@ -349,14 +205,14 @@ hipError_t launch_packet_split(const RuleRec* rules, uint32_t n_rules, PacketsDe
     const uint64_t per_block = uint64_t(kBlock) * K;
     const uint32_t grid = ceil_div(n, per_block);
     if (K == 4)
-        hipLaunchKernelGGL(k_packet_split<4>, dim3(grid), dim3(kBlock), 0, stream, rules,
-                           n_rules, pk, n, out_idx, out_act, uint32_t(default_action));
+        hipLaunchKernelGGL(k_packet_split<4>, dim3(grid), dim3(kBlock), 0, stream, pairs,
+                           rules, n_rules, pk, n, out_idx, out_act, uint32_t(default_action));
     else if (K == 2)
-        hipLaunchKernelGGL(k_packet_split<2>, dim3(grid), dim3(kBlock), 0, stream, rules,
-                           n_rules, pk, n, out_idx, out_act, uint32_t(default_action));
+        hipLaunchKernelGGL(k_packet_split<2>, dim3(grid), dim3(kBlock), 0, stream, pairs,
+                           rules, n_rules, pk, n, out_idx, out_act, uint32_t(default_action));
     else
-        hipLaunchKernelGGL(k_packet_split<1>, dim3(grid), dim3(kBlock), 0, stream, rules,
-                           n_rules, pk, n, out_idx, out_act, uint32_t(default_action));
+        hipLaunchKernelGGL(k_packet_split<1>, dim3(grid), dim3(kBlock), 0, stream, pairs,
+                           rules, n_rules, pk, n, out_idx, out_act, uint32_t(default_action));
     return hipGetLastError();
 }
 
@@ -397,13 +253,14 @@ hipError_t launch_rule_split(const RuleRec* rules, uint32_t n_rules, uint32_t P,
     return hipGetLastError();
 }
 
-hipError_t launch_hybrid(const RuleRec* rules, uint32_t n_rules, uint32_t P, PacketsDev pk,
+hipError_t launch_hybrid(const uint2* pairs, const RuleRec* rules, uint32_t n_rules, uint32_t P,
+                         PacketsDev pk,
                          size_t n, int32_t* out_idx, uint8_t* out_act, uint8_t default_action,
                          hipStream_t stream) {
     if (n == 0) return hipSuccess;
     const uint32_t S = n_rules == 0 ? 1u : ceil_div(n_rules, P);
-    hipLaunchKernelGGL(k_hybrid, dim3(ceil_div(n, 64)), dim3(64 * P), 0, stream, rules, n_rules,
-                       S, pk, n, out_idx, out_act, uint32_t(default_action));
+    hipLaunchKernelGGL(k_hybrid, dim3(ceil_div(n, 64)), dim3(64 * P), 0, stream, pairs, rules,
+                       n_rules, S, pk, n, out_idx, out_act, uint32_t(default_action));
     return hipGetLastError();
 }
 

@@ -1,0 +1,243 @@
+// The packet-split scan of one wave, shared by the single-chain and the
+// multi-chain kernels.
+#pragma once
+
+#include "device_util.h"
+#include "fw_internal.h"
+
+namespace fw {
+
+// Load K consecutive packets starting at p0 (p0 is a multiple of K).  Full
+// groups use one 128-bit (K=4), 64-bit (K=2) or 32-bit load per address array;
+// the ragged tail falls back to element loads.
+template <int K>
+__device__ __forceinline__ void load_packets(const PacketsDev& pk, size_t p0, size_t n,
+                                             uint32_t (&src)[K], uint32_t (&dst)[K],
+                                             uint32_t (&pp)[K], uint32_t (&pr)[K]) {
+    if (p0 + K <= n) {
+        if constexpr (K == 4) {
+            const uint4 s = *reinterpret_cast<const uint4*>(pk.src + p0);
+            const uint4 d = *reinterpret_cast<const uint4*>(pk.dst + p0);
+            const uint2 sp = *reinterpret_cast<const uint2*>(pk.sport + p0);
+            const uint2 dp = *reinterpret_cast<const uint2*>(pk.dport + p0);
+            const uint32_t p = *reinterpret_cast<const uint32_t*>(pk.proto + p0);
+            src[0] = s.x; src[1] = s.y; src[2] = s.z; src[3] = s.w;
+            dst[0] = d.x; dst[1] = d.y; dst[2] = d.z; dst[3] = d.w;
+            // packed pair = sport << 16 | dport
+            pp[0] = (sp.x << 16) | (dp.x & 0xFFFFu);
+            pp[1] = (sp.x & 0xFFFF0000u) | (dp.x >> 16);
+            pp[2] = (sp.y << 16) | (dp.y & 0xFFFFu);
+            pp[3] = (sp.y & 0xFFFF0000u) | (dp.y >> 16);
+            pr[0] = p & 0xFFu; pr[1] = (p >> 8) & 0xFFu;
+            pr[2] = (p >> 16) & 0xFFu; pr[3] = p >> 24;
+            return;
+        } else if constexpr (K == 2) {
+            const uint2 s = *reinterpret_cast<const uint2*>(pk.src + p0);
+            const uint2 d = *reinterpret_cast<const uint2*>(pk.dst + p0);
+            const uint32_t sp = *reinterpret_cast<const uint32_t*>(pk.sport + p0);
+            const uint32_t dp = *reinterpret_cast<const uint32_t*>(pk.dport + p0);
+            const uint32_t p = *reinterpret_cast<const uint16_t*>(pk.proto + p0);
+            src[0] = s.x; src[1] = s.y;
+            dst[0] = d.x; dst[1] = d.y;
+            pp[0] = (sp << 16) | (dp & 0xFFFFu);
+            pp[1] = (sp & 0xFFFF0000u) | (dp >> 16);
+            pr[0] = p & 0xFFu; pr[1] = p >> 8;
+            return;
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+        const size_t i = p0 + s;
+        const bool ok = i < n;
+        src[s] = ok ? pk.src[i] : 0u;
+        dst[s] = ok ? pk.dst[i] : 0u;
+        pp[s] = ok ? ((uint32_t(pk.sport[i]) << 16) | pk.dport[i]) : 0u;
+        pr[s] = ok ? uint32_t(pk.proto[i]) : 0u;
+    }
+}
+
+template <int K>
+__device__ __forceinline__ void store_results(int32_t* out_idx, uint8_t* out_act, size_t p0,
+                                              size_t n, const uint32_t (&best)[K],
+                                              const uint32_t (&act)[K]) {
+    if (p0 + K <= n) {
+        if constexpr (K == 4) {
+            *reinterpret_cast<int4*>(out_idx + p0) =
+                make_int4(int(best[0]), int(best[1]), int(best[2]), int(best[3]));
+            *reinterpret_cast<uint32_t*>(out_act + p0) =
+                act[0] | (act[1] << 8) | (act[2] << 16) | (act[3] << 24);
+            return;
+        } else if constexpr (K == 2) {
+            *reinterpret_cast<int2*>(out_idx + p0) = make_int2(int(best[0]), int(best[1]));
+            *reinterpret_cast<uint16_t*>(out_act + p0) = uint16_t(act[0] | (act[1] << 8));
+            return;
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+        if (p0 + s < n) {
+            out_idx[p0 + s] = int32_t(best[s]);
+            out_act[p0 + s] = uint8_t(act[s]);
+        }
+    }
+}
+
+// Which packet field a scan tests first (the rest only when some live lane passes).
+enum class FirstField { Dst, Src };
+
+// Rules per prefetch block of the first-test pairs: 8 pairs = 64 bytes, one
+// scalar load.  Pair arrays carry kPairPadding extra entries so the block
+// after the last one can be fetched without a bounds test.
+constexpr uint32_t kPairBlock = 8;
+static_assert(kPairPadding >= kPairBlock, "pair arrays must be padded by a whole block");
+
+// First-match state of one wave over 64*K packets (K per lane), advanced over
+// any number of consecutive rule blocks.  Rule addresses are wave-uniform: the
+// first-test pair (lo, w) of each rule arrives through scalar loads, 8 rules
+// at a time and one block ahead, so the field test takes its rule operands from
+// SGPRs without waiting.  A ballot turns the lanes' tests into a wave mask;
+// when no live lane passes, the rule is done after 2K vector ops (most rules
+// are rejected this way).  Otherwise the full record is read and the remaining
+// fields are tested the same way.  Once every live lane has matched the scan
+// stops.
+template <int K>
+struct WaveScan {
+    uint32_t src[K], dst[K], pp[K], pr[K];
+    uint64_t live[K];
+    uint64_t live_any;
+    uint32_t best[K], act[K];
+    size_t p0;
+
+    __device__ __forceinline__ void init(const PacketsDev& pk, size_t wave_first, size_t n,
+                                         uint32_t dflt) {
+        p0 = wave_first + size_t(threadIdx.x & 63u) * K;
+        load_packets<K>(pk, p0, n, src, dst, pp, pr);
+        live_any = 0;
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            live[s] = ballot(p0 + s < n);
+            live_any |= live[s];
+            best[s] = kNoMatch;
+            act[s] = dflt;
+        }
+    }
+
+    // Single-packet-per-lane start from values already in registers.
+    __device__ __forceinline__ void init_values(uint32_t s_, uint32_t d_, uint32_t pp_,
+                                                uint32_t pr_, bool valid, uint32_t dflt) {
+        static_assert(K == 1, "one packet per lane");
+        src[0] = s_;
+        dst[0] = d_;
+        pp[0] = pp_;
+        pr[0] = pr_;
+        live[0] = ballot(valid);
+        live_any = live[0];
+        best[0] = kNoMatch;
+        act[0] = dflt;
+        p0 = 0;
+    }
+
+    __device__ __forceinline__ bool any_live() const { return live_any != 0; }
+
+    // Remaining tests of a rule some live lane passed on its first field;
+    // records matches and clears matched lanes from the live masks.
+    template <FirstField F>
+    __device__ __forceinline__ void finish(const uint64_t (&c)[K], const RuleRec& q,
+                                           uint32_t idx) {
+        const uint32_t lane = threadIdx.x & 63u;
+        const uint32_t plo = proto_lo(q.proto), pw = proto_w(q.proto);
+        uint64_t m[K];
+        uint64_t any = 0;
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            m[s] = c[s] & live[s];
+            if constexpr (F == FirstField::Dst) m[s] &= ballot(in_range(src[s], q.src_lo, q.src_w));
+            m[s] &= ballot(ports_in(pp[s], q.port_lo, q.port_w)) &
+                    ballot(in_range(pr[s], plo, pw));
+            any |= m[s];
+        }
+        if (any == 0) return;
+        const uint32_t ra = rule_action(q.proto);
+        live_any = 0;
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            if ((m[s] >> lane) & 1u) {
+                best[s] = idx;
+                act[s] = ra;
+            }
+            live[s] &= ~m[s];
+            live_any |= live[s];
+        }
+    }
+
+    // First-field test of rule r for every slot; the full record is read only
+    // when some live lane passes.
+    template <FirstField F, bool OWN_INDEX>
+    __device__ __forceinline__ void step(uint2 f, const RuleRec* __restrict__ rules, uint32_t r,
+                                         uint32_t base) {
+        uint64_t c[K];
+        uint64_t any = 0;
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            c[s] = ballot(in_range(F == FirstField::Dst ? dst[s] : src[s], f.x, f.y));
+            any |= c[s];
+        }
+        if (__builtin_expect((any & live_any) != 0, 0)) {
+            const RuleRec q = rules[r];
+            finish<F>(c, q, OWN_INDEX ? q.idx : base + r);
+        }
+    }
+
+    // Rules r = 0..count-1: first-test pair first[r], record rules[r], global
+    // index base + r (or the record's own index field with OWN_INDEX).  The
+    // pairs come 8 at a time, one block ahead; the wave stops after the block
+    // in which its last live lane matched.  Returns false once every packet of
+    // the wave has matched.
+    template <FirstField F, bool OWN_INDEX = false>
+    __device__ __forceinline__ bool scan(const uint2* __restrict__ first,
+                                         const RuleRec* __restrict__ rules, uint32_t count,
+                                         uint32_t base) {
+        if (live_any == 0) return false;
+        uint32_t r = 0;
+        if (count >= kPairBlock) {
+            uint2 cur[kPairBlock];
+#pragma unroll
+            for (uint32_t u = 0; u < kPairBlock; ++u) cur[u] = first[u];
+            for (; r + kPairBlock <= count; r += kPairBlock) {
+                uint2 nxt[kPairBlock];
+#pragma unroll
+                for (uint32_t u = 0; u < kPairBlock; ++u) nxt[u] = first[r + kPairBlock + u];
+#pragma unroll
+                for (uint32_t u = 0; u < kPairBlock; ++u)
+                    step<F, OWN_INDEX>(cur[u], rules, r + u, base);
+                if (live_any == 0) return false;
+#pragma unroll
+                for (uint32_t u = 0; u < kPairBlock; ++u) cur[u] = nxt[u];
+            }
+        }
+        for (; r < count; ++r) {
+            step<F, OWN_INDEX>(first[r], rules, r, base);
+            if (live_any == 0) return false;
+        }
+        return true;
+    }
+
+    __device__ __forceinline__ void store(int32_t* out_idx, uint8_t* out_act, size_t n) const {
+        store_results<K>(out_idx, out_act, p0, n, best, act);
+    }
+};
+
+// One wave classifies the 64*K packets starting at wave_first.
+template <int K>
+__device__ __forceinline__ void scan_wave(const uint2* __restrict__ first,
+                                          const RuleRec* __restrict__ rules, uint32_t n_rules,
+                                          const PacketsDev& pk, size_t wave_first, size_t n,
+                                          int32_t* __restrict__ out_idx,
+                                          uint8_t* __restrict__ out_act, uint32_t dflt) {
+    WaveScan<K> w;
+    w.init(pk, wave_first, n, dflt);
+    w.template scan<FirstField::Dst>(first, rules, n_rules, 0u);
+    w.store(out_idx, out_act, n);
+}
+
+}  // namespace fw

@@ -63,6 +63,34 @@ class IndexStats(ctypes.Structure):
                 ("train_ms", ctypes.c_float), ("device_bytes", ctypes.c_uint64)]
 
 
+class ChainBatch(ctypes.Structure):
+    _fields_ = [("rs", ctypes.c_void_p), ("pk", Packets), ("n", ctypes.c_size_t),
+                ("out_rule_idx", ctypes.c_void_p), ("out_action", ctypes.c_void_p)]
+
+
+class MultiOpts(ctypes.Structure):
+    _fields_ = [("stream", ctypes.c_void_p), ("packets_per_lane", ctypes.c_uint32),
+                ("placement", ctypes.c_uint32), ("rule_tile", ctypes.c_uint32),
+                ("_reserved", ctypes.c_uint32)]
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_uint32), ("mode", ctypes.c_uint32),
+                ("partitions", ctypes.c_uint32), ("_reserved", ctypes.c_uint32),
+                ("mem_budget", ctypes.c_uint64)]
+
+
+class HostPackets(ctypes.Structure):
+    _fields_ = [("src_ip", ctypes.c_void_p), ("dst_ip", ctypes.c_void_p),
+                ("src_port", ctypes.c_void_p), ("dst_port", ctypes.c_void_p),
+                ("proto", ctypes.c_void_p)]
+
+
+class RequestTimes(ctypes.Structure):
+    _fields_ = [("submit", ctypes.c_double), ("admit", ctypes.c_double),
+                ("done", ctypes.c_double)]
+
+
 #: Every symbol include/fw.h declares, with (restype, argtypes).
 _VP, _SZ, _U32, _U8 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint32, ctypes.c_uint8
 SIGNATURES = {
@@ -79,6 +107,19 @@ SIGNATURES = {
     "fw_rmi_gradients": (ctypes.c_int, [_U32, _U32, _VP, _SZ, _VP, _VP, _VP, _U32, _VP, _VP]),
     "fw_rmi_adam_step": (ctypes.c_int, [_SZ, _VP, _VP, _VP, _VP, _U32, ctypes.c_float,
                                         ctypes.c_float, ctypes.c_float, ctypes.c_float]),
+    "fw_classify_multi": (ctypes.c_int, [ctypes.POINTER(ChainBatch), _U32,
+                                         ctypes.POINTER(MultiOpts)]),
+    "fw_autotune_multi": (ctypes.c_int, [ctypes.POINTER(ChainBatch), _U32, _VP,
+                                         ctypes.POINTER(MultiOpts),
+                                         ctypes.POINTER(ctypes.c_float)]),
+    "fw_server_create": (ctypes.c_int, [ctypes.POINTER(_VP), _U32, ctypes.POINTER(ServerOpts),
+                                        ctypes.POINTER(_VP)]),
+    "fw_server_submit": (ctypes.c_int, [_VP, _U32, ctypes.POINTER(HostPackets), _SZ, _VP, _VP,
+                                        ctypes.POINTER(ctypes.c_uint64)]),
+    "fw_server_wait": (ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.POINTER(RequestTimes)]),
+    "fw_server_destroy": (ctypes.c_int, [_VP]),
+    "fw_server_replay": (ctypes.c_int, [_VP, _U32, _VP, _VP, _VP, _VP,
+                                        ctypes.POINTER(HostPackets), _VP, _VP, _VP]),
     "fw_last_error": (ctypes.c_char_p, []),
 }
 
@@ -293,3 +334,107 @@ def rmi_adam_step(params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8
     _check(load_library().fw_rmi_adam_step(p.size, p.ctypes.data, g.ctypes.data, m.ctypes.data,
                                            v.ctypes.data, int(step), lr, beta1, beta2, eps))
     return p, m, v
+
+
+def _chain_array(items):
+    """items: list of (Ruleset, DevicePackets, out_idx tensor, out_act tensor)."""
+    arr = (ChainBatch * len(items))()
+    for k, (rs, pk, oi, oa) in enumerate(items):
+        arr[k] = ChainBatch(rs.handle.value, pk.c_struct(), len(pk), oi.data_ptr(),
+                            oa.data_ptr())
+    return arr
+
+
+def classify_multi(items, stream=None, packets_per_lane=0, placement=0, rule_tile=0):
+    """One persistent launch over many chains; items as for _chain_array (outputs preallocated)."""
+    arr = _chain_array(items)
+    opts = MultiOpts(_stream_ptr(stream), int(packets_per_lane), int(placement), int(rule_tile), 0)
+    _check(load_library().fw_classify_multi(arr, len(items), ctypes.byref(opts)))
+
+
+def autotune_multi(items, stream=None):
+    """Time the configuration grid on these chains; returns (options dict, best ms)."""
+    arr = _chain_array(items)
+    best = MultiOpts()
+    ms = ctypes.c_float(0)
+    _check(load_library().fw_autotune_multi(arr, len(items), _stream_ptr(stream),
+                                            ctypes.byref(best), ctypes.byref(ms)))
+    return ({"packets_per_lane": best.packets_per_lane, "placement": best.placement,
+             "rule_tile": best.rule_tile}, float(ms.value))
+
+
+class Server:
+    """Continuous-batching server over resident rulesets (fw_server_*).
+
+    ``submit`` takes host arrays (numpy, ideally views of pinned torch tensors)
+    that must stay alive until ``wait`` returns for the ticket; it returns the
+    ticket at once.  ``wait`` returns the request's (submit, admit, done)
+    times in seconds.
+    """
+
+    def __init__(self, rulesets, slots: int = 8, mode="auto", partitions: int = 0,
+                 mem_budget: int = 0):
+        lib = load_library()
+        self._chains = list(rulesets)
+        arr = (ctypes.c_void_p * len(self._chains))(*[r.handle.value for r in self._chains])
+        opts = ServerOpts(int(slots), MODES[mode] if isinstance(mode, str) else int(mode),
+                          int(partitions), 0, int(mem_budget))
+        h = ctypes.c_void_p()
+        _check(lib.fw_server_create(arr, len(self._chains), ctypes.byref(opts), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def submit(self, chain: int, src_ip, dst_ip, sport, dport, proto, out_idx, out_act) -> int:
+        arrays = (src_ip, dst_ip, sport, dport, proto, out_idx, out_act)
+        for a in arrays:
+            if not (isinstance(a, np.ndarray) and a.flags.c_contiguous):
+                raise TypeError("server buffers must be C-contiguous numpy arrays")
+        n = int(src_ip.shape[0])
+        pk = HostPackets(*(a.ctypes.data for a in arrays[:5]))
+        t = ctypes.c_uint64(0)
+        _check(load_library().fw_server_submit(self._h, int(chain), ctypes.byref(pk), n,
+                                               out_idx.ctypes.data, out_act.ctypes.data,
+                                               ctypes.byref(t)))
+        self._keep[t.value] = arrays
+        return int(t.value)
+
+    def wait(self, ticket: int):
+        times = RequestTimes()
+        try:
+            _check(load_library().fw_server_wait(self._h, int(ticket), ctypes.byref(times)))
+        finally:
+            self._keep.pop(int(ticket), None)
+        return times.submit, times.admit, times.done
+
+    def replay(self, arrival_s, chain, offset, n, pool, out_idx, out_act):
+        """Replay an arrival trace (fw_server_replay); returns an (n_req, 3) array of
+        (scheduled arrival, admit, done) times in seconds."""
+        arr = np.ascontiguousarray(arrival_s, dtype=np.float64)
+        ch = np.ascontiguousarray(chain, dtype=np.uint32)
+        off = np.ascontiguousarray(offset, dtype=np.uint64)
+        cnt = np.ascontiguousarray(n, dtype=np.uint64)
+        pk = HostPackets(*(np.asarray(a).ctypes.data for a in pool))
+        times = np.zeros((len(arr), 3), dtype=np.float64)
+        _check(load_library().fw_server_replay(self._h, len(arr), arr.ctypes.data, ch.ctypes.data,
+                                               off.ctypes.data, cnt.ctypes.data, ctypes.byref(pk),
+                                               out_idx.ctypes.data, out_act.ctypes.data,
+                                               times.ctypes.data))
+        return times
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(load_library().fw_server_destroy(self._h))
+            self._h = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

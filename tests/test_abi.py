@@ -55,7 +55,10 @@ def _c_layout(tmp_path, structs):
 
 def test_struct_layouts_match_header(fw, tmp_path):
     structs = {"fw_packets": fw.Packets, "fw_classify_opts": fw.ClassifyOpts,
-               "fw_index_opts": fw.IndexOpts, "fw_index_stats": fw.IndexStats}
+               "fw_index_opts": fw.IndexOpts, "fw_index_stats": fw.IndexStats,
+               "fw_server_opts": fw.ServerOpts, "fw_host_packets": fw.HostPackets,
+               "fw_request_times": fw.RequestTimes, "fw_chain_batch": fw.ChainBatch,
+               "fw_multi_opts": fw.MultiOpts}
     c = _c_layout(tmp_path, {k: [f for f, _ in v._fields_] for k, v in structs.items()} |
                   {"fw_rule": [n for n in fw.RULE_DTYPE.names if n != "_pad"]})
     for name, cls in structs.items():
@@ -105,3 +108,14 @@ def test_argument_errors(fw):
     assert lib.fw_build_learned_index(None, None, None) == fw.E_INVAL
     assert lib.fw_index_lookup(None, None, 0, None, 0, None) == fw.E_INVAL
     assert lib.fw_index_export(None, 0, None, 0, None) == fw.E_INVAL
+    out = ctypes.c_void_p()
+    assert lib.fw_server_create(None, 0, None, ctypes.byref(out)) == fw.E_INVAL
+    assert out.value is None
+    assert lib.fw_server_submit(None, 0, None, 0, None, None, None) == fw.E_INVAL
+    assert lib.fw_server_wait(None, 1, None) == fw.E_INVAL
+    assert lib.fw_server_destroy(None) == fw.OK
+    assert lib.fw_server_replay(None, 0, None, None, None, None, None, None, None, None) == fw.E_INVAL
+    bad = (fw.ChainBatch * 1)()
+    assert lib.fw_classify_multi(bad, 1, None) == fw.E_INVAL       # NULL ruleset
+    assert lib.fw_classify_multi(None, 0, None) == fw.OK           # nothing to do
+    assert lib.fw_autotune_multi(None, 3, None, None, None) == fw.E_INVAL

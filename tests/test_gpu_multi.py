@@ -1,0 +1,79 @@
+"""Many chains in one persistent launch: every chain bit-exact against the oracle."""
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import gen
+from tests.gpu_util import fwmod, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(scale, seed=1, extra_edge=True):
+    import torch
+    fw = fwmod()
+    work = gen.multichain_workload(seed=seed, scale=scale)
+    if extra_edge:
+        work.append((gen.make_rules(0, 5), gen.make_packets(gen.make_rules(3, 6), 300, 5)))
+        work.append((gen.make_rules(50, 7), gen.make_packets(gen.make_rules(50, 7), 1, 7)))
+        empty = gen.make_packets(gen.make_rules(3, 8), 1, 8).subset(slice(0, 0))
+        work.append((gen.make_rules(20, 9), empty))
+    items, rss = [], []
+    for rules, pk in work:
+        rs = fw.Ruleset(rules)
+        rss.append(rs)
+        n = len(pk)
+        dp = fw.DevicePackets.from_host(pk) if n else fw.DevicePackets.from_host(
+            gen.make_packets(rules if len(rules) else gen.make_rules(1, 1), 1, 1)).slice(0, 0)
+        items.append((rs, dp, torch.full((max(n, 1),), 7, dtype=torch.int32, device="cuda")[:n],
+                      torch.full((max(n, 1),), 9, dtype=torch.uint8, device="cuda")[:n]))
+    torch.cuda.synchronize()
+    return work, items, rss
+
+
+def _check(work, items, what):
+    import torch
+    torch.cuda.synchronize()
+    for c, ((rules, pk), (_, _, oi, oa)) in enumerate(zip(work, items)):
+        want_i, want_a = oracle.classify(rules, pk, threads=8)
+        np.testing.assert_array_equal(oi.cpu().numpy(), want_i, err_msg=f"{what} chain {c} idx")
+        np.testing.assert_array_equal(oa.cpu().numpy(), want_a, err_msg=f"{what} chain {c} act")
+
+
+@pytest.mark.parametrize("placement,tile", [(1, 0), (2, 256), (2, 1024)])
+@pytest.mark.parametrize("K", [1, 2, 4])
+def test_every_configuration(K, placement, tile):
+    fw = fwmod()
+    work, items, rss = _setup(scale=0.02)
+    say(f"multi K={K} placement={placement} tile={tile} chains={len(items)}")
+    for _, _, oi, oa in items:
+        oi.fill_(7)
+        oa.fill_(9)
+    fw.classify_multi(items, packets_per_lane=K, placement=placement, rule_tile=tile)
+    _check(work, items, f"K={K} placement={placement} tile={tile}")
+    for rs in rss:
+        rs.close()
+
+
+def test_autotuned_full_shape_sampled():
+    """64 chains at full batch sizes (log-uniform 4,096..1,048,576 packets); a sample per chain."""
+    import torch
+    fw = fwmod()
+    work, items, rss = _setup(scale=1.0, seed=2, extra_edge=False)
+    say(f"multi autotune over {sum(len(p) for _, p in work)} packets")
+    best, ms = fw.autotune_multi(items)
+    say(f"  best {best} {ms:.3f} ms")
+    assert best["packets_per_lane"] in (1, 2, 4) and best["placement"] in (1, 2)
+    for _, _, oi, oa in items:
+        oi.fill_(7)
+    fw.classify_multi(items)                    # tuned options
+    torch.cuda.synchronize()
+    rng = np.random.Generator(np.random.PCG64(3))
+    for c, ((rules, pk), (_, _, oi, oa)) in enumerate(zip(work, items)):
+        sel = np.sort(rng.choice(len(pk), min(len(pk), 2000), replace=False))
+        want_i, want_a = oracle.classify(rules, pk.subset(sel), threads=8)
+        np.testing.assert_array_equal(oi.cpu().numpy()[sel], want_i, err_msg=f"chain {c}")
+        np.testing.assert_array_equal(oa.cpu().numpy()[sel], want_a, err_msg=f"chain {c}")
+    for rs in rss:
+        rs.close()
