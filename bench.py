@@ -37,6 +37,37 @@ BYTES_PER_PACKET = 13 + 5          # 5-tuple in (4+4+2+2+1), index + action out 
 RECORD_BYTES = 32                  # one compiled rule record
 
 
+def kernel_sources_sha256() -> str:
+    """Hash of every .hip and .h kernel source (name + bytes, sorted)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1312_4188_amd", "csrc")
+    for p in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h"))):
+        h.update(os.path.basename(p).encode())
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def committed_traffic(workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or {} when
+    that summary is for another workload or the kernels changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.txt")
+    if not os.path.exists(path):
+        return {}
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#") or ":" not in line:
+                continue
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return {}
+    return {k.split(".")[0]: float(v) for k, v in vals.items() if k.endswith(".traffic_bytes")}
+
+
 def learned_work(rs, pk, idx, hidden: int = 32):
     """Exact algorithmic work of the learned path for every packet of the batch.
 
@@ -116,6 +147,77 @@ def closed_loop_latency(rs, dp, mode_kw, seed: int, n_batches: int, stream):
     return float(np.percentile(lat, 50) * 1e6), float(np.percentile(lat, 99) * 1e6)
 
 
+def serving_leg(seed: int, n_req: int, loads, log_fn):
+    """Open-loop serving: 3 resident chains, Poisson arrivals of log-uniform batches.
+
+    The same trace of request sizes and chains is replayed at each offered
+    load (a fraction of the saturated throughput measured first), through the
+    native load generator; latency is done - scheduled arrival.
+    """
+    import torch
+    from synth import gen
+    from paper_1312_4188_amd import fw
+    chains = gen.serving_chains(seed)
+    rsets = [fw.Ruleset(c) for c in chains]
+    build = []
+    for rs in rsets:
+        t0 = time.perf_counter()
+        st = rs.build_learned_index(seed=seed)
+        build.append({"rules": rs.n_rules, "build_s": time.perf_counter() - t0,
+                      "err_mean": st["err_mean"], "boundaries": st["n_boundaries"]})
+    _, sizes, chain = gen.serving_arrivals(seed, n_req, 1.0, n_chains=len(chains))
+    sizes = (sizes + 15) // 16 * 16                     # 16-byte aligned slices
+    offset = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.uint64)
+    total = int(sizes.sum())
+
+    def pinned(n, dt):
+        t = torch.empty(n, dtype=dt, pin_memory=True)
+        return t, t.numpy()
+    keep, pool = [], []
+    for n_bytes, dt, field in ((4, torch.int32, "src_ip"), (4, torch.int32, "dst_ip"),
+                               (2, torch.int16, "sport"), (2, torch.int16, "dport"),
+                               (1, torch.uint8, "proto")):
+        t, a = pinned(total, dt)
+        keep.append(t)
+        pool.append(a)
+    for k in range(n_req):
+        pk = gen.make_packets(chains[chain[k]], int(sizes[k]), seed * 7919 + k)
+        o, e = int(offset[k]), int(offset[k] + sizes[k])
+        pool[0][o:e] = pk.src_ip.view(np.int32)
+        pool[1][o:e] = pk.dst_ip.view(np.int32)
+        pool[2][o:e] = pk.sport.view(np.int16)
+        pool[3][o:e] = pk.dport.view(np.int16)
+        pool[4][o:e] = pk.proto
+    ti, out_i = pinned(total, torch.int32)
+    ta, out_a = pinned(total, torch.uint8)
+    out = {"chains": build, "requests": n_req, "packets": total, "modes": {}}
+    mean_batch = total / n_req
+    for mode in ("auto", "packet_split"):
+        with fw.Server(rsets, slots=8, mode=mode) as sv:
+            zero = np.zeros(n_req)
+            sv.replay(zero[:32], chain[:32], offset[:32], sizes[:32], pool, out_i, out_a)
+            t = sv.replay(zero, chain, offset, sizes, pool, out_i, out_a)
+            peak = total / (t[:, 2].max() - t[:, 0].min()) / 1e6
+            res = {"peak_mpps": peak, "loads": []}
+            for frac in loads:
+                rate = frac * peak * 1e6 / mean_batch          # requests per second
+                rng = np.random.Generator(np.random.PCG64(seed + int(frac * 1000)))
+                arr = np.cumsum(rng.exponential(1.0 / rate, n_req))
+                t = sv.replay(arr, chain, offset, sizes, pool, out_i, out_a)
+                lat = (t[:, 2] - t[:, 0]) * 1e6
+                span = t[:, 2].max() - t[:, 0].min()
+                res["loads"].append({"offered_frac": frac, "offered_mpps": frac * peak,
+                                     "achieved_mpps": total / span / 1e6,
+                                     "p50_us": float(np.percentile(lat, 50)),
+                                     "p99_us": float(np.percentile(lat, 99))})
+                log_fn(f"  serving {mode} load {frac:.0%}: p50 {res['loads'][-1]['p50_us']:.0f} us "
+                       f"p99 {res['loads'][-1]['p99_us']:.0f} us")
+            out["modes"]["learned" if mode == "auto" else mode] = res
+    for rs in rsets:
+        rs.close()
+    return out
+
+
 def cpu_baseline(rules, pk, n_sample: int):
     """The CPU oracle, as it stands, on a bounded sample of the same batch."""
     import oracle
@@ -141,6 +243,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--modes", default="",
                     help="comma list of modes to time (default: all); the first is the headline")
+    ap.add_argument("--serving-requests", type=int, default=600,
+                    help="requests per offered load in the serving leg (0 = skip it)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (for scaling HBM counters)")
     args = ap.parse_args()
@@ -174,7 +278,11 @@ def main():
     modes = {"learned": (rs, dict(mode="learned")),
              "learned_binary_search": (rs, dict(mode="learned", lookup=1)),
              "learned_untrained": (rs_un, dict(mode="learned")),
+             "learned_k1": (rs, dict(mode="learned", packets_per_lane=1)),
+             "learned_k4": (rs, dict(mode="learned", packets_per_lane=4)),
              "packet_split": (rs, dict(mode="packet_split")),
+             "packet_split_k1": (rs, dict(mode="packet_split", packets_per_lane=1)),
+             "packet_split_k2": (rs, dict(mode="packet_split", packets_per_lane=2)),
              "rule_split_p16": (rs, dict(mode="rule_split", partitions=16)),
              "hybrid_p16": (rs, dict(mode="hybrid", partitions=16))}
     if args.modes:
@@ -220,9 +328,10 @@ def main():
     ms = results[head]["ms"]
     work = learned_work(rs, pk, ref)
     achieved_tops = work["lane_ops"] / (ms * 1e-3) / 1e12
+    traffic = committed_traffic(args.workload)
     roofline = {"bound": "alu", "achieved": achieved_tops, "peak": VALU_INT32_PEAK_TOPS,
                 "unit": "Tops/s", "frac": achieved_tops / VALU_INT32_PEAK_TOPS,
-                "traffic": None, "kernel": "k_learned<true,true>",
+                "traffic": traffic.get("k_learned"), "kernel": "k_learned<true,2>",
                 "algorithmic_lane_ops": work["lane_ops"], "algorithmic_bytes": work["bytes"],
                 "hbm_gbs": work["bytes"] / (ms * 1e-3) / 1e9,
                 "hbm_frac": work["bytes"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
@@ -231,6 +340,7 @@ def main():
         scan_ms = results["packet_split"]["ms"]
         scan_ops = checks * OPS_PER_CHECK
         scan_roofline = {"bound": "alu", "kernel": "k_packet_split<4>",
+                         "traffic": traffic.get("k_packet_split"),
                          "achieved": scan_ops / (scan_ms * 1e-3) / 1e12,
                          "frac": scan_ops / (scan_ms * 1e-3) / 1e12 / VALU_INT32_PEAK_TOPS,
                          "hbm_gbs": n * BYTES_PER_PACKET / (scan_ms * 1e-3) / 1e9}
@@ -242,6 +352,12 @@ def main():
         torch.cuda.synchronize()
         b.copy_(a)
         torch.cuda.synchronize()
+
+    serving = None
+    if args.serving_requests > 0:
+        log("serving leg")
+        serving = serving_leg(args.seed, args.serving_requests,
+                              (0.1, 0.3, 0.5, 0.7, 0.9, 1.0, 1.2), log)
 
     cpu = None
     if not args.no_cpu:
@@ -264,7 +380,8 @@ def main():
         "modes": results, "latency": latency,
         "scan_rule_checks": checks, "learned_candidate_checks": work["candidate_checks"],
         "index": index_stats, "index_untrained": untrained_stats,
-        "roofline": roofline, "scan_roofline": scan_roofline, "cpu_baseline": cpu,
+        "roofline": roofline, "scan_roofline": scan_roofline, "serving": serving,
+        "cpu_baseline": cpu,
     }
     rs.close()
     rs_un.close()

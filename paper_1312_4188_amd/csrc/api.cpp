@@ -218,8 +218,8 @@ fw_status fw_classify_ex(const fw_ruleset* rs, const fw_packets* pk, size_t n,
                               rs->default_action, stream);
             break;
         case FW_MODE_LEARNED:
-            return classify_learned(rs->index, rs->d_rules, rs->n_rules, rs->default_action,
-                                    pd, n, out_rule_idx, out_action, o.lookup, stream,
+            return classify_learned(rs->index, rs->default_action, pd, n, out_rule_idx,
+                                    out_action, o.lookup, o.packets_per_lane, stream,
                                     o.window_misses);
         default:
             return fail(FW_E_INVAL, "unknown mode %u", mode);

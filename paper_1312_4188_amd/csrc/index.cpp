@@ -29,7 +29,7 @@
 namespace fw {
 
 struct LearnedIndex {
-    uint32_t M = 0, E = 0, H = 0, stride2 = 0;
+    uint32_t M = 0, E = 0, H = 0;
     uint32_t nG = 0;
     uint64_t nL = 0;
     uint32_t* d_B = nullptr;
@@ -104,6 +104,12 @@ void init_network(float* p, uint32_t H, SplitMix& rng) {
         p[2 * H + k] = float(rng.normal() / std::sqrt(double(H)));
     }
     p[3 * H] = 0.0f;
+}
+
+// Slot of parameter k of the training layout [w1 (H), b1 (H), w2 (H), b2] in
+// the inference layout of 32-slot segments.
+uint32_t infer_slot(uint32_t k, uint32_t H) {
+    return k < 3 * H ? (k / H) * 32u + k % H : 96u;
 }
 
 bool full_match_all(const RuleRec& q) {
@@ -235,10 +241,8 @@ LookupArgs args_of(const LearnedIndex* ix, uint32_t use_net) {
     a.M = ix->M;
     a.w1 = ix->d_w1;
     a.w2 = ix->d_w2;
-    a.stride2 = ix->stride2;
     a.meta = ix->d_meta;
     a.E = ix->E;
-    a.H = ix->H;
     a.off = ix->d_off;
     a.L = ix->d_L;
     a.G = ix->d_G;
@@ -360,13 +364,12 @@ fw_status build_index(const fw_rule* rules, const RuleRec* recs, uint32_t n_rule
     const uint32_t M = ix->M, E = o.experts, H = o.hidden, P = 3 * H + 1;
     ix->E = E;
     ix->H = H;
-    ix->stride2 = (P + 7u) & ~7u;
 
     // device footprint of what the index keeps
     const uint64_t keep = uint64_t(M) * 4 + (uint64_t(M) + 1) * 4 + ix->nL * sizeof(RuleRec) +
                           uint64_t(ix->nG ? ix->nG : 1) * sizeof(RuleRec) +
                           (uint64_t(ix->nG) + kPairPadding) * 8 + kGradCols * 4 +
-                          uint64_t(E) * ix->stride2 * 2 + uint64_t(E) * sizeof(ExpertMeta) + 8;
+                          uint64_t(E) * kInferStride * 2 + uint64_t(E) * sizeof(ExpertMeta) + 8;
     if (o.mem_budget && keep > o.mem_budget) {
         delete ix;
         return fail(FW_E_NOMEM, "learned index needs %llu bytes, budget is %llu",
@@ -386,7 +389,7 @@ fw_status build_index(const fw_rule* rules, const RuleRec* recs, uint32_t n_rule
         (e = dalloc(&ix->d_G, ix->nG, &bytes)) != hipSuccess ||
         (e = dalloc(&ix->d_Gpairs, size_t(ix->nG) + kPairPadding, &bytes)) != hipSuccess ||
         (e = dalloc(&ix->d_w1, kGradCols, &bytes)) != hipSuccess ||
-        (e = dalloc(&ix->d_w2, size_t(E) * ix->stride2, &bytes)) != hipSuccess ||
+        (e = dalloc(&ix->d_w2, size_t(E) * kInferStride, &bytes)) != hipSuccess ||
         (e = dalloc(&ix->d_meta, E, &bytes)) != hipSuccess ||
         (e = dalloc(&ix->d_miss, 1, &bytes)) != hipSuccess)
         return bail(e, "allocating the learned index");
@@ -472,14 +475,14 @@ fw_status build_index(const fw_rule* rules, const RuleRec* recs, uint32_t n_rule
         if (e != hipSuccess) return fail_train(e, "training stage 1");
     }
     // quantise to bf16; the lookup uses the widened bf16 values
-    std::vector<float> w1q(kGradCols, 0.0f);
-    for (uint32_t k = 0; k < P; ++k) w1q[k] = from_bf16(to_bf16(w1[k]));
+    std::vector<float> w1q(kGradCols, 0.0f);   // inference layout, see kInferStride
+    for (uint32_t k = 0; k < P; ++k) w1q[infer_slot(k, H)] = from_bf16(to_bf16(w1[k]));
     if ((e = upload(ix->d_w1, w1q, s)) != hipSuccess)
         return fail_train(e, "uploading stage-1 weights");
 
     // ---- route every key with the quantised stage 1
     std::vector<uint32_t> route(N);
-    if ((e = launch_route(ix->d_w1, H, E, d_keys, N, d_route, s)) != hipSuccess ||
+    if ((e = launch_route(ix->d_w1, E, d_keys, N, d_route, s)) != hipSuccess ||
         (e = hipMemcpyAsync(route.data(), d_route, sizeof(uint32_t) * N, hipMemcpyDeviceToHost,
                             s)) != hipSuccess ||
         (e = hipStreamSynchronize(s)) != hipSuccess)
@@ -549,13 +552,13 @@ fw_status build_index(const fw_rule* rules, const RuleRec* recs, uint32_t n_rule
         if (e != hipSuccess) return fail_train(e, "training stage 2");
         for (float x : l2) loss2 += x;
     }
-    std::vector<uint16_t> w2q(size_t(E) * ix->stride2, 0);
+    std::vector<uint16_t> w2q(size_t(E) * kInferStride, 0);
     ix->weights.assign(size_t(P) * (E + 1), 0.0f);
-    for (uint32_t k = 0; k < P; ++k) ix->weights[k] = w1q[k];
+    for (uint32_t k = 0; k < P; ++k) ix->weights[k] = w1q[infer_slot(k, H)];
     for (uint32_t ex = 0; ex < E; ++ex)
         for (uint32_t k = 0; k < P; ++k) {
             const uint16_t b = to_bf16(w2[size_t(ex) * P + k]);
-            w2q[size_t(ex) * ix->stride2 + k] = b;
+            w2q[size_t(ex) * kInferStride + infer_slot(k, H)] = b;
             ix->weights[size_t(ex + 1) * P + k] = from_bf16(b);
         }
     if ((e = upload(ix->d_w2, w2q, s)) != hipSuccess ||
@@ -603,12 +606,10 @@ fw_status build_index(const fw_rule* rules, const RuleRec* recs, uint32_t n_rule
     return FW_OK;
 }
 
-fw_status classify_learned(const LearnedIndex* ix, const RuleRec* rules, uint32_t n_rules,
-                           uint8_t default_action, PacketsDev pk, size_t n, int32_t* out_idx,
-                           uint8_t* out_act, uint32_t lookup, hipStream_t stream,
+fw_status classify_learned(const LearnedIndex* ix, uint8_t default_action, PacketsDev pk,
+                           size_t n, int32_t* out_idx, uint8_t* out_act, uint32_t lookup,
+                           uint32_t packets_per_lane, hipStream_t stream,
                            uint64_t* window_misses) {
-    (void)rules;
-    (void)n_rules;
     if (lookup > 1) return fail(FW_E_INVAL, "lookup must be 0 or 1");
     LookupArgs a = args_of(ix, lookup == 0 ? 1u : 0u);
     hipError_t e = hipSuccess;
@@ -617,7 +618,8 @@ fw_status classify_learned(const LearnedIndex* ix, const RuleRec* rules, uint32_
         if (e != hipSuccess) return hip_fail(e, "clearing the miss counter");
         a.miss = ix->d_miss;
     }
-    e = launch_learned(a, pk, n, out_idx, out_act, default_action, nullptr, nullptr, stream);
+    e = launch_learned(a, pk, n, out_idx, out_act, default_action, nullptr, nullptr,
+                       packets_per_lane, stream);
     if (e != hipSuccess) return hip_fail(e, "learned lookup launch");
     if (window_misses) {
         unsigned long long v = 0;
@@ -633,7 +635,7 @@ fw_status index_lookup(const LearnedIndex* ix, const uint32_t* keys, size_t n,
                        int32_t* out_interval, uint32_t lookup, hipStream_t stream) {
     const LookupArgs a = args_of(ix, lookup == 0 ? 1u : 0u);
     const hipError_t e = launch_learned(a, PacketsDev{}, n, nullptr, nullptr, 0, keys,
-                                        out_interval, stream);
+                                        out_interval, 1, stream);
     if (e != hipSuccess) return hip_fail(e, "interval lookup launch");
     return FW_OK;
 }

@@ -18,9 +18,9 @@ struct LearnedIndex;
 fw_status build_index(const fw_rule* rules, const RuleRec* recs, uint32_t n_rules,
                       const fw_index_opts& opts, fw_index_stats* stats, LearnedIndex** out);
 void destroy_index(LearnedIndex* ix);
-fw_status classify_learned(const LearnedIndex* ix, const RuleRec* rules, uint32_t n_rules,
-                           uint8_t default_action, PacketsDev pk, size_t n, int32_t* out_idx,
-                           uint8_t* out_act, uint32_t lookup, hipStream_t stream,
+fw_status classify_learned(const LearnedIndex* ix, uint8_t default_action, PacketsDev pk,
+                           size_t n, int32_t* out_idx, uint8_t* out_act, uint32_t lookup,
+                           uint32_t packets_per_lane, hipStream_t stream,
                            uint64_t* window_misses);
 fw_status index_lookup(const LearnedIndex* ix, const uint32_t* keys, size_t n,
                        int32_t* out_interval, uint32_t lookup, hipStream_t stream);
@@ -47,16 +47,18 @@ constexpr uint32_t kMaxHidden = 32;
 constexpr uint32_t kMaxExperts = 256;
 constexpr uint32_t kGradCols = 128;      // padded column count of the gradient product
 constexpr uint32_t kNoExpert = 0xFFFFFFFFu;
+// Inference layout of one network: [w1][b1][w2][b2] in 32-slot segments,
+// padded to 104 entries (a multiple of 8); hidden units past H are zero.
+constexpr uint32_t kInferStride = 104;
 
 // Everything the lookup kernel reads.
 struct LookupArgs {
     const uint32_t* B;        // M boundaries
     uint32_t M;
-    const float* w1;          // stage 1, 3H+1 floats (bf16 values, widened)
-    const uint16_t* w2;       // stage 2, E experts x stride2 bf16
-    uint32_t stride2;         // per-expert stride in w2 (multiple of 8)
+    const float* w1;          // stage 1 in the inference layout (bf16 values, widened)
+    const uint16_t* w2;       // stage 2, E experts x kInferStride bf16
     const ExpertMeta* meta;   // E
-    uint32_t E, H;
+    uint32_t E;
     const uint32_t* off;      // M + 1 per-interval list offsets
     const RuleRec* L;         // per-interval candidate records
     const RuleRec* G;         // global (destination-wildcard) candidate records
@@ -79,13 +81,13 @@ hipError_t launch_grad_fp32(const float* at, size_t n_pad, const uint32_t* seg, 
                             uint32_t H, float* grad, float* loss, hipStream_t s);
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, size_t count, float lr,
                        float b1, float b2, float eps, float bc1, float bc2, hipStream_t s);
-hipError_t launch_route(const float* w1, uint32_t H, uint32_t E, const uint32_t* keys, size_t n,
+hipError_t launch_route(const float* w1, uint32_t E, const uint32_t* keys, size_t n,
                         uint32_t* expert, hipStream_t s);
 hipError_t launch_err_bound(const LookupArgs& a, const uint32_t* keys, const int32_t* pos,
                             size_t n, uint32_t* err, hipStream_t s);
 hipError_t launch_learned(const LookupArgs& a, PacketsDev pk, size_t n, int32_t* out_idx,
                           uint8_t* out_act, uint32_t dflt, const uint32_t* keys,
-                          int32_t* out_interval, hipStream_t s);
+                          int32_t* out_interval, uint32_t packets_per_lane, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 size_t learned_lds_bytes(const LookupArgs& a, bool b_in_lds);
 

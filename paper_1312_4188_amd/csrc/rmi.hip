@@ -184,24 +184,42 @@ __global__ void k_fill(uint32_t* p, size_t n, uint32_t v) {
 }
 
 // ------------------------------------------------------------------ inference
-// Stage 1 (fp32 copy of the bf16 weights): u = x / 2^32 -> expert index.
-__device__ __forceinline__ uint32_t route(const float* w1, uint32_t H, uint32_t E, uint32_t x) {
+// Inference layout of one network: four 32-slot segments [w1][b1][w2][b2],
+// kInferStride entries in all; hidden units past H carry zero weights and
+// add nothing.  Stage 1 is kept as fp32 (the bf16 values widened), stage 2 as
+// bf16.  Every routine below is shared by the error-bound kernel and the
+// lookup kernels, so the recorded error bounds describe exactly the lookup's
+// arithmetic.
+constexpr uint32_t kSeg = 32;
+
+// Stage 1: u = x / 2^32 -> expert index in [0, E).
+__device__ __forceinline__ uint32_t route(const float* w1, uint32_t E, uint32_t x) {
     const float u = float(x) * 0x1p-32f;
-    float y = w1[3 * H];
-    for (uint32_t k = 0; k < H; ++k) y = fmaf(w1[2 * H + k], fmaxf(fmaf(w1[k], u, w1[H + k]), 0.0f), y);
+    float y = w1[3 * kSeg];
+#pragma unroll
+    for (uint32_t k = 0; k < kSeg; ++k)
+        y = fmaf(w1[2 * kSeg + k], fmaxf(fmaf(w1[k], u, w1[kSeg + k]), 0.0f), y);
     const float s = y * float(E);
     // NaN and negatives go to expert 0, overflow to the last expert
     return s >= 1.0f ? (s < float(E) ? uint32_t(s) : E - 1u) : 0u;
 }
 
-// Stage 2 (bf16 weights): position estimate of x inside expert e's range.
-__device__ __forceinline__ int32_t position(const uint16_t* w2e, uint32_t H,
-                                            const ExpertMeta& m, uint32_t x) {
+// Stage 2 (bf16 weights, read 8 at a time): position estimate of x inside
+// expert e's range of positions.
+__device__ __forceinline__ int32_t position(const uint16_t* w2e, const ExpertMeta& m,
+                                            uint32_t x) {
     const float v = x >= m.key_lo ? fminf(float(x - m.key_lo) * m.inv_span, 1.0f) : 0.0f;
-    float y = bf16_to_f32(w2e[3 * H]);
-    for (uint32_t k = 0; k < H; ++k) {
-        const float z = fmaf(bf16_to_f32(w2e[k]), v, bf16_to_f32(w2e[H + k]));
-        y = fmaf(bf16_to_f32(w2e[2 * H + k]), fmaxf(z, 0.0f), y);
+    float y = bf16_to_f32(w2e[3 * kSeg]);
+#pragma unroll
+    for (uint32_t c = 0; c < kSeg; c += 8) {
+        const u16x8 a = *reinterpret_cast<const u16x8*>(w2e + c);
+        const u16x8 b = *reinterpret_cast<const u16x8*>(w2e + kSeg + c);
+        const u16x8 o = *reinterpret_cast<const u16x8*>(w2e + 2 * kSeg + c);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const float z = fmaf(bf16_to_f32(a[i]), v, bf16_to_f32(b[i]));
+            y = fmaf(bf16_to_f32(o[i]), fmaxf(z, 0.0f), y);
+        }
     }
     const float q = fminf(fmaxf(y * m.pos_span, 0.0f), m.pos_span);  // NaN -> 0
     return m.pos_lo + int32_t(rintf(q));
@@ -223,13 +241,12 @@ __device__ __forceinline__ uint32_t search_le(const uint32_t* B, uint32_t lo, ui
 // Interval of x: the window [p - err, p + err] of the predicted position first,
 // checked by B[j] <= x < B[j+1]; a miss falls back to the full range.
 __device__ __forceinline__ uint32_t locate(const uint32_t* B, uint32_t M, const float* w1,
-                                           const uint16_t* w2, uint32_t stride2,
-                                           const ExpertMeta* meta, uint32_t E, uint32_t H,
+                                           const uint16_t* w2, const ExpertMeta* meta, uint32_t E,
                                            uint32_t use_net, uint32_t x, bool* miss) {
     if (use_net) {
-        const uint32_t e = route(w1, H, E, x);
+        const uint32_t e = route(w1, E, x);
         const ExpertMeta m = meta[e];
-        const int32_t p = position(w2 + size_t(e) * stride2, H, m, x);
+        const int32_t p = position(w2 + size_t(e) * kInferStride, m, x);
         const int64_t lo = int64_t(p) - int64_t(m.err), hi = int64_t(p) + int64_t(m.err);
         const uint32_t l = uint32_t(lo < 0 ? 0 : (lo >= int64_t(M) ? M - 1 : lo));
         const uint32_t h = uint32_t(hi < int64_t(l) ? l : (hi >= int64_t(M) ? M - 1 : hi));
@@ -247,126 +264,147 @@ __device__ __forceinline__ uint32_t locate(const uint32_t* B, uint32_t M, const 
     return search_le(B, 0, M - 1u, x);
 }
 
-__global__ void k_route(const float* __restrict__ w1, uint32_t H, uint32_t E,
-                        const uint32_t* __restrict__ keys, size_t n, uint32_t* __restrict__ out) {
+__global__ void k_route(const float* __restrict__ w1, uint32_t E, const uint32_t* __restrict__ keys,
+                        size_t n, uint32_t* __restrict__ out) {
     const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = route(w1, H, E, keys[i]);
+    if (i < n) out[i] = route(w1, E, keys[i]);
 }
 
-// Per-expert maximum |predicted - true position| over the training keys,
-// with exactly the arithmetic the lookup kernel uses.
+// Per-expert maximum |predicted - true position| over the training keys.
 __global__ void k_err_bound(LookupArgs a, const uint32_t* __restrict__ keys,
                             const int32_t* __restrict__ pos, size_t n, uint32_t* __restrict__ err) {
     const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint32_t x = keys[i];
-    const uint32_t e = route(a.w1, a.H, a.E, x);
-    const int32_t p = position(a.w2 + size_t(e) * a.stride2, a.H, a.meta[e], x);
+    const uint32_t e = route(a.w1, a.E, x);
+    const int32_t p = position(a.w2 + size_t(e) * kInferStride, a.meta[e], x);
     const int32_t d = p - pos[i];
     atomicMax(err + e, uint32_t(d < 0 ? -d : d));
 }
 
 // ------------------------------------------------------------------ lookup + candidate scan
-// Persistent work-groups of 16 waves.  Each stages the stage-1 weights (fp32),
-// the experts' records and bf16 weights, and (when it fits) the boundary
-// array into LDS once, then its waves stride over 64-packet tiles:
-//   1. locate the destination interval j (network + window, else full search);
+// Persistent work-groups of 16 waves.  Each stages the stage-1 weights, the
+// experts' records and bf16 weights, and (when it fits) the boundary array
+// into LDS once; its waves then stride over tiles of 64*K packets:
+//   1. locate each packet's destination interval j (network + window, else a
+//      full binary search);
 //   2. scan j's own candidate list per lane (ascending, stop at the first match);
-//   3. scan the shared destination-wildcard list with wave-uniform records,
-//      dropping lanes whose best index is already below the current record's;
-//   4. write the index and action.
-// With CLASSIFY false only step 1 runs and j is written.
+//   3. scan the shared destination-wildcard list with the packet-split wave
+//      scan (source tested first; the destination test is implied);
+//   4. keep the smaller of the two partial first matches and write it.
 constexpr uint32_t kLearnedBlock = 1024;
-constexpr uint32_t kW1Slots = 3 * kMaxHidden + 4;   // floats reserved for stage 1
+constexpr uint32_t kLearnedK = 2;     // default packets per lane in the classify kernel
 
-__host__ __device__ inline size_t lds_layout(uint32_t E, uint32_t stride2, uint32_t M, bool b_lds,
-                                             size_t* off_meta, size_t* off_w2, size_t* off_b) {
-    size_t o = kW1Slots * sizeof(float);
+__host__ __device__ inline size_t lds_layout(uint32_t E, uint32_t M, bool b_lds, size_t* off_meta,
+                                             size_t* off_w2, size_t* off_b) {
+    size_t o = kInferStride * sizeof(float);
     *off_meta = o;
     o += size_t(E) * sizeof(ExpertMeta);
     *off_w2 = o;
-    o += size_t(E) * stride2 * sizeof(uint16_t);
+    o += size_t(E) * kInferStride * sizeof(uint16_t);
     o = (o + 15) & ~size_t(15);
     *off_b = o;
     if (b_lds) o += size_t(M) * sizeof(uint32_t);
     return o;
 }
 
-template <bool B_LDS, bool CLASSIFY>
-__global__ __launch_bounds__(kLearnedBlock) void k_learned(LookupArgs a, PacketsDev pk, size_t n,
-                                                           int32_t* __restrict__ out_idx,
-                                                           uint8_t* __restrict__ out_act,
-                                                           uint32_t dflt,
-                                                           const uint32_t* __restrict__ keys,
-                                                           int32_t* __restrict__ out_interval) {
-    extern __shared__ __align__(16) unsigned char smem[];
+struct IndexView {
+    const float* w1;
+    const ExpertMeta* meta;
+    const uint16_t* w2;
+    const uint32_t* B;
+};
+
+template <bool B_LDS>
+__device__ __forceinline__ IndexView stage_index(const LookupArgs& a, unsigned char* smem) {
     size_t o_meta, o_w2, o_b;
-    lds_layout(a.E, a.stride2, a.M, B_LDS, &o_meta, &o_w2, &o_b);
+    lds_layout(a.E, a.M, B_LDS, &o_meta, &o_w2, &o_b);
     float* s_w1 = reinterpret_cast<float*>(smem);
     ExpertMeta* s_meta = reinterpret_cast<ExpertMeta*>(smem + o_meta);
     uint16_t* s_w2 = reinterpret_cast<uint16_t*>(smem + o_w2);
     uint32_t* s_b = reinterpret_cast<uint32_t*>(smem + o_b);
     const uint32_t tid = threadIdx.x;
-    for (uint32_t k = tid; k < 3 * a.H + 1; k += blockDim.x) s_w1[k] = a.w1[k];
+    for (uint32_t k = tid; k < kInferStride; k += blockDim.x) s_w1[k] = a.w1[k];
     for (uint32_t k = tid; k < a.E * 8u; k += blockDim.x)
         reinterpret_cast<uint32_t*>(s_meta)[k] = reinterpret_cast<const uint32_t*>(a.meta)[k];
-    for (uint32_t k = tid; k < a.E * a.stride2 / 2u; k += blockDim.x)
+    for (uint32_t k = tid; k < a.E * kInferStride / 2u; k += blockDim.x)
         reinterpret_cast<uint32_t*>(s_w2)[k] = reinterpret_cast<const uint32_t*>(a.w2)[k];
     if constexpr (B_LDS)
         for (uint32_t k = tid; k < a.M; k += blockDim.x) s_b[k] = a.B[k];
     __syncthreads();
-    const uint32_t* B = B_LDS ? s_b : a.B;
+    return IndexView{s_w1, s_meta, s_w2, B_LDS ? s_b : a.B};
+}
 
-    const uint32_t lane = tid & 63u;
+// With one or two packets per lane, two work-groups per CU (the LDS footprint
+// allows two): eight waves per SIMD, so at most 64 VGPRs.  Four packets per
+// lane need more registers and run one work-group per CU.
+template <bool B_LDS, int K>
+__global__ __launch_bounds__(kLearnedBlock, K >= 4 ? 4 : 8) void k_learned(LookupArgs a, PacketsDev pk, size_t n,
+                                                           int32_t* __restrict__ out_idx,
+                                                           uint8_t* __restrict__ out_act,
+                                                           uint32_t dflt) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const IndexView v = stage_index<B_LDS>(a, smem);
+    const uint32_t lane = threadIdx.x & 63u;
     const size_t waves = size_t(gridDim.x) * (blockDim.x >> 6);
-    const size_t wave0 = size_t(blockIdx.x) * (blockDim.x >> 6) + (tid >> 6);
-    for (size_t base = wave0 * 64u; base < n; base += waves * 64u) {
-        const size_t i = base + lane;
-        const bool valid = i < n;
-        const uint32_t x = valid ? (CLASSIFY ? pk.dst[i] : keys[i]) : 0u;
-        bool miss = false;
-        const uint32_t j = locate(B, a.M, s_w1, s_w2, a.stride2, s_meta, a.E, a.H, a.use_net,
-                                  x, &miss);
-        if (a.miss) {
-            const uint64_t mm = ballot(valid && miss);
-            if (lane == 0 && mm) atomicAdd(a.miss, (unsigned long long)__popcll(mm));
-        }
-        if constexpr (!CLASSIFY) {
-            if (valid) out_interval[i] = int32_t(j);
-            continue;
-        }
-        uint32_t src = 0, pp = 0, pr = 0;
-        if (valid) {
-            src = pk.src[i];
-            pp = (uint32_t(pk.sport[i]) << 16) | pk.dport[i];
-            pr = pk.proto[i];
-        }
-        uint32_t best = kNoMatch, act = dflt;
-        if (valid) {
-            const uint32_t kb = a.off[j], ke = a.off[j + 1u];
-            for (uint32_t k = kb; k < ke; ++k) {
-                const RuleRec q = a.L[k];
-                if (match_no_dst(q, src, pp, pr)) {
-                    best = q.idx;
-                    act = rule_action(q.proto);
-                    break;
+    const size_t wave0 = size_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    for (size_t base = wave0 * 64u * K; base < n; base += waves * 64u * K) {
+        WaveScan<K> w;
+        w.init(pk, base, n, dflt);
+        uint32_t lbest[K], lact[K];
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            const bool valid = w.p0 + s < n;
+            bool miss = false;
+            const uint32_t j = locate(v.B, a.M, v.w1, v.w2, v.meta, a.E, a.use_net, w.dst[s],
+                                      &miss);
+            if (a.miss) {
+                const uint64_t mm = ballot(valid && miss);
+                if (lane == 0 && mm) atomicAdd(a.miss, (unsigned long long)__popcll(mm));
+            }
+            lbest[s] = kNoMatch;
+            lact[s] = dflt;
+            if (valid) {
+                const uint32_t kb = a.off[j], ke = a.off[j + 1u];
+                for (uint32_t k = kb; k < ke; ++k) {
+                    const RuleRec q = a.L[k];
+                    if (match_no_dst(q, w.src[s], w.pp[s], w.pr[s])) {
+                        lbest[s] = q.idx;
+                        lact[s] = rule_action(q.proto);
+                        break;
+                    }
                 }
             }
         }
-        // shared list: wave-uniform records, source tested first (the
-        // destination test is implied); the two partial first matches meet
-        // in a minimum
-        WaveScan<1> w;
-        w.init_values(src, x, pp, pr, valid, dflt);
         w.template scan<FirstField::Src, true>(a.Gpairs, a.G, a.nG, 0u);
-        if (w.best[0] < best) {
-            best = w.best[0];
-            act = w.act[0];
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            if (lbest[s] < w.best[s]) {
+                w.best[s] = lbest[s];
+                w.act[s] = lact[s];
+            }
         }
-        if (valid) {
-            out_idx[i] = int32_t(best);
-            out_act[i] = uint8_t(act);
-        }
+        w.store(out_idx, out_act, n);
+    }
+}
+
+// Interval lookup only, one key per lane.
+template <bool B_LDS>
+__global__ __launch_bounds__(kLearnedBlock) void k_lookup(LookupArgs a,
+                                                          const uint32_t* __restrict__ keys,
+                                                          size_t n,
+                                                          int32_t* __restrict__ out_interval) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const IndexView v = stage_index<B_LDS>(a, smem);
+    const size_t waves = size_t(gridDim.x) * (blockDim.x >> 6);
+    const size_t wave0 = size_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    for (size_t base = wave0 * 64u; base < n; base += waves * 64u) {
+        const size_t i = base + (threadIdx.x & 63u);
+        const bool valid = i < n;
+        bool miss = false;
+        const uint32_t j = locate(v.B, a.M, v.w1, v.w2, v.meta, a.E, a.use_net,
+                                  valid ? keys[i] : 0u, &miss);
+        if (valid) out_interval[i] = int32_t(j);
     }
 }
 
@@ -375,14 +413,12 @@ inline uint32_t blocks_for(size_t n, uint32_t per) { return uint32_t((n + per - 
 struct LearnedLaunchCache {
     int device = -1;
     int cus = 0;
+    int max_lds = 0;
 };
 thread_local LearnedLaunchCache g_cache;
 
-template <bool B_LDS, bool CLASSIFY>
-hipError_t launch_learned_t(const LookupArgs& a, PacketsDev pk, size_t n, int32_t* out_idx,
-                            uint8_t* out_act, uint32_t dflt, const uint32_t* keys,
-                            int32_t* out_interval, size_t lds, hipStream_t s) {
-    auto kern = k_learned<B_LDS, CLASSIFY>;
+template <class Kern, class... Args>
+hipError_t launch_persistent(Kern kern, size_t lds, size_t tiles, hipStream_t s, Args... args) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     if (e != hipSuccess) return e;
@@ -390,13 +426,11 @@ hipError_t launch_learned_t(const LookupArgs& a, PacketsDev pk, size_t n, int32_
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kLearnedBlock, lds);
     if (e != hipSuccess) return e;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
-    const size_t tiles = (n + 63) / 64;
     const size_t want = (tiles + (kLearnedBlock / 64) - 1) / (kLearnedBlock / 64);
     size_t grid = size_t(per_cu) * size_t(g_cache.cus);
     if (grid > want) grid = want;
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(kern, dim3(uint32_t(grid)), dim3(kLearnedBlock), lds, s, a, pk, n,
-                       out_idx, out_act, dflt, keys, out_interval);
+    hipLaunchKernelGGL(kern, dim3(uint32_t(grid)), dim3(kLearnedBlock), lds, s, args...);
     return hipGetLastError();
 }
 
@@ -454,11 +488,10 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, size_t coun
     return hipGetLastError();
 }
 
-hipError_t launch_route(const float* w1, uint32_t H, uint32_t E, const uint32_t* keys, size_t n,
+hipError_t launch_route(const float* w1, uint32_t E, const uint32_t* keys, size_t n,
                         uint32_t* expert, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_route, dim3(blocks_for(n, 256)), dim3(256), 0, s, w1, H, E, keys, n,
-                       expert);
+    hipLaunchKernelGGL(k_route, dim3(blocks_for(n, 256)), dim3(256), 0, s, w1, E, keys, n, expert);
     return hipGetLastError();
 }
 
@@ -472,37 +505,46 @@ hipError_t launch_err_bound(const LookupArgs& a, const uint32_t* keys, const int
 
 size_t learned_lds_bytes(const LookupArgs& a, bool b_in_lds) {
     size_t o1, o2, o3;
-    return lds_layout(a.E, a.stride2, a.M, b_in_lds, &o1, &o2, &o3);
+    return lds_layout(a.E, a.M, b_in_lds, &o1, &o2, &o3);
 }
 
 hipError_t launch_learned(const LookupArgs& a, PacketsDev pk, size_t n, int32_t* out_idx,
                           uint8_t* out_act, uint32_t dflt, const uint32_t* keys,
-                          int32_t* out_interval, hipStream_t s) {
+                          int32_t* out_interval, uint32_t packets_per_lane, hipStream_t s) {
     if (n == 0) return hipSuccess;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     if (g_cache.device != dev) {
         e = hipDeviceGetAttribute(&g_cache.cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess)
+            e = hipDeviceGetAttribute(&g_cache.max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                                      dev);
         if (e != hipSuccess) return e;
         g_cache.device = dev;
     }
-    int max_lds = 0;
-    e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-    if (e != hipSuccess) return e;
+    // keep two work-groups of 16 waves per CU: boundaries in LDS up to 80 KiB in all
     const size_t with_b = learned_lds_bytes(a, true);
-    const bool b_lds = with_b <= size_t(max_lds) && with_b <= 80u * 1024u;
+    const bool b_lds = with_b <= size_t(g_cache.max_lds) && with_b <= 80u * 1024u;
     const size_t lds = b_lds ? with_b : learned_lds_bytes(a, false);
-    const bool classify = keys == nullptr;
-    if (b_lds)
-        return classify ? launch_learned_t<true, true>(a, pk, n, out_idx, out_act, dflt, keys,
-                                                       out_interval, lds, s)
-                        : launch_learned_t<true, false>(a, pk, n, out_idx, out_act, dflt, keys,
-                                                        out_interval, lds, s);
-    return classify ? launch_learned_t<false, true>(a, pk, n, out_idx, out_act, dflt, keys,
-                                                    out_interval, lds, s)
-                    : launch_learned_t<false, false>(a, pk, n, out_idx, out_act, dflt, keys,
-                                                     out_interval, lds, s);
+    if (keys) {
+        const size_t tiles = (n + 63) / 64;
+        return b_lds ? launch_persistent(k_lookup<true>, lds, tiles, s, a, keys, n, out_interval)
+                     : launch_persistent(k_lookup<false>, lds, tiles, s, a, keys, n, out_interval);
+    }
+    const uint32_t K = packets_per_lane ? packets_per_lane : kLearnedK;
+    const size_t tiles = (n + 64 * K - 1) / (64 * K);
+#define FW_LEARNED(BL, KK) \
+    launch_persistent(k_learned<BL, KK>, lds, tiles, s, a, pk, n, out_idx, out_act, dflt)
+    if (b_lds) {
+        if (K == 1) return FW_LEARNED(true, 1);
+        if (K == 2) return FW_LEARNED(true, 2);
+        return FW_LEARNED(true, 4);
+    }
+    if (K == 1) return FW_LEARNED(false, 1);
+    if (K == 2) return FW_LEARNED(false, 2);
+    return FW_LEARNED(false, 4);
+#undef FW_LEARNED
 }
 
 }  // namespace fw

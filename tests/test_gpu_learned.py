@@ -85,9 +85,9 @@ def test_learned_classify_matches_oracle(wl, seed):
     rules, pk = gen.workload(wl, seed=seed)
     say(f"learned {wl} seed={seed}")
     want = oracle.classify(rules, pk, threads=16)
-    for lookup in (0, 1):
-        got, miss, st = _learned_np(rules, pk, lookup=lookup)
-        assert_same(got, want, f"learned {wl} seed {seed} lookup {lookup}")
+    for lookup, ppl in ((0, 0), (1, 0), (0, 1), (0, 4)):
+        got, miss, st = _learned_np(rules, pk, lookup=lookup, packets_per_lane=ppl)
+        assert_same(got, want, f"learned {wl} seed {seed} lookup {lookup} ppl {ppl}")
         if lookup == 1:
             assert miss == 0
 
@@ -125,8 +125,9 @@ def test_learned_ragged_and_edge_rulesets(n):
         pk = gen.make_packets(gen.make_rules(20, seed + 50), n, seed)
         say(f"learned ragged n={n} R={R}")
         want = oracle.classify(rules, pk)
-        got, _, _ = _learned_np(rules, pk)
-        assert_same(got, want, f"learned n={n} R={R}")
+        for ppl in (1, 2, 4):
+            got, _, _ = _learned_np(rules, pk, packets_per_lane=ppl)
+            assert_same(got, want, f"learned n={n} R={R} ppl={ppl}")
 
 
 def test_forced_window_miss_stays_exact():
@@ -138,6 +139,16 @@ def test_forced_window_miss_stays_exact():
     assert st["err_max"] == 0 and miss > len(pk) // 4
     got, miss2, st2 = _learned_np(rules, pk, build_kw=dict(FAST, train=False))
     assert_same(got, want, "untrained network")
+
+
+def test_small_network_shapes():
+    """Fewer hidden units and experts than the defaults (padded inference layout)."""
+    rules, pk = gen.workload("scan_1000x1M", seed=2, n_packets=100_000)
+    want = oracle.classify(rules, pk, threads=16)
+    for hidden, experts in ((7, 5), (1, 1), (32, 200)):
+        say(f"learned hidden={hidden} experts={experts}")
+        got, _, st = _learned_np(rules, pk, build_kw=dict(FAST, hidden=hidden, experts=experts))
+        assert_same(got, want, f"hidden={hidden} experts={experts}")
 
 
 def test_network_gain():
