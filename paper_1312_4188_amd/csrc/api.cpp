@@ -18,6 +18,7 @@ struct fw_ruleset {
     int device = 0;
     fw::RuleRec* d_rules = nullptr;          // n_rules records (at least one allocated)
     uint2* d_pairs = nullptr;                // (dst_lo, dst_w) per rule, + kPairPadding
+    fw::DevicePlan plan;                     // grouped scan plan (packet split)
     std::vector<fw::RuleRec> h_rules;        // host copy of the compiled records
     std::vector<fw_rule> source;             // the rules as given
     fw::LearnedIndex* index = nullptr;       // null until built
@@ -146,9 +147,11 @@ fw_status fw_load_ruleset(const fw_rule* rules, uint32_t n_rules, uint8_t defaul
     if (e == hipSuccess)
         e = hipMemcpy(rs->d_pairs, pairs.data(), sizeof(uint2) * pairs.size(),
                       hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = make_plan(rs->h_rules.data(), n_rules, &rs->plan);
     if (e != hipSuccess) {
         if (rs->d_rules) (void)hipFree(rs->d_rules);
         if (rs->d_pairs) (void)hipFree(rs->d_pairs);
+        free_plan(&rs->plan);
         delete rs;
         return hip_fail(e, "uploading the ruleset");
     }
@@ -161,6 +164,7 @@ fw_status fw_free_ruleset(fw_ruleset* rs) {
     hipError_t e = hipDeviceSynchronize();
     destroy_index(rs->index);
     rs->index = nullptr;
+    free_plan(&rs->plan);
     for (void* p : {static_cast<void*>(rs->d_rules), static_cast<void*>(rs->d_pairs)}) {
         if (!p) continue;
         const hipError_t e2 = hipFree(p);
@@ -203,8 +207,7 @@ fw_status fw_classify_ex(const fw_ruleset* rs, const fw_packets* pk, size_t n,
     hipError_t e = hipSuccess;
     switch (mode) {
         case FW_MODE_PACKET_SPLIT:
-            e = launch_packet_split(rs->d_pairs, rs->d_rules, rs->n_rules, pd, n, out_rule_idx,
-                                    out_action,
+            e = launch_packet_split(rs->plan.plan, pd, n, out_rule_idx, out_action,
                                     rs->default_action,
                                     o.packets_per_lane ? int(o.packets_per_lane) : 4, stream);
             break;

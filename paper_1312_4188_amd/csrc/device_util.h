@@ -13,6 +13,11 @@ typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
+// Index of the calling wave within its work-group, as a wave-uniform (scalar) value.
+__device__ __forceinline__ uint32_t wave_in_group() {
+    return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+}
+
 // Unsigned range test: v lies in [lo, lo + w].
 __device__ __forceinline__ bool in_range(uint32_t v, uint32_t lo, uint32_t w) {
     return (v - lo) <= w;

@@ -35,8 +35,7 @@ struct LearnedIndex {
     uint32_t* d_B = nullptr;
     uint32_t* d_off = nullptr;
     RuleRec* d_L = nullptr;
-    RuleRec* d_G = nullptr;
-    uint2* d_Gpairs = nullptr;
+    DevicePlan gplan;             // shared list as a grouped scan plan
     float* d_w1 = nullptr;
     uint16_t* d_w2 = nullptr;
     ExpertMeta* d_meta = nullptr;
@@ -227,9 +226,9 @@ struct Trainer {
 };
 
 void free_index_memory(LearnedIndex* ix) {
+    free_plan(&ix->gplan);
     for (void* p : {static_cast<void*>(ix->d_B), static_cast<void*>(ix->d_off),
-                    static_cast<void*>(ix->d_L), static_cast<void*>(ix->d_G),
-                    static_cast<void*>(ix->d_Gpairs),
+                    static_cast<void*>(ix->d_L),
                     static_cast<void*>(ix->d_w1), static_cast<void*>(ix->d_w2),
                     static_cast<void*>(ix->d_meta), static_cast<void*>(ix->d_miss)})
         if (p) (void)hipFree(p);
@@ -245,9 +244,7 @@ LookupArgs args_of(const LearnedIndex* ix, uint32_t use_net) {
     a.E = ix->E;
     a.off = ix->d_off;
     a.L = ix->d_L;
-    a.G = ix->d_G;
-    a.Gpairs = ix->d_Gpairs;
-    a.nG = ix->nG;
+    a.G = ix->gplan.plan;
     a.use_net = use_net;
     a.miss = nullptr;
     return a;
@@ -386,8 +383,7 @@ fw_status build_index(const fw_rule* rules, const RuleRec* recs, uint32_t n_rule
     if ((e = dalloc(&ix->d_B, M, &bytes)) != hipSuccess ||
         (e = dalloc(&ix->d_off, size_t(M) + 1, &bytes)) != hipSuccess ||
         (e = dalloc(&ix->d_L, ix->nL, &bytes)) != hipSuccess ||
-        (e = dalloc(&ix->d_G, ix->nG, &bytes)) != hipSuccess ||
-        (e = dalloc(&ix->d_Gpairs, size_t(ix->nG) + kPairPadding, &bytes)) != hipSuccess ||
+
         (e = dalloc(&ix->d_w1, kGradCols, &bytes)) != hipSuccess ||
         (e = dalloc(&ix->d_w2, size_t(E) * kInferStride, &bytes)) != hipSuccess ||
         (e = dalloc(&ix->d_meta, E, &bytes)) != hipSuccess ||
@@ -396,13 +392,10 @@ fw_status build_index(const fw_rule* rules, const RuleRec* recs, uint32_t n_rule
     ix->device_bytes = bytes;
     if ((e = upload(ix->d_B, ix->B, s)) != hipSuccess ||
         (e = upload(ix->d_off, ix->off, s)) != hipSuccess ||
-        (e = upload(ix->d_L, L, s)) != hipSuccess || (e = upload(ix->d_G, G, s)) != hipSuccess)
+        (e = upload(ix->d_L, L, s)) != hipSuccess || (e = hipStreamSynchronize(s)) != hipSuccess ||
+        (e = make_plan(G.data(), ix->nG, &ix->gplan)) != hipSuccess)
         return bail(e, "uploading the learned index");
-    std::vector<uint2> gpairs(size_t(ix->nG) + kPairPadding, uint2{0u, 0u});
-    for (uint32_t k = 0; k < ix->nG; ++k) gpairs[k] = uint2{G[k].src_lo, G[k].src_w};
-    if ((e = upload(ix->d_Gpairs, gpairs, s)) != hipSuccess ||
-        (e = hipStreamSynchronize(s)) != hipSuccess)
-        return bail(e, "uploading the learned index");
+    ix->device_bytes += ix->gplan.bytes;
 
     // ---- training samples: both ends of every interval, target = its position
     std::vector<uint32_t> keys;

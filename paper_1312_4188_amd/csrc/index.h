@@ -61,9 +61,7 @@ struct LookupArgs {
     uint32_t E;
     const uint32_t* off;      // M + 1 per-interval list offsets
     const RuleRec* L;         // per-interval candidate records
-    const RuleRec* G;         // global (destination-wildcard) candidate records
-    const uint2* Gpairs;      // (src_lo, src_w) of each G record, + kPairPadding
-    uint32_t nG;
+    ScanPlan G;               // shared (destination-wildcard) candidates as a grouped plan
     uint32_t use_net;         // 0: full binary search only
     unsigned long long* miss; // optional window-miss counter
 };

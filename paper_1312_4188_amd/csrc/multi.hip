@@ -102,7 +102,7 @@ __global__ __launch_bounds__(256) void k_multi_lds(const ChainDesc* __restrict__
     __shared__ uint32_t s_item;
     __shared__ RuleRec s_rules[TILE];
     __shared__ uint2 s_pairs[TILE + kPairPadding];
-    const uint32_t wave = threadIdx.x >> 6;
+    const uint32_t wave = wave_in_group();
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
         __syncthreads();

@@ -103,7 +103,7 @@ __global__ __launch_bounds__(256) void k_grad_mfma(const uint16_t* __restrict__ 
                                                    const uint32_t* __restrict__ ex, size_t n_pad,
                                                    uint32_t E_pad, float* __restrict__ partial) {
     const uint32_t chunk = blockIdx.x, mtile = blockIdx.y;
-    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    const uint32_t wave = wave_in_group(), lane = threadIdx.x & 63u;
     const uint32_t m = mtile * 32u + (lane & 31u);
     const uint32_t c = wave * 32u + (lane & 31u);
     const uint32_t kq = (lane >> 5) * 8u;
@@ -289,9 +289,10 @@ __global__ void k_err_bound(LookupArgs a, const uint32_t* __restrict__ keys,
 //   1. locate each packet's destination interval j (network + window, else a
 //      full binary search);
 //   2. scan j's own candidate list per lane (ascending, stop at the first match);
-//   3. scan the shared destination-wildcard list with the packet-split wave
-//      scan (source tested first; the destination test is implied);
-//   4. keep the smaller of the two partial first matches and write it.
+//   3. scan the shared destination-wildcard list (a grouped scan plan) with
+//      the packet-split wave scan, seeded with step 2's answer, so each lane
+//      keeps the smaller of the two partial first matches;
+//   4. write the index and action.
 constexpr uint32_t kLearnedBlock = 1024;
 constexpr uint32_t kLearnedK = 2;     // default packets per lane in the classify kernel
 
@@ -324,13 +325,13 @@ __device__ __forceinline__ IndexView stage_index(const LookupArgs& a, unsigned c
     uint16_t* s_w2 = reinterpret_cast<uint16_t*>(smem + o_w2);
     uint32_t* s_b = reinterpret_cast<uint32_t*>(smem + o_b);
     const uint32_t tid = threadIdx.x;
-    for (uint32_t k = tid; k < kInferStride; k += blockDim.x) s_w1[k] = a.w1[k];
-    for (uint32_t k = tid; k < a.E * 8u; k += blockDim.x)
+    for (uint32_t k = tid; k < kInferStride; k += kLearnedBlock) s_w1[k] = a.w1[k];
+    for (uint32_t k = tid; k < a.E * 8u; k += kLearnedBlock)
         reinterpret_cast<uint32_t*>(s_meta)[k] = reinterpret_cast<const uint32_t*>(a.meta)[k];
-    for (uint32_t k = tid; k < a.E * kInferStride / 2u; k += blockDim.x)
+    for (uint32_t k = tid; k < a.E * kInferStride / 2u; k += kLearnedBlock)
         reinterpret_cast<uint32_t*>(s_w2)[k] = reinterpret_cast<const uint32_t*>(a.w2)[k];
     if constexpr (B_LDS)
-        for (uint32_t k = tid; k < a.M; k += blockDim.x) s_b[k] = a.B[k];
+        for (uint32_t k = tid; k < a.M; k += kLearnedBlock) s_b[k] = a.B[k];
     __syncthreads();
     return IndexView{s_w1, s_meta, s_w2, B_LDS ? s_b : a.B};
 }
@@ -346,8 +347,9 @@ __global__ __launch_bounds__(kLearnedBlock, K >= 4 ? 4 : 8) void k_learned(Looku
     extern __shared__ __align__(16) unsigned char smem[];
     const IndexView v = stage_index<B_LDS>(a, smem);
     const uint32_t lane = threadIdx.x & 63u;
-    const size_t waves = size_t(gridDim.x) * (blockDim.x >> 6);
-    const size_t wave0 = size_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    constexpr uint32_t kWaves = kLearnedBlock / 64;   // compile-time: keeps the loop scalar
+    const size_t waves = size_t(gridDim.x) * kWaves;
+    const size_t wave0 = size_t(blockIdx.x) * kWaves + wave_in_group();
     for (size_t base = wave0 * 64u * K; base < n; base += waves * 64u * K) {
         WaveScan<K> w;
         w.init(pk, base, n, dflt);
@@ -376,14 +378,12 @@ __global__ __launch_bounds__(kLearnedBlock, K >= 4 ? 4 : 8) void k_learned(Looku
                 }
             }
         }
-        w.template scan<FirstField::Src, true>(a.Gpairs, a.G, a.nG, 0u);
 #pragma unroll
         for (int s = 0; s < K; ++s) {
-            if (lbest[s] < w.best[s]) {
-                w.best[s] = lbest[s];
-                w.act[s] = lact[s];
-            }
+            w.best[s] = lbest[s];
+            w.act[s] = lact[s];
         }
+        w.scan_plan(a.G);
         w.store(out_idx, out_act, n);
     }
 }
@@ -396,8 +396,9 @@ __global__ __launch_bounds__(kLearnedBlock) void k_lookup(LookupArgs a,
                                                           int32_t* __restrict__ out_interval) {
     extern __shared__ __align__(16) unsigned char smem[];
     const IndexView v = stage_index<B_LDS>(a, smem);
-    const size_t waves = size_t(gridDim.x) * (blockDim.x >> 6);
-    const size_t wave0 = size_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    constexpr uint32_t kWaves = kLearnedBlock / 64;   // compile-time: keeps the loop scalar
+    const size_t waves = size_t(gridDim.x) * kWaves;
+    const size_t wave0 = size_t(blockIdx.x) * kWaves + wave_in_group();
     for (size_t base = wave0 * 64u; base < n; base += waves * 64u) {
         const size_t i = base + (threadIdx.x & 63u);
         const bool valid = i < n;

@@ -17,19 +17,23 @@
 namespace fw {
 namespace {
 
+constexpr uint32_t kScanBlock = 256;   // threads per work-group of the scan kernels
+
 // ------------------------------------------------------------------ packet split
-// The packet-split kernel: each wave classifies 64*K packets with scan_wave.
+// The packet-split kernel: each wave classifies 64*K packets against the
+// ruleset's grouped scan plan.
 template <int K>
-__global__ __launch_bounds__(256) void k_packet_split(const uint2* __restrict__ pairs,
-                                                      const RuleRec* __restrict__ rules,
-                                                      uint32_t n_rules, PacketsDev pk, size_t n,
+__global__ __launch_bounds__(kScanBlock) void k_packet_split(ScanPlan plan, PacketsDev pk, size_t n,
                                                       int32_t* __restrict__ out_idx,
                                                       uint8_t* __restrict__ out_act,
                                                       uint32_t dflt) {
-    const size_t wave = (size_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const size_t wave = size_t(blockIdx.x) * (kScanBlock / 64) + wave_in_group();
     const size_t wave_first = wave * 64u * K;
     if (wave_first >= n) return;  // wave-uniform
-    scan_wave<K>(pairs, rules, n_rules, pk, wave_first, n, out_idx, out_act, dflt);
+    WaveScan<K> w;
+    w.init(pk, wave_first, n, dflt);
+    w.scan_plan(plan);
+    w.store(out_idx, out_act, n);
 }
 
 // ------------------------------------------------------------------ rule split
@@ -72,14 +76,14 @@ __device__ __forceinline__ bool full_match(const RuleRec& q, uint32_t src, uint3
 constexpr int kPrune = 8;
 
 template <int LP>
-__global__ __launch_bounds__(256) void k_rule_split(const RuleRec* __restrict__ rules,
+__global__ __launch_bounds__(kScanBlock) void k_rule_split(const RuleRec* __restrict__ rules,
                                                     uint32_t n_rules, uint32_t P, uint32_t S,
                                                     uint32_t wpp, PacketsDev pk, size_t n,
                                                     int32_t* __restrict__ out_idx,
                                                     uint8_t* __restrict__ out_act,
                                                     uint32_t dflt, int use_atomic) {
     const uint32_t lane = threadIdx.x & 63u;
-    const size_t wave = (size_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const size_t wave = size_t(blockIdx.x) * (kScanBlock / 64) + wave_in_group();
     const size_t group = wave / wpp;
     const uint32_t blk = uint32_t(wave % wpp);
     const uint32_t slot = lane / LP, sub = lane % LP;
@@ -164,7 +168,7 @@ __global__ __launch_bounds__(1024) void k_hybrid(const uint2* __restrict__ pairs
                                                  uint8_t* __restrict__ out_act, uint32_t dflt) {
     __shared__ uint32_t smin[64];
     const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t w = threadIdx.x >> 6;
+    const uint32_t w = wave_in_group();
     const size_t first = size_t(blockIdx.x) * 64u;
     if (w == 0) smin[lane] = kNoMatch;
     __syncthreads();
@@ -195,24 +199,24 @@ inline uint32_t ceil_div(uint64_t a, uint64_t b) { return uint32_t((a + b - 1) /
 
 }  // namespace
 
-hipError_t launch_packet_split(const uint2* pairs, const RuleRec* rules, uint32_t n_rules,
-                               PacketsDev pk, size_t n,
-                               int32_t* out_idx, uint8_t* out_act, uint8_t default_action,
-                               int packets_per_lane, hipStream_t stream) {
+hipError_t launch_packet_split(const ScanPlan& plan, PacketsDev pk, size_t n, int32_t* out_idx,
+                               uint8_t* out_act, uint8_t default_action, int packets_per_lane,
+                               hipStream_t stream) {
     if (n == 0) return hipSuccess;
-    constexpr uint32_t kBlock = 256;
+    constexpr uint32_t kBlock = kScanBlock;
     const int K = packets_per_lane;
     const uint64_t per_block = uint64_t(kBlock) * K;
     const uint32_t grid = ceil_div(n, per_block);
+    const uint32_t dflt = default_action;
     if (K == 4)
-        hipLaunchKernelGGL(k_packet_split<4>, dim3(grid), dim3(kBlock), 0, stream, pairs,
-                           rules, n_rules, pk, n, out_idx, out_act, uint32_t(default_action));
+        hipLaunchKernelGGL(k_packet_split<4>, dim3(grid), dim3(kBlock), 0, stream, plan, pk, n,
+                           out_idx, out_act, dflt);
     else if (K == 2)
-        hipLaunchKernelGGL(k_packet_split<2>, dim3(grid), dim3(kBlock), 0, stream, pairs,
-                           rules, n_rules, pk, n, out_idx, out_act, uint32_t(default_action));
+        hipLaunchKernelGGL(k_packet_split<2>, dim3(grid), dim3(kBlock), 0, stream, plan, pk, n,
+                           out_idx, out_act, dflt);
     else
-        hipLaunchKernelGGL(k_packet_split<1>, dim3(grid), dim3(kBlock), 0, stream, pairs,
-                           rules, n_rules, pk, n, out_idx, out_act, uint32_t(default_action));
+        hipLaunchKernelGGL(k_packet_split<1>, dim3(grid), dim3(kBlock), 0, stream, plan, pk, n,
+                           out_idx, out_act, dflt);
     return hipGetLastError();
 }
 
@@ -220,7 +224,7 @@ hipError_t launch_rule_split(const RuleRec* rules, uint32_t n_rules, uint32_t P,
                              size_t n, int32_t* out_idx, uint8_t* out_act,
                              uint8_t default_action, hipStream_t stream) {
     if (n == 0) return hipSuccess;
-    constexpr uint32_t kBlock = 256;
+    constexpr uint32_t kBlock = kScanBlock;
     const uint32_t S = n_rules == 0 ? 1u : ceil_div(n_rules, P);
     uint32_t LP = 1;
     while (LP < P && LP < 64) LP <<= 1;

@@ -82,8 +82,8 @@ __device__ __forceinline__ void store_results(int32_t* out_idx, uint8_t* out_act
     }
 }
 
-// Which packet field a scan tests first (the rest only when some live lane passes).
-enum class FirstField { Dst, Src };
+// Which packet field a rule is tested on first (see FirstTest).
+enum class FirstField { Dst = kFirstDst, Src = kFirstSrc, Ports = kFirstPorts, Proto = kFirstProto };
 
 // Rules per prefetch block of the first-test pairs: 8 pairs = 64 bytes, one
 // scalar load.  Pair arrays carry kPairPadding extra entries so the block
@@ -91,18 +91,18 @@ enum class FirstField { Dst, Src };
 constexpr uint32_t kPairBlock = 8;
 static_assert(kPairPadding >= kPairBlock, "pair arrays must be padded by a whole block");
 
-// First-match state of one wave over 64*K packets (K per lane), advanced over
-// any number of consecutive rule blocks.  Rule addresses are wave-uniform: the
-// first-test pair (lo, w) of each rule arrives through scalar loads, 8 rules
-// at a time and one block ahead, so the field test takes its rule operands from
-// SGPRs without waiting.  A ballot turns the lanes' tests into a wave mask;
-// when no live lane passes, the rule is done after 2K vector ops (most rules
-// are rejected this way).  Otherwise the full record is read and the remaining
-// fields are tested the same way.  Once every live lane has matched the scan
-// stops.
+// First-match state of one wave over 64*K packets (K per lane).  Rule
+// addresses are wave-uniform: the first-test pair (lo, w) of each rule arrives
+// through scalar loads, 8 rules at a time and one block ahead, so the field
+// test takes its rule operands from SGPRs without waiting.  A ballot turns
+// the lanes' tests into a wave mask; when no live lane passes, the rule is
+// done after 2K vector ops (3K for the port pair).  Otherwise the full record
+// is read and the remaining fields are tested the same way; matched lanes
+// take the rule through a select on the wave mask itself.
 template <int K>
 struct WaveScan {
     uint32_t src[K], dst[K], pp[K], pr[K];
+    uint64_t valid[K];
     uint64_t live[K];
     uint64_t live_any;
     uint32_t best[K], act[K];
@@ -115,7 +115,8 @@ struct WaveScan {
         live_any = 0;
 #pragma unroll
         for (int s = 0; s < K; ++s) {
-            live[s] = ballot(p0 + s < n);
+            valid[s] = ballot(p0 + s < n);
+            live[s] = valid[s];
             live_any |= live[s];
             best[s] = kNoMatch;
             act[s] = dflt;
@@ -124,13 +125,14 @@ struct WaveScan {
 
     // Single-packet-per-lane start from values already in registers.
     __device__ __forceinline__ void init_values(uint32_t s_, uint32_t d_, uint32_t pp_,
-                                                uint32_t pr_, bool valid, uint32_t dflt) {
+                                                uint32_t pr_, bool ok, uint32_t dflt) {
         static_assert(K == 1, "one packet per lane");
         src[0] = s_;
         dst[0] = d_;
         pp[0] = pp_;
         pr[0] = pr_;
-        live[0] = ballot(valid);
+        valid[0] = ballot(ok);
+        live[0] = valid[0];
         live_any = live[0];
         best[0] = kNoMatch;
         act[0] = dflt;
@@ -139,21 +141,34 @@ struct WaveScan {
 
     __device__ __forceinline__ bool any_live() const { return live_any != 0; }
 
-    // Remaining tests of a rule some live lane passed on its first field;
-    // records matches and clears matched lanes from the live masks.
     template <FirstField F>
+    __device__ __forceinline__ bool first_test(int s, uint2 f) const {
+        if constexpr (F == FirstField::Dst) return in_range(dst[s], f.x, f.y);
+        if constexpr (F == FirstField::Src) return in_range(src[s], f.x, f.y);
+        if constexpr (F == FirstField::Ports) return ports_in(pp[s], f.x, f.y);
+        return in_range(pr[s], f.x, f.y);
+    }
+
+    // Remaining tests of a rule some live lane passed on its first field.  A
+    // rule tested first on the ports has both addresses unspecified, one
+    // tested first on the protocol has addresses and ports unspecified, so
+    // those tests are skipped.  With SEEDED, a lane takes the rule only if it
+    // beats the lane's current answer.  Matched lanes leave the live masks.
+    template <FirstField F, bool SEEDED>
     __device__ __forceinline__ void finish(const uint64_t (&c)[K], const RuleRec& q,
                                            uint32_t idx) {
-        const uint32_t lane = threadIdx.x & 63u;
         const uint32_t plo = proto_lo(q.proto), pw = proto_w(q.proto);
         uint64_t m[K];
         uint64_t any = 0;
 #pragma unroll
         for (int s = 0; s < K; ++s) {
             m[s] = c[s] & live[s];
+            if constexpr (F == FirstField::Src) m[s] &= ballot(in_range(dst[s], q.dst_lo, q.dst_w));
             if constexpr (F == FirstField::Dst) m[s] &= ballot(in_range(src[s], q.src_lo, q.src_w));
-            m[s] &= ballot(ports_in(pp[s], q.port_lo, q.port_w)) &
-                    ballot(in_range(pr[s], plo, pw));
+            if constexpr (F == FirstField::Dst || F == FirstField::Src)
+                m[s] &= ballot(ports_in(pp[s], q.port_lo, q.port_w));
+            if constexpr (F != FirstField::Proto) m[s] &= ballot(in_range(pr[s], plo, pw));
+            if constexpr (SEEDED) m[s] &= ballot(best[s] > idx);
             any |= m[s];
         }
         if (any == 0) return;
@@ -161,7 +176,7 @@ struct WaveScan {
         live_any = 0;
 #pragma unroll
         for (int s = 0; s < K; ++s) {
-            if ((m[s] >> lane) & 1u) {
+            if (__builtin_amdgcn_inverse_ballot_w64(m[s])) {
                 best[s] = idx;
                 act[s] = ra;
             }
@@ -170,30 +185,27 @@ struct WaveScan {
         }
     }
 
-    // First-field test of rule r for every slot; the full record is read only
-    // when some live lane passes.
-    template <FirstField F, bool OWN_INDEX>
+    template <FirstField F, bool OWN_INDEX, bool SEEDED>
     __device__ __forceinline__ void step(uint2 f, const RuleRec* __restrict__ rules, uint32_t r,
                                          uint32_t base) {
         uint64_t c[K];
         uint64_t any = 0;
 #pragma unroll
         for (int s = 0; s < K; ++s) {
-            c[s] = ballot(in_range(F == FirstField::Dst ? dst[s] : src[s], f.x, f.y));
+            c[s] = ballot(first_test<F>(s, f));
             any |= c[s];
         }
         if (__builtin_expect((any & live_any) != 0, 0)) {
             const RuleRec q = rules[r];
-            finish<F>(c, q, OWN_INDEX ? q.idx : base + r);
+            finish<F, SEEDED>(c, q, OWN_INDEX ? q.idx : base + r);
         }
     }
 
-    // Rules r = 0..count-1: first-test pair first[r], record rules[r], global
-    // index base + r (or the record's own index field with OWN_INDEX).  The
-    // pairs come 8 at a time, one block ahead; the wave stops after the block
-    // in which its last live lane matched.  Returns false once every packet of
-    // the wave has matched.
-    template <FirstField F, bool OWN_INDEX = false>
+    // Rules r = 0..count-1: first-test pair first[r], record rules[r], index
+    // base + r (or the record's own index field with OWN_INDEX).  The pairs
+    // come 8 at a time, one block ahead; the scan stops after the block in
+    // which its last live lane matched.  Returns false once no lane is live.
+    template <FirstField F, bool OWN_INDEX = false, bool SEEDED = false>
     __device__ __forceinline__ bool scan(const uint2* __restrict__ first,
                                          const RuleRec* __restrict__ rules, uint32_t count,
                                          uint32_t base) {
@@ -209,17 +221,57 @@ struct WaveScan {
                 for (uint32_t u = 0; u < kPairBlock; ++u) nxt[u] = first[r + kPairBlock + u];
 #pragma unroll
                 for (uint32_t u = 0; u < kPairBlock; ++u)
-                    step<F, OWN_INDEX>(cur[u], rules, r + u, base);
+                    step<F, OWN_INDEX, SEEDED>(cur[u], rules, r + u, base);
                 if (live_any == 0) return false;
 #pragma unroll
                 for (uint32_t u = 0; u < kPairBlock; ++u) cur[u] = nxt[u];
             }
         }
         for (; r < count; ++r) {
-            step<F, OWN_INDEX>(first[r], rules, r, base);
+            step<F, OWN_INDEX, SEEDED>(first[r], rules, r, base);
             if (live_any == 0) return false;
         }
         return true;
+    }
+
+    // Grouped scan (ScanPlan).  The catch-all tail seeds every valid lane's
+    // answer (when it beats what the lane already holds); then each group is
+    // scanned in rule order by every valid lane whose answer could still
+    // improve, taking a rule only when it beats the lane's answer.  The
+    // answer is the minimum over groups of each group's first match, which is
+    // the first match of the whole list.
+    __device__ __forceinline__ void scan_plan(const ScanPlan& plan) {
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            if (__builtin_amdgcn_inverse_ballot_w64(valid[s]) && plan.tail_idx < best[s]) {
+                best[s] = plan.tail_idx;
+                act[s] = plan.tail_act;
+            }
+        }
+        for (uint32_t g = 0; g < plan.n_groups; ++g) {
+            const ScanGroup& G = plan.g[g];
+            const uint32_t first_idx = G.recs[0].idx;
+            live_any = 0;
+#pragma unroll
+            for (int s = 0; s < K; ++s) {
+                live[s] = valid[s] & ballot(best[s] > first_idx);
+                live_any |= live[s];
+            }
+            switch (G.kind) {
+                case kFirstDst:
+                    scan<FirstField::Dst, true, true>(G.pairs, G.recs, G.count, 0u);
+                    break;
+                case kFirstSrc:
+                    scan<FirstField::Src, true, true>(G.pairs, G.recs, G.count, 0u);
+                    break;
+                case kFirstPorts:
+                    scan<FirstField::Ports, true, true>(G.pairs, G.recs, G.count, 0u);
+                    break;
+                default:
+                    scan<FirstField::Proto, true, true>(G.pairs, G.recs, G.count, 0u);
+                    break;
+            }
+        }
     }
 
     __device__ __forceinline__ void store(int32_t* out_idx, uint8_t* out_act, size_t n) const {

@@ -184,3 +184,45 @@ def test_plain_entry_point_and_errors():
         assert ei.value.status == fw.E_INVAL
         # n == 0 is accepted and writes nothing
         rs.classify(dp.slice(0, 0))
+
+
+@pytest.mark.parametrize("catch_all_at", [None, 0, 150, 299])
+def test_every_first_test_kind(catch_all_at):
+    """Rules whose most selective field is each of destination, source, ports and protocol,
+    with and without a catch-all (rules after it can never match)."""
+    rng = np.random.Generator(np.random.PCG64(77))
+    R = 300
+    rules = gen.make_rules(R, 77, skew=True)
+    kind = rng.integers(0, 4, R)
+    rules.src_plen[kind == 0] = 0                      # destination only (or both narrow)
+    rules.dst_plen[kind == 1] = 0                      # source only
+    for k in (2, 3):
+        rules.src_plen[kind == k] = 0
+        rules.dst_plen[kind == k] = 0
+    rules.proto_any[kind == 2] = 1                     # ports only
+    rules.sport_lo[kind == 3] = 0                      # protocol only
+    rules.sport_hi[kind == 3] = 65535
+    rules.dport_lo[kind == 3] = 0
+    rules.dport_hi[kind == 3] = 65535
+    rules.proto_any[kind == 3] = 0
+    if catch_all_at is not None:
+        c = catch_all_at
+        rules.src_plen[c] = rules.dst_plen[c] = 0
+        rules.sport_lo[c] = rules.dport_lo[c] = 0
+        rules.sport_hi[c] = rules.dport_hi[c] = 65535
+        rules.proto_any[c] = 1
+    pk = gen.make_packets(rules, 50_000, 78)
+    want = oracle.classify(rules, pk, threads=8)
+    for kw in SCAN_MODES + [dict(mode="learned")]:
+        say(f"kinds catch_all_at={catch_all_at} {kw}")
+        if kw["mode"] == "learned":
+            import torch
+            fw = fwmod()
+            with fw.Ruleset(rules) as rs:
+                rs.build_learned_index(epochs1=200, epochs2=400)
+                idx, act = rs.classify(fw.DevicePackets.from_host(pk), mode="learned")
+                torch.cuda.synchronize()
+                got = (idx.cpu().numpy(), act.cpu().numpy())
+        else:
+            got = classify_np(rules, pk, **kw)
+        assert_same(got, want, f"kinds {catch_all_at} {kw}")
