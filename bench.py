@@ -218,6 +218,50 @@ def serving_leg(seed: int, n_req: int, loads, log_fn):
     return out
 
 
+def multichain_leg(seed: int, steps: int, log_fn):
+    """64 independent chains (32..8,192 rules, 4,096..1,048,576 packets, log-uniform) in one
+    persistent launch, autotuned, against one packet-split launch per chain."""
+    import torch
+    from synth import gen
+    from paper_1312_4188_amd import fw
+    work = gen.multichain_workload(seed=seed)
+    items, rss = [], []
+    for rules, pk in work:
+        rs = fw.Ruleset(rules)
+        rss.append(rs)
+        n = len(pk)
+        items.append((rs, fw.DevicePackets.from_host(pk),
+                      torch.empty(n, dtype=torch.int32, device="cuda"),
+                      torch.empty(n, dtype=torch.uint8, device="cuda")))
+    total = sum(len(it[1]) for it in items)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    best, tuned_ms = fw.autotune_multi(items)
+    log_fn(f"  multichain autotuned {best} ({tuned_ms:.3f} ms)")
+    configs = {"tuned": {}}
+    for K in (1, 2, 4):
+        configs[f"scalar_k{K}"] = dict(packets_per_lane=K, placement=1)
+        configs[f"lds1024_k{K}"] = dict(packets_per_lane=K, placement=2, rule_tile=1024)
+    out = {"chains": len(items), "packets": total,
+           "rules_total": int(sum(len(r) for r, _ in work)), "tuned": best, "configs": {}}
+    for name, kw in configs.items():
+        ms, _ = time_steps(lambda: fw.classify_multi(items, stream=stream, **kw), steps, 2, stream)
+        out["configs"][name] = {"ms": ms, "mpps": total / ms / 1e3}
+    ref = [(it[2].clone(), it[3].clone()) for it in items]
+
+    def per_chain():
+        for rs, dp, oi, oa in items:
+            rs.classify(dp, mode="packet_split", stream=stream, out_idx=oi, out_act=oa)
+    ms, _ = time_steps(per_chain, steps, 2, stream)
+    out["configs"]["one_launch_per_chain"] = {"ms": ms, "mpps": total / ms / 1e3}
+    torch.cuda.synchronize()
+    out["same_as_per_chain"] = bool(all(torch.equal(a, it[2]) and torch.equal(b, it[3])
+                                        for (a, b), it in zip(ref, items)))
+    for rs in rss:
+        rs.close()
+    return out
+
+
 def cpu_baseline(rules, pk, n_sample: int):
     """The CPU oracle, as it stands, on a bounded sample of the same batch."""
     import oracle
@@ -245,6 +289,7 @@ def main():
                     help="comma list of modes to time (default: all); the first is the headline")
     ap.add_argument("--serving-requests", type=int, default=600,
                     help="requests per offered load in the serving leg (0 = skip it)")
+    ap.add_argument("--no-multichain", action="store_true", help="skip the 64-chain leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (for scaling HBM counters)")
     args = ap.parse_args()
@@ -359,6 +404,11 @@ def main():
         serving = serving_leg(args.seed, args.serving_requests,
                               (0.1, 0.3, 0.5, 0.7, 0.9, 1.0, 1.2), log)
 
+    multichain = None
+    if not args.no_multichain:
+        log("multi-chain leg")
+        multichain = multichain_leg(args.seed, max(3, args.steps // 2), log)
+
     cpu = None
     if not args.no_cpu:
         log("cpu baseline")
@@ -381,6 +431,7 @@ def main():
         "scan_rule_checks": checks, "learned_candidate_checks": work["candidate_checks"],
         "index": index_stats, "index_untrained": untrained_stats,
         "roofline": roofline, "scan_roofline": scan_roofline, "serving": serving,
+        "multichain": multichain,
         "cpu_baseline": cpu,
     }
     rs.close()
