@@ -217,7 +217,16 @@ fw_status fw_index_lookup(const fw_ruleset *rs, const uint32_t *keys, size_t n,
  *  3 = global list (uint32 rule indices of destination-wildcard candidates);
  *  4 = per-expert error bounds (uint32, `experts` entries);
  *  5 = network weights as float (stage 1 then the experts, each
- *      [w1 (H), b1 (H), w2 (H), b2]), after bf16 quantisation.
+ *      [w1 (H), b1 (H), w2 (H), b2]), after bf16 quantisation;
+ *  6 = source boundaries of the destination-wildcard candidates that specify a
+ *      source (uint32);
+ *  7 = their per-source-interval list offsets (uint32, count of 6 + 1);
+ *  8 = their per-source-interval list entries (uint32 rule indices);
+ *  9 = the candidates with source and destination both unspecified (uint32
+ *      rule indices), scanned by every packet.
+ * Lists 2, 8 and 9 are cut where no later entry can be a first match (after a
+ * rule that matches every packet reaching the list, and past the shared
+ * list's first catch-all).
  * At most `cap` bytes are written; *size receives the full size in bytes.
  * FW_E_NOINDEX without an index. */
 fw_status fw_index_export(const fw_ruleset *rs, uint32_t what, void *host, size_t cap,

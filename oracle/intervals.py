@@ -1,8 +1,9 @@
-"""Destination elementary intervals and exact candidate lists.  TEST INFRASTRUCTURE.
+"""Elementary address intervals and exact candidate lists.  TEST INFRASTRUCTURE.
 
 Not in the paper: the learned index is this project's addition on top of the
 paper's scan.  Everything here is written from set definitions, with no
-blocking, splitting or truncation tricks, so a reader can check it by eye:
+blocking, splitting or truncation tricks, so a reader can check it by eye
+(written for the destination field; `field="src"` applies the same to sources):
 
 * a rule's destination prefix (base, len) covers the addresses whose top
   ``len`` bits equal the base's: the range [lo, hi] with
@@ -27,19 +28,19 @@ import numpy as np
 TOP = 2**32 - 1
 
 
-def dst_ranges(rules):
-    """Per-rule destination range [lo, hi] as Python-int-safe uint64 arrays."""
-    base = np.asarray(rules.dst_ip, dtype=np.uint64)
-    plen = np.asarray(rules.dst_plen, dtype=np.uint64)
+def dst_ranges(rules, field: str = "dst"):
+    """Per-rule address range [lo, hi] (uint64 arrays) of the `field` ("dst" or "src") prefix."""
+    base = np.asarray(getattr(rules, f"{field}_ip"), dtype=np.uint64)
+    plen = np.asarray(getattr(rules, f"{field}_plen"), dtype=np.uint64)
     span = np.left_shift(np.uint64(1), np.uint64(32) - plen)        # 2**(32-len)
     lo = (base // span) * span                                       # clear low bits
     hi = lo + span - np.uint64(1)
     return lo, hi
 
 
-def boundaries(rules) -> np.ndarray:
-    """Sorted unique boundary set B (uint32)."""
-    lo, hi = dst_ranges(rules)
+def boundaries(rules, field: str = "dst") -> np.ndarray:
+    """Sorted unique boundary set B (uint32) of the `field` prefixes."""
+    lo, hi = dst_ranges(rules, field)
     ends = hi[hi < TOP] + np.uint64(1)
     b = np.unique(np.concatenate([np.zeros(1, np.uint64), lo, ends]))
     return b.astype(np.uint32)
@@ -57,9 +58,9 @@ def interval_end(B: np.ndarray) -> np.ndarray:
     return np.concatenate([b[1:] - np.uint64(1), np.array([TOP], np.uint64)])
 
 
-def candidates(rules, B: np.ndarray):
+def candidates(rules, B: np.ndarray, field: str = "dst"):
     """C_j for every interval j: list of int64 arrays of rule indices, ascending."""
-    lo, hi = dst_ranges(rules)
+    lo, hi = dst_ranges(rules, field)
     start = B.astype(np.uint64)
     end = interval_end(B)
     out = []

@@ -35,7 +35,13 @@ struct LearnedIndex {
     uint32_t* d_B = nullptr;
     uint32_t* d_off = nullptr;
     RuleRec* d_L = nullptr;
-    DevicePlan gplan;             // shared list as a grouped scan plan
+    DevicePlan gplan;             // source-and-destination-wildcard candidates, grouped plan
+    uint32_t Ms = 0;              // source intervals of the destination-wildcard candidates
+    uint64_t nS = 0;
+    uint32_t* d_Bs = nullptr;
+    uint32_t* d_soff = nullptr;
+    RuleRec* d_S = nullptr;
+    std::vector<uint32_t> Bs, soff, S_idx, Gw_idx;
     float* d_w1 = nullptr;
     uint16_t* d_w2 = nullptr;
     ExpertMeta* d_meta = nullptr;
@@ -228,7 +234,8 @@ struct Trainer {
 void free_index_memory(LearnedIndex* ix) {
     free_plan(&ix->gplan);
     for (void* p : {static_cast<void*>(ix->d_B), static_cast<void*>(ix->d_off),
-                    static_cast<void*>(ix->d_L),
+                    static_cast<void*>(ix->d_L), static_cast<void*>(ix->d_Bs),
+                    static_cast<void*>(ix->d_soff), static_cast<void*>(ix->d_S),
                     static_cast<void*>(ix->d_w1), static_cast<void*>(ix->d_w2),
                     static_cast<void*>(ix->d_meta), static_cast<void*>(ix->d_miss)})
         if (p) (void)hipFree(p);
@@ -245,79 +252,131 @@ LookupArgs args_of(const LearnedIndex* ix, uint32_t use_net) {
     a.off = ix->d_off;
     a.L = ix->d_L;
     a.G = ix->gplan.plan;
+    a.Bs = ix->d_Bs;
+    a.Ms = ix->Ms;
+    a.soff = ix->d_soff;
+    a.S = ix->d_S;
     a.use_net = use_net;
     a.miss = nullptr;
     return a;
 }
 
-fw_status build_lists(const RuleRec* recs, uint32_t n_rules, LearnedIndex* ix,
-                      std::vector<RuleRec>* L, std::vector<RuleRec>* G) {
-    // boundaries
-    std::vector<uint32_t>& B = ix->B;
-    B.clear();
-    B.reserve(size_t(n_rules) * 2 + 1);
-    B.push_back(0u);
-    for (uint32_t r = 0; r < n_rules; ++r) {
-        const uint64_t lo = recs[r].dst_lo, hi = lo + recs[r].dst_w;
-        B.push_back(uint32_t(lo));
-        if (hi < 0xFFFFFFFFull) B.push_back(uint32_t(hi + 1));
+// Elementary intervals of one address field over the rules `sel` (ascending
+// indices into recs) and, per interval, the ascending list of those rules whose
+// range for that field contains the whole interval, cut after the first rule
+// that `full` says matches every packet of the interval.
+template <class Range, class Full>
+fw_status interval_lists(const RuleRec* recs, const std::vector<uint32_t>& sel, Range range,
+                         Full full, std::vector<uint32_t>* B, std::vector<uint32_t>* off,
+                         std::vector<uint32_t>* idx, std::vector<RuleRec>* out) {
+    B->clear();
+    B->reserve(sel.size() * 2 + 1);
+    B->push_back(0u);
+    for (uint32_t r : sel) {
+        uint32_t lo, w;
+        range(recs[r], &lo, &w);
+        const uint64_t hi = uint64_t(lo) + w;
+        B->push_back(lo);
+        if (hi < 0xFFFFFFFFull) B->push_back(uint32_t(hi + 1));
     }
-    std::sort(B.begin(), B.end());
-    B.erase(std::unique(B.begin(), B.end()), B.end());
-    const uint32_t M = uint32_t(B.size());
-    ix->M = M;
-
-    // shared list: destination-wildcard rules up to the first catch-all
-    uint32_t g_cut = 0xFFFFFFFFu;
-    G->clear();
-    ix->G_idx.clear();
-    for (uint32_t r = 0; r < n_rules; ++r) {
-        if (recs[r].dst_w != 0xFFFFFFFFu) continue;
-        G->push_back(recs[r]);
-        ix->G_idx.push_back(r);
-        if (full_match_all(recs[r])) {
-            g_cut = r;
-            break;
-        }
-    }
-
-    // per-interval lists, built rule by rule so each list stays ascending
+    std::sort(B->begin(), B->end());
+    B->erase(std::unique(B->begin(), B->end()), B->end());
+    const uint32_t M = uint32_t(B->size());
     std::vector<std::vector<uint32_t>> lists(M);
     std::vector<uint8_t> closed(M, 0);
-    for (uint32_t r = 0; r < n_rules && r < g_cut; ++r) {
-        const RuleRec& q = recs[r];
-        if (q.dst_w == 0xFFFFFFFFu) continue;
-        const uint64_t lo = q.dst_lo, hi = lo + q.dst_w;
-        const uint32_t jlo = uint32_t(std::lower_bound(B.begin(), B.end(), uint32_t(lo)) - B.begin());
+    for (uint32_t r : sel) {
+        uint32_t lo, w;
+        range(recs[r], &lo, &w);
+        const uint64_t hi = uint64_t(lo) + w;
+        const uint32_t jlo = uint32_t(std::lower_bound(B->begin(), B->end(), lo) - B->begin());
         const uint32_t jhi =
             hi >= 0xFFFFFFFFull
                 ? M - 1
-                : uint32_t(std::lower_bound(B.begin(), B.end(), uint32_t(hi + 1)) - B.begin()) - 1;
-        const bool full = full_match_in_interval(q);
+                : uint32_t(std::lower_bound(B->begin(), B->end(), uint32_t(hi + 1)) - B->begin()) - 1;
+        const bool f = full(recs[r]);
         for (uint32_t j = jlo; j <= jhi; ++j) {
             if (closed[j]) continue;
             lists[j].push_back(r);
-            if (full) closed[j] = 1;
+            if (f) closed[j] = 1;
         }
     }
-    ix->off.assign(size_t(M) + 1, 0);
+    off->assign(size_t(M) + 1, 0);
     uint64_t total = 0;
     for (uint32_t j = 0; j < M; ++j) {
         total += lists[j].size();
         if (total > 0xFFFFFFFFull) return fail(FW_E_NOMEM, "candidate lists exceed 2^32 entries");
-        ix->off[j + 1] = uint32_t(total);
+        (*off)[j + 1] = uint32_t(total);
     }
-    ix->L_idx.clear();
-    ix->L_idx.reserve(total);
-    L->clear();
-    L->reserve(total);
+    idx->clear();
+    idx->reserve(total);
+    out->clear();
+    out->reserve(total);
     for (uint32_t j = 0; j < M; ++j)
         for (uint32_t r : lists[j]) {
-            ix->L_idx.push_back(r);
-            L->push_back(recs[r]);
+            idx->push_back(r);
+            out->push_back(recs[r]);
         }
-    ix->nL = total;
-    ix->nG = uint32_t(G->size());
+    return FW_OK;
+}
+
+// Destination intervals with their per-interval lists L_j (rules with a
+// specified destination), the shared destination-wildcard candidates G cut
+// at the first catch-all, and G split once more: rules of G with a specified
+// source get source intervals and per-interval lists S_i (an address in
+// source interval i passes exactly the source tests of the rules in S_i, by
+// the same covering argument), and the rest of G (source and destination
+// both unspecified, ending with the catch-all) is the wave-uniform list Gw.
+fw_status build_lists(const RuleRec* recs, uint32_t n_rules, LearnedIndex* ix,
+                      std::vector<RuleRec>* L, std::vector<RuleRec>* S,
+                      std::vector<RuleRec>* Gw) {
+    uint32_t g_cut = 0xFFFFFFFFu;
+    std::vector<uint32_t> dsel, ssel;
+    ix->G_idx.clear();
+    ix->Gw_idx.clear();
+    Gw->clear();
+    for (uint32_t r = 0; r < n_rules; ++r) {
+        const RuleRec& q = recs[r];
+        if (q.dst_w != 0xFFFFFFFFu) {
+            dsel.push_back(r);
+            continue;
+        }
+        ix->G_idx.push_back(r);
+        if (q.src_w != 0xFFFFFFFFu) {
+            ssel.push_back(r);
+        } else {
+            ix->Gw_idx.push_back(r);
+            Gw->push_back(q);
+        }
+        if (full_match_all(q)) {
+            g_cut = r;
+            break;
+        }
+    }
+    // rules past the first catch-all are unreachable (dsel is ascending, so trim its tail)
+    while (!dsel.empty() && dsel.back() > g_cut) dsel.pop_back();
+    auto dst_range = [](const RuleRec& q, uint32_t* lo, uint32_t* w) {
+        *lo = q.dst_lo;
+        *w = q.dst_w;
+    };
+    auto src_range = [](const RuleRec& q, uint32_t* lo, uint32_t* w) {
+        *lo = q.src_lo;
+        *w = q.src_w;
+    };
+    fw_status st = interval_lists(recs, dsel, dst_range, full_match_in_interval, &ix->B,
+                                  &ix->off, &ix->L_idx, L);
+    if (st != FW_OK) return st;
+    // a source-interval candidate (destination already unspecified) matches every
+    // packet of its interval when ports and protocol are unspecified
+    auto full_src = [](const RuleRec& q) {
+        return q.port_lo == 0 && q.port_w == 0xFFFFFFFFu && ((q.proto >> 8) & 0xFFu) == 255u;
+    };
+    st = interval_lists(recs, ssel, src_range, full_src, &ix->Bs, &ix->soff, &ix->S_idx, S);
+    if (st != FW_OK) return st;
+    ix->M = uint32_t(ix->B.size());
+    ix->Ms = uint32_t(ix->Bs.size());
+    ix->nL = ix->L_idx.size();
+    ix->nS = ix->S_idx.size();
+    ix->nG = uint32_t(ix->G_idx.size());
     return FW_OK;
 }
 
@@ -347,10 +406,10 @@ fw_status build_index(const fw_rule* rules, const RuleRec* recs, uint32_t n_rule
 
     LearnedIndex* ix = new (std::nothrow) LearnedIndex();
     if (!ix) return fail(FW_E_NOMEM, "host allocation failed");
-    std::vector<RuleRec> L, G;
+    std::vector<RuleRec> L, S, G;
     fw_status st;
     try {
-        st = build_lists(recs, n_rules, ix, &L, &G);
+        st = build_lists(recs, n_rules, ix, &L, &S, &G);
     } catch (const std::bad_alloc&) {
         st = fail(FW_E_NOMEM, "host allocation failed while building candidate lists");
     }
@@ -364,6 +423,7 @@ fw_status build_index(const fw_rule* rules, const RuleRec* recs, uint32_t n_rule
 
     // device footprint of what the index keeps
     const uint64_t keep = uint64_t(M) * 4 + (uint64_t(M) + 1) * 4 + ix->nL * sizeof(RuleRec) +
+                          uint64_t(ix->Ms) * 8 + 4 + ix->nS * sizeof(RuleRec) +
                           uint64_t(ix->nG ? ix->nG : 1) * sizeof(RuleRec) +
                           (uint64_t(ix->nG) + kPairPadding) * 8 + kGradCols * 4 +
                           uint64_t(E) * kInferStride * 2 + uint64_t(E) * sizeof(ExpertMeta) + 8;
@@ -383,6 +443,9 @@ fw_status build_index(const fw_rule* rules, const RuleRec* recs, uint32_t n_rule
     if ((e = dalloc(&ix->d_B, M, &bytes)) != hipSuccess ||
         (e = dalloc(&ix->d_off, size_t(M) + 1, &bytes)) != hipSuccess ||
         (e = dalloc(&ix->d_L, ix->nL, &bytes)) != hipSuccess ||
+        (e = dalloc(&ix->d_Bs, ix->Ms, &bytes)) != hipSuccess ||
+        (e = dalloc(&ix->d_soff, size_t(ix->Ms) + 1, &bytes)) != hipSuccess ||
+        (e = dalloc(&ix->d_S, ix->nS, &bytes)) != hipSuccess ||
 
         (e = dalloc(&ix->d_w1, kGradCols, &bytes)) != hipSuccess ||
         (e = dalloc(&ix->d_w2, size_t(E) * kInferStride, &bytes)) != hipSuccess ||
@@ -392,8 +455,10 @@ fw_status build_index(const fw_rule* rules, const RuleRec* recs, uint32_t n_rule
     ix->device_bytes = bytes;
     if ((e = upload(ix->d_B, ix->B, s)) != hipSuccess ||
         (e = upload(ix->d_off, ix->off, s)) != hipSuccess ||
-        (e = upload(ix->d_L, L, s)) != hipSuccess || (e = hipStreamSynchronize(s)) != hipSuccess ||
-        (e = make_plan(G.data(), ix->nG, &ix->gplan)) != hipSuccess)
+        (e = upload(ix->d_L, L, s)) != hipSuccess || (e = upload(ix->d_Bs, ix->Bs, s)) != hipSuccess ||
+        (e = upload(ix->d_soff, ix->soff, s)) != hipSuccess ||
+        (e = upload(ix->d_S, S, s)) != hipSuccess || (e = hipStreamSynchronize(s)) != hipSuccess ||
+        (e = make_plan(G.data(), uint32_t(G.size()), &ix->gplan)) != hipSuccess)
         return bail(e, "uploading the learned index");
     ix->device_bytes += ix->gplan.bytes;
 
@@ -644,6 +709,10 @@ fw_status index_export(const LearnedIndex* ix, uint32_t what, void* host, size_t
         case 3: src = ix->G_idx.data(); bytes = ix->G_idx.size() * 4; break;
         case 4: src = ix->err.data(); bytes = ix->err.size() * 4; break;
         case 5: src = ix->weights.data(); bytes = ix->weights.size() * 4; break;
+        case 6: src = ix->Bs.data(); bytes = ix->Bs.size() * 4; break;
+        case 7: src = ix->soff.data(); bytes = ix->soff.size() * 4; break;
+        case 8: src = ix->S_idx.data(); bytes = ix->S_idx.size() * 4; break;
+        case 9: src = ix->Gw_idx.data(); bytes = ix->Gw_idx.size() * 4; break;
         default: return fail(FW_E_INVAL, "unknown export %u", what);
     }
     if (size) *size = bytes;

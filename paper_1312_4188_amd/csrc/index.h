@@ -61,7 +61,11 @@ struct LookupArgs {
     uint32_t E;
     const uint32_t* off;      // M + 1 per-interval list offsets
     const RuleRec* L;         // per-interval candidate records
-    ScanPlan G;               // shared (destination-wildcard) candidates as a grouped plan
+    ScanPlan G;               // source- and destination-wildcard candidates (grouped plan)
+    const uint32_t* Bs;       // source intervals of the other destination-wildcard candidates
+    uint32_t Ms;
+    const uint32_t* soff;     // Ms + 1 per-source-interval list offsets
+    const RuleRec* S;         // per-source-interval candidate records
     uint32_t use_net;         // 0: full binary search only
     unsigned long long* miss; // optional window-miss counter
 };
@@ -87,6 +91,6 @@ hipError_t launch_learned(const LookupArgs& a, PacketsDev pk, size_t n, int32_t*
                           uint8_t* out_act, uint32_t dflt, const uint32_t* keys,
                           int32_t* out_interval, uint32_t packets_per_lane, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
-size_t learned_lds_bytes(const LookupArgs& a, bool b_in_lds);
+size_t learned_lds_bytes(const LookupArgs& a, bool b_in_lds, bool w2_f32);
 
 }  // namespace fw

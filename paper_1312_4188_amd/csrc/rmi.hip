@@ -15,6 +15,8 @@
 // product S^T * A, which runs on the matrix cores as bf16 x bf16 -> fp32 MFMA
 // (S is exact in bf16).  A plain fp32 reduction computes the same sums for
 // checking.
+#include <type_traits>
+
 #include "device_util.h"
 #include "fw_internal.h"
 #include "index.h"
@@ -225,6 +227,25 @@ __device__ __forceinline__ int32_t position(const uint16_t* w2e, const ExpertMet
     return m.pos_lo + int32_t(rintf(q));
 }
 
+// The same stage-2 arithmetic on a row already widened to fp32 (the widening
+// of a bf16 value is exact, so both routines return identical positions).
+__device__ __forceinline__ int32_t position(const float* w2e, const ExpertMeta& m, uint32_t x) {
+    const float v = x >= m.key_lo ? fminf(float(x - m.key_lo) * m.inv_span, 1.0f) : 0.0f;
+    float y = w2e[3 * kSeg];
+#pragma unroll
+    for (uint32_t c = 0; c < kSeg; c += 4) {
+        const float4 a = *reinterpret_cast<const float4*>(w2e + c);
+        const float4 b = *reinterpret_cast<const float4*>(w2e + kSeg + c);
+        const float4 o = *reinterpret_cast<const float4*>(w2e + 2 * kSeg + c);
+        y = fmaf(o.x, fmaxf(fmaf(a.x, v, b.x), 0.0f), y);
+        y = fmaf(o.y, fmaxf(fmaf(a.y, v, b.y), 0.0f), y);
+        y = fmaf(o.z, fmaxf(fmaf(a.z, v, b.z), 0.0f), y);
+        y = fmaf(o.w, fmaxf(fmaf(a.w, v, b.w), 0.0f), y);
+    }
+    const float q = fminf(fmaxf(y * m.pos_span, 0.0f), m.pos_span);  // NaN -> 0
+    return m.pos_lo + int32_t(rintf(q));
+}
+
 // Largest j in [lo, hi] with B[j] <= x, assuming B[lo] <= x.
 __device__ __forceinline__ uint32_t search_le(const uint32_t* B, uint32_t lo, uint32_t hi,
                                               uint32_t x) {
@@ -240,8 +261,9 @@ __device__ __forceinline__ uint32_t search_le(const uint32_t* B, uint32_t lo, ui
 
 // Interval of x: the window [p - err, p + err] of the predicted position first,
 // checked by B[j] <= x < B[j+1]; a miss falls back to the full range.
+template <class W2>
 __device__ __forceinline__ uint32_t locate(const uint32_t* B, uint32_t M, const float* w1,
-                                           const uint16_t* w2, const ExpertMeta* meta, uint32_t E,
+                                           const W2* w2, const ExpertMeta* meta, uint32_t E,
                                            uint32_t use_net, uint32_t x, bool* miss) {
     if (use_net) {
         const uint32_t e = route(w1, E, x);
@@ -289,51 +311,72 @@ __global__ void k_err_bound(LookupArgs a, const uint32_t* __restrict__ keys,
 //   1. locate each packet's destination interval j (network + window, else a
 //      full binary search);
 //   2. scan j's own candidate list per lane (ascending, stop at the first match);
-//   3. scan the shared destination-wildcard list (a grouped scan plan) with
-//      the packet-split wave scan, seeded with step 2's answer, so each lane
-//      keeps the smaller of the two partial first matches;
-//   4. write the index and action.
+//   3. locate the source interval i among the destination-wildcard candidates
+//      that specify a source, and scan i's list per lane the same way (ports
+//      and protocol tested; destination and source are implied);
+//   4. scan the remaining candidates (source and destination both
+//      unspecified, a grouped scan plan) with the packet-split wave scan,
+//      seeded with the best of steps 2-3, so each lane keeps the smallest of
+//      the partial first matches;
+//   5. write the index and action.
 constexpr uint32_t kLearnedBlock = 1024;
 constexpr uint32_t kLearnedK = 2;     // default packets per lane in the classify kernel
 
-__host__ __device__ inline size_t lds_layout(uint32_t E, uint32_t M, bool b_lds, size_t* off_meta,
-                                             size_t* off_w2, size_t* off_b) {
+__host__ __device__ inline size_t lds_layout(uint32_t E, uint32_t M, uint32_t Ms, bool b_lds,
+                                             bool w2_f32, size_t* off_meta, size_t* off_w2,
+                                             size_t* off_b, size_t* off_bs) {
     size_t o = kInferStride * sizeof(float);
     *off_meta = o;
     o += size_t(E) * sizeof(ExpertMeta);
+    o = (o + 15) & ~size_t(15);
     *off_w2 = o;
-    o += size_t(E) * kInferStride * sizeof(uint16_t);
+    o += size_t(E) * kInferStride * (w2_f32 ? sizeof(float) : sizeof(uint16_t));
     o = (o + 15) & ~size_t(15);
     *off_b = o;
     if (b_lds) o += size_t(M) * sizeof(uint32_t);
+    *off_bs = o;
+    if (b_lds) o += size_t(Ms) * sizeof(uint32_t);
     return o;
 }
 
+template <class W2>
 struct IndexView {
     const float* w1;
     const ExpertMeta* meta;
-    const uint16_t* w2;
+    const W2* w2;
     const uint32_t* B;
+    const uint32_t* Bs;
 };
 
-template <bool B_LDS>
-__device__ __forceinline__ IndexView stage_index(const LookupArgs& a, unsigned char* smem) {
-    size_t o_meta, o_w2, o_b;
-    lds_layout(a.E, a.M, B_LDS, &o_meta, &o_w2, &o_b);
+// Stage the index into LDS; stage-2 weights stay bf16 (W2 = uint16_t) or are
+// widened to fp32 (W2 = float) on the way in.
+template <bool B_LDS, class W2>
+__device__ __forceinline__ IndexView<W2> stage_index(const LookupArgs& a, unsigned char* smem) {
+    constexpr bool kF32 = sizeof(W2) == 4;
+    size_t o_meta, o_w2, o_b, o_bs;
+    lds_layout(a.E, a.M, a.Ms, B_LDS, kF32, &o_meta, &o_w2, &o_b, &o_bs);
     float* s_w1 = reinterpret_cast<float*>(smem);
     ExpertMeta* s_meta = reinterpret_cast<ExpertMeta*>(smem + o_meta);
-    uint16_t* s_w2 = reinterpret_cast<uint16_t*>(smem + o_w2);
+    W2* s_w2 = reinterpret_cast<W2*>(smem + o_w2);
     uint32_t* s_b = reinterpret_cast<uint32_t*>(smem + o_b);
+    uint32_t* s_bs = reinterpret_cast<uint32_t*>(smem + o_bs);
     const uint32_t tid = threadIdx.x;
     for (uint32_t k = tid; k < kInferStride; k += kLearnedBlock) s_w1[k] = a.w1[k];
     for (uint32_t k = tid; k < a.E * 8u; k += kLearnedBlock)
         reinterpret_cast<uint32_t*>(s_meta)[k] = reinterpret_cast<const uint32_t*>(a.meta)[k];
-    for (uint32_t k = tid; k < a.E * kInferStride / 2u; k += kLearnedBlock)
-        reinterpret_cast<uint32_t*>(s_w2)[k] = reinterpret_cast<const uint32_t*>(a.w2)[k];
-    if constexpr (B_LDS)
+    if constexpr (kF32) {
+        for (uint32_t k = tid; k < a.E * kInferStride; k += kLearnedBlock)
+            s_w2[k] = bf16_to_f32(a.w2[k]);
+    } else {
+        for (uint32_t k = tid; k < a.E * kInferStride / 2u; k += kLearnedBlock)
+            reinterpret_cast<uint32_t*>(s_w2)[k] = reinterpret_cast<const uint32_t*>(a.w2)[k];
+    }
+    if constexpr (B_LDS) {
         for (uint32_t k = tid; k < a.M; k += kLearnedBlock) s_b[k] = a.B[k];
+        for (uint32_t k = tid; k < a.Ms; k += kLearnedBlock) s_bs[k] = a.Bs[k];
+    }
     __syncthreads();
-    return IndexView{s_w1, s_meta, s_w2, B_LDS ? s_b : a.B};
+    return IndexView<W2>{s_w1, s_meta, s_w2, B_LDS ? s_b : a.B, B_LDS ? s_bs : a.Bs};
 }
 
 // With one or two packets per lane, two work-groups per CU (the LDS footprint
@@ -345,7 +388,10 @@ __global__ __launch_bounds__(kLearnedBlock, K >= 4 ? 4 : 8) void k_learned(Looku
                                                            uint8_t* __restrict__ out_act,
                                                            uint32_t dflt) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const IndexView v = stage_index<B_LDS>(a, smem);
+    // four packets per lane already limit the kernel to one work-group per CU,
+    // so the LDS can hold fp32 expert weights (no widening in the loop)
+    using W2 = typename std::conditional<(K >= 4), float, uint16_t>::type;
+    const IndexView<W2> v = stage_index<B_LDS, W2>(a, smem);
     const uint32_t lane = threadIdx.x & 63u;
     constexpr uint32_t kWaves = kLearnedBlock / 64;   // compile-time: keeps the loop scalar
     const size_t waves = size_t(gridDim.x) * kWaves;
@@ -376,6 +422,21 @@ __global__ __launch_bounds__(kLearnedBlock, K >= 4 ? 4 : 8) void k_learned(Looku
                         break;
                     }
                 }
+                // destination-wildcard candidates with a specified source: the
+                // packet's source interval lists exactly those whose source
+                // test it passes; stop at the first match or past lbest
+                const uint32_t si = search_le(v.Bs, 0, a.Ms - 1u, w.src[s]);
+                const uint32_t sb = a.soff[si], se = a.soff[si + 1u];
+                for (uint32_t k = sb; k < se; ++k) {
+                    const RuleRec q = a.S[k];
+                    if (q.idx > lbest[s]) break;
+                    if (ports_in(w.pp[s], q.port_lo, q.port_w) &&
+                        in_range(w.pr[s], proto_lo(q.proto), proto_w(q.proto))) {
+                        lbest[s] = q.idx;
+                        lact[s] = rule_action(q.proto);
+                        break;
+                    }
+                }
             }
         }
 #pragma unroll
@@ -395,7 +456,7 @@ __global__ __launch_bounds__(kLearnedBlock) void k_lookup(LookupArgs a,
                                                           size_t n,
                                                           int32_t* __restrict__ out_interval) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const IndexView v = stage_index<B_LDS>(a, smem);
+    const IndexView<uint16_t> v = stage_index<B_LDS, uint16_t>(a, smem);
     constexpr uint32_t kWaves = kLearnedBlock / 64;   // compile-time: keeps the loop scalar
     const size_t waves = size_t(gridDim.x) * kWaves;
     const size_t wave0 = size_t(blockIdx.x) * kWaves + wave_in_group();
@@ -504,9 +565,9 @@ hipError_t launch_err_bound(const LookupArgs& a, const uint32_t* keys, const int
     return hipGetLastError();
 }
 
-size_t learned_lds_bytes(const LookupArgs& a, bool b_in_lds) {
-    size_t o1, o2, o3;
-    return lds_layout(a.E, a.M, b_in_lds, &o1, &o2, &o3);
+size_t learned_lds_bytes(const LookupArgs& a, bool b_in_lds, bool w2_f32) {
+    size_t o1, o2, o3, o4;
+    return lds_layout(a.E, a.M, a.Ms, b_in_lds, w2_f32, &o1, &o2, &o3, &o4);
 }
 
 hipError_t launch_learned(const LookupArgs& a, PacketsDev pk, size_t n, int32_t* out_idx,
@@ -524,16 +585,21 @@ hipError_t launch_learned(const LookupArgs& a, PacketsDev pk, size_t n, int32_t*
         if (e != hipSuccess) return e;
         g_cache.device = dev;
     }
-    // keep two work-groups of 16 waves per CU: boundaries in LDS up to 80 KiB in all
-    const size_t with_b = learned_lds_bytes(a, true);
-    const bool b_lds = with_b <= size_t(g_cache.max_lds) && with_b <= 80u * 1024u;
-    const size_t lds = b_lds ? with_b : learned_lds_bytes(a, false);
+    // keep two work-groups of 16 waves per CU: boundary arrays in LDS up to 80 KiB in all
+    const uint32_t K = packets_per_lane ? packets_per_lane : kLearnedK;
+    const bool f32 = !keys && K >= 4;
+    // one or two packets per lane: keep two work-groups of 16 waves per CU, so
+    // the boundary arrays go to LDS only while everything stays within 80 KiB;
+    // four per lane run one work-group per CU and may use up to 150 KiB
+    const size_t budget = f32 ? 150u * 1024u : 80u * 1024u;
+    const size_t with_b = learned_lds_bytes(a, true, f32);
+    const bool b_lds = with_b <= size_t(g_cache.max_lds) && with_b <= budget;
+    const size_t lds = b_lds ? with_b : learned_lds_bytes(a, false, f32);
     if (keys) {
         const size_t tiles = (n + 63) / 64;
         return b_lds ? launch_persistent(k_lookup<true>, lds, tiles, s, a, keys, n, out_interval)
                      : launch_persistent(k_lookup<false>, lds, tiles, s, a, keys, n, out_interval);
     }
-    const uint32_t K = packets_per_lane ? packets_per_lane : kLearnedK;
     const size_t tiles = (n + 64 * K - 1) / (64 * K);
 #define FW_LEARNED(BL, KK) \
     launch_persistent(k_learned<BL, KK>, lds, tiles, s, a, pk, n, out_idx, out_act, dflt)

@@ -220,3 +220,31 @@ def test_memory_budget_leaves_scan_usable():
         idx, act = rs.classify(dp)          # AUTO falls back to the scan
         torch.cuda.synchronize()
         assert_same((idx.cpu().numpy(), act.cpu().numpy()), want, "auto after failed build")
+
+
+@pytest.mark.parametrize("seed,R", [(2, 300), (3, 1000), (1, 10_000)])
+def test_source_lists_match_definition(seed, R):
+    """The destination-wildcard candidates, split by source: for every source interval i of
+    those that specify a source, the entries of S_i together with the fully wildcard list
+    Gw hold every candidate reachable for a packet whose source lies in interval i."""
+    fw = fwmod()
+    rules = gen.make_rules(R, seed, skew=True)
+    with fw.Ruleset(rules) as rs:
+        rs.build_learned_index(**FAST)
+        G = rs.export(3)
+        Bs, soff, S, Gw = rs.export(6), rs.export(7), rs.export(8), rs.export(9)
+    wild_src = rules.src_plen[G] == 0
+    np.testing.assert_array_equal(Gw, G[wild_src])
+    sub = rules.subset(G[~wild_src])
+    np.testing.assert_array_equal(Bs, iv.boundaries(sub, "src"))
+    C = iv.candidates(sub, Bs, "src")
+    # within a source interval every candidate's source test passes: it matches every
+    # packet there once ports and protocol are unspecified
+    full = ((sub.sport_lo == 0) & (sub.sport_hi == 65535) & (sub.dport_lo == 0)
+            & (sub.dport_hi == 65535) & (sub.proto_any != 0))
+    mapped = G[~wild_src]
+    for i in range(len(Bs)):
+        got = S[soff[i]:soff[i + 1]]
+        want = mapped[iv.truncated(C[i], full)]
+        assert set(want.tolist()) <= set(got.tolist()) <= set(mapped[C[i]].tolist()), i
+        assert np.all(np.diff(got.astype(np.int64)) > 0)

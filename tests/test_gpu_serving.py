@@ -36,15 +36,14 @@ def _requests(chains, n_req, seed, max_batch=20_000):
 
 
 def _run(server, reqs):
-    keep, tickets = [], []
+    """Prepare every request's pinned buffers first, then submit them back to back."""
+    keep = []
     for c, pk in reqs:
         bufs = [_pinned(a) for a in (pk.src_ip, pk.dst_ip, pk.sport, pk.dport, pk.proto)]
-        oi = np.empty(len(pk), np.int32)
-        oa = np.empty(len(pk), np.uint8)
-        keep.append((bufs, oi, oa))
-        tickets.append(server.submit(c, *[b[1] for b in bufs], oi, oa))
+        keep.append((c, bufs, np.empty(len(pk), np.int32), np.empty(len(pk), np.uint8)))
+    tickets = [server.submit(c, *[b[1] for b in bufs], oi, oa) for c, bufs, oi, oa in keep]
     times = [server.wait(t) for t in tickets]
-    return [(k[1], k[2]) for k in keep], times
+    return [(k[2], k[3]) for k in keep], times
 
 
 def test_mix_equals_alone_equals_oracle():
