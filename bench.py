@@ -107,17 +107,179 @@ def learned_work(rs, pk, idx, hidden: int = 32):
             "bytes": nbytes, "probes_per_packet": probes}
 
 
+def log(msg: str):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def time_steps(fn, steps: int, warmup: int, stream):
+    """Run fn() `warmup` times, then time exactly `steps` calls with events on `stream`."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record(stream)
+    for _ in range(steps):
+        fn()
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return start.elapsed_time(stop) / steps, wall
+
+
+def closed_loop_latency(rs, dp, mode_kw, seed: int, n_batches: int, stream):
+    """p50/p99 of host-enqueue-to-completion over batches of log-uniform size."""
+    import torch
+    rng = np.random.Generator(np.random.PCG64(seed + 31337))
+    sizes = np.clip(np.round(np.exp(rng.uniform(math.log(64), math.log(65536), n_batches))),
+                    64, 65536).astype(np.int64)
+    starts = rng.integers(0, (len(dp) - 65536) // 16, n_batches) * 16   # 16-byte aligned
+    n = len(dp)
+    out_i = torch.empty(65536, dtype=torch.int32, device="cuda")
+    out_a = torch.empty(65536, dtype=torch.uint8, device="cuda")
+    for i in range(20):                           # warm the path
+        rs.classify(dp.slice(0, 4096), stream=stream, out_idx=out_i, out_act=out_a, **mode_kw)
+    stream.synchronize()
+    lat = np.empty(n_batches)
+    for b in range(n_batches):
+        s, k = int(starts[b]), int(sizes[b])
+        sub = dp.slice(s, min(n, s + k))
+        t0 = time.perf_counter()
+        rs.classify(sub, stream=stream, out_idx=out_i, out_act=out_a, **mode_kw)
+        stream.synchronize()
+        lat[b] = time.perf_counter() - t0
+    return float(np.percentile(lat, 50) * 1e6), float(np.percentile(lat, 99) * 1e6)
+
+
+def serving_leg(seed: int, n_req: int, loads, log_fn):
+    """Open-loop serving: 3 resident chains, Poisson arrivals of log-uniform batches.
+
+    The same trace of request sizes and chains is replayed at each offered
+    load (a fraction of the saturated throughput measured first), through the
+    native load generator; latency is done - scheduled arrival.
+    """
+    import torch
+    from synth import gen
+    from paper_1312_4188_amd import fw
+    chains = gen.serving_chains(seed)
+    rsets = [fw.Ruleset(c) for c in chains]
+    build = []
+    for rs in rsets:
+        t0 = time.perf_counter()
+        st = rs.build_learned_index(seed=seed)
+        build.append({"rules": rs.n_rules, "build_s": time.perf_counter() - t0,
+                      "err_mean": st["err_mean"], "boundaries": st["n_boundaries"]})
+    _, sizes, chain = gen.serving_arrivals(seed, n_req, 1.0, n_chains=len(chains))
+    sizes = (sizes + 15) // 16 * 16                     # 16-byte aligned slices
+    offset = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.uint64)
+    total = int(sizes.sum())
+
+    def pinned(n, dt):
+        t = torch.empty(n, dtype=dt, pin_memory=True)
+        return t, t.numpy()
+    keep, pool = [], []
+    for n_bytes, dt, field in ((4, torch.int32, "src_ip"), (4, torch.int32, "dst_ip"),
+                               (2, torch.int16, "sport"), (2, torch.int16, "dport"),
+                               (1, torch.uint8, "proto")):
+        t, a = pinned(total, dt)
+        keep.append(t)
+        pool.append(a)
+    for k in range(n_req):
+        pk = gen.make_packets(chains[chain[k]], int(sizes[k]), seed * 7919 + k)
+        o, e = int(offset[k]), int(offset[k] + sizes[k])
+        pool[0][o:e] = pk.src_ip.view(np.int32)
+        pool[1][o:e] = pk.dst_ip.view(np.int32)
+        pool[2][o:e] = pk.sport.view(np.int16)
+        pool[3][o:e] = pk.dport.view(np.int16)
+        pool[4][o:e] = pk.proto
+    ti, out_i = pinned(total, torch.int32)
+    ta, out_a = pinned(total, torch.uint8)
+    out = {"chains": build, "requests": n_req, "packets": total, "modes": {}}
+    mean_batch = total / n_req
+    for mode in ("auto", "packet_split"):
+        with fw.Server(rsets, slots=8, mode=mode) as sv:
+            zero = np.zeros(n_req)
+            sv.replay(zero[:32], chain[:32], offset[:32], sizes[:32], pool, out_i, out_a)
+            t = sv.replay(zero, chain, offset, sizes, pool, out_i, out_a)
+            peak = total / (t[:, 2].max() - t[:, 0].min()) / 1e6
+            res = {"peak_mpps": peak, "loads": []}
+            for frac in loads:
+                rate = frac * peak * 1e6 / mean_batch          # requests per second
+                rng = np.random.Generator(np.random.PCG64(seed + int(frac * 1000)))
+                arr = np.cumsum(rng.exponential(1.0 / rate, n_req))
+                t = sv.replay(arr, chain, offset, sizes, pool, out_i, out_a)
+                lat = (t[:, 2] - t[:, 0]) * 1e6
+                span = t[:, 2].max() - t[:, 0].min()
+                res["loads"].append({"offered_frac": frac, "offered_mpps": frac * peak,
+                                     "achieved_mpps": total / span / 1e6,
+                                     "p50_us": float(np.percentile(lat, 50)),
+                                     "p99_us": float(np.percentile(lat, 99))})
+                log_fn(f"  serving {mode} load {frac:.0%}: p50 {res['loads'][-1]['p50_us']:.0f} us "
+                       f"p99 {res['loads'][-1]['p99_us']:.0f} us")
+            out["modes"]["learned" if mode == "auto" else mode] = res
+    for rs in rsets:
+        rs.close()
+    return out
+
+
+def multichain_leg(seed: int, steps: int, log_fn):
+    """64 independent chains (32..8,192 rules, 4,096..1,048,576 packets, log-uniform) in one
+    persistent launch, autotuned, against one packet-split launch per chain."""
+    import torch
+    from synth import gen
+    from paper_1312_4188_amd import fw
+    work = gen.multichain_workload(seed=seed)
+    items, rss = [], []
+    for rules, pk in work:
+        rs = fw.Ruleset(rules)
+        rss.append(rs)
+        n = len(pk)
+        items.append((rs, fw.DevicePackets.from_host(pk),
+                      torch.empty(n, dtype=torch.int32, device="cuda"),
+                      torch.empty(n, dtype=torch.uint8, device="cuda")))
+    total = sum(len(it[1]) for it in items)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    best, tuned_ms = fw.autotune_multi(items)
+    log_fn(f"  multichain autotuned {best} ({tuned_ms:.3f} ms)")
+    configs = {"tuned": {}}
+    for K in (1, 2, 4):
+        configs[f"scalar_k{K}"] = dict(packets_per_lane=K, placement=1)
+        configs[f"lds1024_k{K}"] = dict(packets_per_lane=K, placement=2, rule_tile=1024)
+    out = {"chains": len(items), "packets": total,
+           "rules_total": int(sum(len(r) for r, _ in work)), "tuned": best, "configs": {}}
+    for name, kw in configs.items():
+        ms, _ = time_steps(lambda: fw.classify_multi(items, stream=stream, **kw), steps, 2, stream)
+        out["configs"][name] = {"ms": ms, "mpps": total / ms / 1e3}
+    ref = [(it[2].clone(), it[3].clone()) for it in items]
+
+    def per_chain():
+        for rs, dp, oi, oa in items:
+            rs.classify(dp, mode="packet_split", stream=stream, out_idx=oi, out_act=oa)
+    ms, _ = time_steps(per_chain, steps, 2, stream)
+    out["configs"]["one_launch_per_chain"] = {"ms": ms, "mpps": total / ms / 1e3}
+    torch.cuda.synchronize()
+    out["same_as_per_chain"] = bool(all(torch.equal(a, it[2]) and torch.equal(b, it[3])
+                                        for (a, b), it in zip(ref, items)))
+    for rs in rss:
+        rs.close()
+    return out
+
+
 def cpu_baseline(rules, pk, n_sample: int):
     """The CPU oracle, as it stands, on a bounded sample of the same batch."""
     import oracle
     threads = max(1, min(16, os.cpu_count() or 1))
+    n_sample = min(n_sample, len(pk))
     sub = pk.subset(slice(0, n_sample))
-    t0 = time.perf_counter()
+    t0, c0 = time.perf_counter(), time.process_time()
     oracle.classify(rules, sub, threads=threads)
-    dt = time.perf_counter() - t0
+    dt, cpu = time.perf_counter() - t0, time.process_time() - c0
     return {"value": n_sample / dt / 1e6, "unit": "Mpps", "cores": threads, "kind": "oracle",
             "sample": f"first {n_sample} packets of the timed batch, {threads} threads, "
-                      f"{dt:.2f} s wall"}
+                      f"{dt:.2f} s wall, {cpu:.1f} s CPU"}
 
 
 def main():
@@ -128,7 +290,7 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--workload", default="learned_10000x16M")
     ap.add_argument("--latency-batches", type=int, default=2000)
-    ap.add_argument("--cpu-sample", type=int, default=4_194_304)
+    ap.add_argument("--cpu-sample", type=int, default=16_777_216)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--modes", default="",
                     help="comma list of modes to time (default: all); the first is the headline")

@@ -47,3 +47,33 @@ def test_candidate_checks_match_brute_force():
             brute += int(np.sum(lst <= idx[p])) if idx[p] >= 0 else len(lst)
     assert work["candidate_checks"] == brute
     assert work["lane_ops"] > 2 * brute
+
+
+def test_every_global_name_in_bench_resolves():
+    """Every module-level name the benchmark's functions read is defined (a missing helper
+    would only show at run time on the GPU)."""
+    import builtins
+    import symtable
+    src = open(bench.__file__).read()
+    top = symtable.symtable(src, bench.__file__, "exec")
+    defined = set(vars(bench))
+    missing = []
+
+    def walk(t):
+        for s in t.get_symbols():
+            if s.is_global() and s.is_referenced() and s.get_name() not in defined \
+                    and not hasattr(builtins, s.get_name()):
+                missing.append((t.get_name(), s.get_name()))
+        for c in t.get_children():
+            walk(c)
+    for child in top.get_children():
+        walk(child)
+    assert not missing, missing
+
+
+def test_bench_refuses_several_gpus():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, bench.__file__, "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
