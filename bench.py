@@ -224,6 +224,45 @@ def serving_leg(seed: int, n_req: int, loads, log_fn):
     return out
 
 
+def ingest_leg(rs, pk, ref_idx, chunk: int, log_fn):
+    """The whole batch from pinned host memory through the serving runtime: copied in,
+    classified and copied out in chunks of `chunk` packets.  With 8 slots one chunk's copies
+    overlap other chunks' classification; 1 slot runs them back to back.  PCIe-inclusive
+    rate, reported beside the headline (which starts from HBM-resident packets)."""
+    import torch
+    from paper_1312_4188_amd import fw
+    n = len(pk)
+    pool, keep = [], []
+    for a, dt in ((pk.src_ip, torch.int32), (pk.dst_ip, torch.int32), (pk.sport, torch.int16),
+                  (pk.dport, torch.int16), (pk.proto, torch.uint8)):
+        t = torch.empty(n, dtype=dt, pin_memory=True)
+        v = t.numpy().view(a.dtype)
+        v[:] = a
+        keep.append(t)
+        pool.append(v)
+    ti = torch.empty(n, dtype=torch.int32, pin_memory=True)
+    ta = torch.empty(n, dtype=torch.uint8, pin_memory=True)
+    out_i, out_a = ti.numpy(), ta.numpy()
+    sizes = np.full((n + chunk - 1) // chunk, chunk, dtype=np.uint64)
+    sizes[-1] = n - chunk * (len(sizes) - 1)
+    offset = np.arange(len(sizes), dtype=np.uint64) * np.uint64(chunk)
+    chain = np.zeros(len(sizes), dtype=np.uint32)
+    zero = np.zeros(len(sizes))
+    out = {"packets": n, "chunk": chunk, "bytes_per_packet": BYTES_PER_PACKET}
+    for slots in (1, 8):
+        with fw.Server([rs], slots=slots, mem_budget=1 << 30) as sv:
+            sv.replay(zero[:2], chain[:2], offset[:2], sizes[:2], pool, out_i, out_a)  # warm
+            out_i[:] = -2
+            t = sv.replay(zero, chain, offset, sizes, pool, out_i, out_a)
+            span = float(t[:, 2].max() - t[:, 0].min())
+            out[f"slots_{slots}"] = {"s": span, "mpps": n / span / 1e6,
+                                     "pcie_gbs": n * BYTES_PER_PACKET / span / 1e9,
+                                     "same_as_device": bool(np.array_equal(out_i, ref_idx))}
+            log_fn(f"  ingest {slots} slot(s): {n / span / 1e6:.0f} Mpps "
+                   f"({n * BYTES_PER_PACKET / span / 1e9:.1f} GB/s over PCIe)")
+    return out
+
+
 def multichain_leg(seed: int, steps: int, log_fn):
     """64 independent chains (32..8,192 rules, 4,096..1,048,576 packets, log-uniform) in one
     persistent launch, autotuned, against one packet-split launch per chain."""
@@ -247,6 +286,7 @@ def multichain_leg(seed: int, steps: int, log_fn):
     configs = {"tuned": {}}
     for K in (1, 2, 4):
         configs[f"scalar_k{K}"] = dict(packets_per_lane=K, placement=1)
+        configs[f"vector_k{K}"] = dict(packets_per_lane=K, placement=3)
         configs[f"lds1024_k{K}"] = dict(packets_per_lane=K, placement=2, rule_tile=1024)
     out = {"chains": len(items), "packets": total,
            "rules_total": int(sum(len(r) for r, _ in work)), "tuned": best, "configs": {}}
@@ -297,6 +337,8 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=600,
                     help="requests per offered load in the serving leg (0 = skip it)")
     ap.add_argument("--no-multichain", action="store_true", help="skip the 64-chain leg")
+    ap.add_argument("--no-ingest", action="store_true",
+                    help="skip the PCIe-inclusive leg (whole batch from pinned host memory)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (for scaling HBM counters)")
     args = ap.parse_args()
@@ -411,6 +453,11 @@ def main():
         serving = serving_leg(args.seed, args.serving_requests,
                               (0.1, 0.3, 0.5, 0.7, 0.9, 1.0, 1.2), log)
 
+    ingest = None
+    if not args.no_ingest:
+        log("ingest leg: whole batch from pinned host memory")
+        ingest = ingest_leg(rs, pk, ref, 1 << 20, log)
+
     multichain = None
     if not args.no_multichain:
         log("multi-chain leg")
@@ -438,7 +485,7 @@ def main():
         "scan_rule_checks": checks, "learned_candidate_checks": work["candidate_checks"],
         "index": index_stats, "index_untrained": untrained_stats,
         "roofline": roofline, "scan_roofline": scan_roofline, "serving": serving,
-        "multichain": multichain,
+        "multichain": multichain, "ingest": ingest,
         "cpu_baseline": cpu,
     }
     rs.close()

@@ -12,11 +12,13 @@
  *  - packet split: every GPU lane owns whole packets and walks the whole
  *    rule list (the paper's data-parallel firewall, Section IV-A: each node
  *    holds a duplicate of the policy, each packet goes to one node);
- *  - rule split: the rule list is cut into P contiguous partitions, the lanes
- *    of one packet each scan one partition, and the partial first matches are
- *    merged by a minimum over rule indices (the paper's function-parallel
- *    firewall, Section IV-B, where each node holds a part of the policy; the
- *    paper merges on the CPU, here the merge runs on the GPU);
+ *  - rule split: the rule list is cut into P contiguous partitions, one wave
+ *    per partition and group of 8 packets holds 64 of its rules in its lanes,
+ *    and the partial first matches are merged by a minimum over rule indices,
+ *    within the wave by a cross-lane reduction and across partitions by an
+ *    atomic minimum (the paper's function-parallel firewall, Section IV-B,
+ *    where each node holds a part of the policy; the paper merges on the CPU,
+ *    here the merge runs on the GPU);
  *  - learned index: a small network trained on the rule list's destination
  *    interval boundaries locates each packet's destination interval, and
  *    only that interval's exact candidate rules are scanned.  Not in the
@@ -272,7 +274,8 @@ typedef struct fw_multi_opts {
     void *stream;              /* hipStream_t; NULL = null stream */
     uint32_t packets_per_lane; /* 1, 2 or 4; 0 = tuned choice for this batch shape, else 4 */
     uint32_t placement;        /* 0 = tuned (else scalar), 1 = rules through the scalar
-                                  cache, 2 = rules staged in LDS tiles */
+                                  cache, 2 = rules staged in LDS tiles, 3 = rules read
+                                  by vector loads (every lane the same address) */
     uint32_t rule_tile;        /* LDS tile in rules: 256 or 1024; 0 = tuned or 1024 */
     uint32_t _reserved;
 } fw_multi_opts;

@@ -212,8 +212,11 @@ fw_status fw_classify_ex(const fw_ruleset* rs, const fw_packets* pk, size_t n,
                                     o.packets_per_lane ? int(o.packets_per_lane) : 4, stream);
             break;
         case FW_MODE_RULE_SPLIT:
-            e = launch_rule_split(rs->d_rules, rs->n_rules, P, pd, n, out_rule_idx, out_action,
-                                  rs->default_action, stream);
+            // rules past the first catch-all can never be a first match
+            e = launch_rule_split(rs->d_rules,
+                                  rs->plan.plan.tail_idx == kNoMatch ? rs->n_rules
+                                                                     : rs->plan.plan.tail_idx + 1u,
+                                  P, pd, n, out_rule_idx, out_action, rs->default_action, stream);
             break;
         case FW_MODE_HYBRID:
             e = launch_hybrid(rs->d_pairs, rs->d_rules, rs->n_rules, P, pd, n, out_rule_idx,

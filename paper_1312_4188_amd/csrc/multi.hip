@@ -4,10 +4,12 @@
 // Work items are tiles of one chain's packets.  Chains are ordered by an
 // estimate of their cost (rules x packets, largest first) so the expensive
 // items are handed out first; resident work-groups take items from a global
-// counter until none are left, so uneven chains balance themselves.  Two rule
-// placements: records read through the scalar cache (each wave takes its own
-// 64*K-packet items), or records staged into LDS tiles shared by the four
-// waves of a work-group (items of 256*K packets).  The autotuner times the
+// counter until none are left, so uneven chains balance themselves.  Three
+// rule placements (the paper's Section IV-A compares global, constant and
+// shared memory for the rule table): records read through the scalar cache
+// into SGPRs (each wave takes its own 64*K-packet items), the same records
+// read by vector loads into VGPRs, or records staged into LDS tiles shared by
+// the four waves of a work-group (items of 256*K packets).  The autotuner times the
 // packets-per-lane x placement grid on the caller's own batches and caches
 // the fastest choice per batch shape.
 #include <algorithm>
@@ -92,6 +94,28 @@ __global__ __launch_bounds__(256) void k_multi_scalar(const ChainDesc* __restric
     }
 }
 
+// Vector placement: as the scalar placement, but every rule operand is read
+// by vector loads (all lanes the same address) and held in VGPRs.
+template <int K>
+__global__ __launch_bounds__(256) void k_multi_vector(const ChainDesc* __restrict__ cd,
+                                                      uint32_t n_chains, uint32_t total_items,
+                                                      uint32_t* __restrict__ counter) {
+    const uint32_t lane = threadIdx.x & 63u;
+    for (;;) {
+        uint32_t item = 0;
+        if (lane == 0) item = atomicAdd(counter, 1u);
+        item = __builtin_amdgcn_readfirstlane(item);
+        if (item >= total_items) break;
+        const ChainDesc& c = cd[chain_of(cd, n_chains, item)];
+        const size_t first = size_t(item - c.item_begin) * (64u * K);
+        const PacketsDev pk{c.src, c.dst, c.sport, c.dport, c.proto};
+        WaveScan<K> w;
+        w.init(pk, first, c.n, c.dflt);
+        w.scan_vector(c.pairs, c.rules, c.n_rules);
+        w.store(c.out_idx, c.out_act, c.n);
+    }
+}
+
 // LDS placement: a work-group takes 256*K-packet items; rule tiles of TILE
 // records are staged into LDS and scanned by all four waves, until every
 // wave's packets have matched or the rules run out.
@@ -132,7 +156,8 @@ __global__ __launch_bounds__(256) void k_multi_lds(const ChainDesc* __restrict__
 
 struct Config {
     int K = 4;
-    uint32_t tile = 0;   // 0 = scalar placement
+    uint32_t tile = 0;     // LDS tile in rules; 0 = records read from global memory
+    bool vector = false;   // with tile 0: vector loads instead of scalar loads
 };
 
 std::mutex g_tune_mu;
@@ -217,7 +242,11 @@ hipError_t run(const fw_chain_batch* b, uint32_t n_chains, Config cfg, hipStream
             e = hipGetLastError();                                                       \
         }                                                                                \
     } while (0)
-    if (cfg.tile == 0) {
+    if (cfg.tile == 0 && cfg.vector) {
+        if (cfg.K == 1) FW_MULTI(k_multi_vector<1>);
+        else if (cfg.K == 2) FW_MULTI(k_multi_vector<2>);
+        else FW_MULTI(k_multi_vector<4>);
+    } else if (cfg.tile == 0) {
         if (cfg.K == 1) FW_MULTI(k_multi_scalar<1>);
         else if (cfg.K == 2) FW_MULTI(k_multi_scalar<2>);
         else FW_MULTI(k_multi_scalar<4>);
@@ -260,7 +289,7 @@ fw_status resolve(const fw_chain_batch* b, uint32_t n, const fw_multi_opts& o, C
     if (o.packets_per_lane != 0 && o.packets_per_lane != 1 && o.packets_per_lane != 2 &&
         o.packets_per_lane != 4)
         return fail(FW_E_INVAL, "packets_per_lane must be 0, 1, 2 or 4");
-    if (o.placement > 2) return fail(FW_E_INVAL, "placement must be 0, 1 or 2");
+    if (o.placement > 3) return fail(FW_E_INVAL, "placement must be 0, 1, 2 or 3");
     if (o.rule_tile != 0 && o.rule_tile != 256 && o.rule_tile != 1024)
         return fail(FW_E_INVAL, "rule_tile must be 0, 256 or 1024");
     Config c;
@@ -270,8 +299,14 @@ fw_status resolve(const fw_chain_batch* b, uint32_t n, const fw_multi_opts& o, C
         if (it != g_tuned.end()) c = it->second;
     }
     if (o.packets_per_lane) c.K = int(o.packets_per_lane);
-    if (o.placement == 1) c.tile = 0;
-    if (o.placement == 2) c.tile = o.rule_tile ? o.rule_tile : (c.tile ? c.tile : 1024u);
+    if (o.placement == 1 || o.placement == 3) {
+        c.tile = 0;
+        c.vector = o.placement == 3;
+    }
+    if (o.placement == 2) {
+        c.tile = o.rule_tile ? o.rule_tile : (c.tile ? c.tile : 1024u);
+        c.vector = false;
+    }
     *cfg = c;
     return FW_OK;
 }
@@ -307,10 +342,12 @@ fw_status fw_autotune_multi(const fw_chain_batch* batches, uint32_t n_chains, vo
     if (e == hipSuccess) e = hipEventCreate(&z);
     Config win;
     float win_ms = -1.0f;
+    const Config placements[] = {{4, 0u, false}, {4, 0u, true}, {4, 256u, false},
+                                 {4, 1024u, false}};
     for (int K : {1, 2, 4}) {
-        for (uint32_t tile : {0u, 256u, 1024u}) {
+        for (Config c : placements) {
             if (e != hipSuccess) break;
-            const Config c{K, tile};
+            c.K = K;
             e = run(batches, n_chains, c, s);   // warm-up
             float ms_best = -1.0f;
             for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
@@ -339,7 +376,7 @@ fw_status fw_autotune_multi(const fw_chain_batch* batches, uint32_t n_chains, vo
         std::memset(best, 0, sizeof *best);
         best->stream = stream;
         best->packets_per_lane = uint32_t(win.K);
-        best->placement = win.tile ? 2u : 1u;
+        best->placement = win.tile ? 2u : (win.vector ? 3u : 1u);
         best->rule_tile = win.tile;
     }
     if (best_ms) *best_ms = win_ms;

@@ -37,103 +37,92 @@ __global__ __launch_bounds__(kScanBlock) void k_packet_split(ScanPlan plan, Pack
 }
 
 // ------------------------------------------------------------------ rule split
-// Minimum over the LP lanes of one packet group, with DPP lane permutations
-// (quad swaps, half-row and row mirrors), one swizzle across the two rows of a
-// 32-lane half, and a readlane pair across the halves.  Every lane of the
-// group receives the minimum.  Must be called with the whole wave active.
-template <int LP>
-__device__ __forceinline__ uint32_t group_min(uint32_t v) {
-    if constexpr (LP >= 2)   // quad_perm [1,0,3,2]
-        v = umin(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0xB1, 0xF, 0xF, false)));
-    if constexpr (LP >= 4)   // quad_perm [2,3,0,1]
-        v = umin(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x4E, 0xF, 0xF, false)));
-    if constexpr (LP >= 8)   // row_half_mirror: lane i <-> 7 - i within each half row
-        v = umin(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x141, 0xF, 0xF, false)));
-    if constexpr (LP >= 16)  // row_mirror: lane i <-> 15 - i within each row
-        v = umin(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x140, 0xF, 0xF, false)));
-    if constexpr (LP >= 32)  // swizzle, bit mode: lane ^ 16 within each 32-lane half
-        v = umin(v, uint32_t(__builtin_amdgcn_ds_swizzle(int(v), 0x401F)));
-    if constexpr (LP >= 64) {
-        const uint32_t a = __builtin_amdgcn_readlane(int(v), 0);
-        const uint32_t b = __builtin_amdgcn_readlane(int(v), 32);
-        v = umin(a, b);
-    }
-    return v;
+// Minimum over the 64 lanes of a wave, with DPP lane permutations (quad
+// swaps, half-row and row mirrors), one swizzle across the two rows of each
+// 32-lane half and a readlane pair across the halves; every lane receives it.
+// Must be called with the whole wave active.
+__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
+    v = umin(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0xB1, 0xF, 0xF, false)));   // quad_perm [1,0,3,2]
+    v = umin(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x4E, 0xF, 0xF, false)));   // quad_perm [2,3,0,1]
+    v = umin(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x141, 0xF, 0xF, false)));  // row_half_mirror
+    v = umin(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x140, 0xF, 0xF, false)));  // row_mirror
+    v = umin(v, uint32_t(__builtin_amdgcn_ds_swizzle(int(v), 0x401F)));                     // lane ^ 16
+    return umin(uint32_t(__builtin_amdgcn_readlane(int(v), 0)),
+                uint32_t(__builtin_amdgcn_readlane(int(v), 32)));
 }
 
+// All five tests without short-circuit branches: each compare yields a lane
+// mask and the masks are combined, so the lanes never diverge.
 __device__ __forceinline__ bool full_match(const RuleRec& q, uint32_t src, uint32_t dst,
                                            uint32_t pp, uint32_t pr) {
-    return in_range(dst, q.dst_lo, q.dst_w) && in_range(src, q.src_lo, q.src_w) &&
-           ports_in(pp, q.port_lo, q.port_w) && in_range(pr, proto_lo(q.proto), proto_w(q.proto));
+    return (unsigned(in_range(dst, q.dst_lo, q.dst_w)) & unsigned(in_range(src, q.src_lo, q.src_w)) &
+            unsigned(ports_in(pp, q.port_lo, q.port_w)) &
+            unsigned(in_range(pr, proto_lo(q.proto), proto_w(q.proto)))) != 0u;
 }
 
-// Lane = (packet slot, partition).  LP lanes share one packet; lane `sub` of a
-// slot scans partition blk*64 + sub, i.e. rules [part*S, min(R, part*S + S)).
-// A lane stops at its partition's first match.  Every kPrune rules the group
-// minimum is taken again and lanes whose next rule lies beyond it stop: no
-// later find could win.  With more than 64 partitions a packet spans
-// `wpp` waves whose minima meet through atomicMin on the 32-bit index.
-constexpr int kPrune = 8;
+// Function-parallel scan (paper Section IV-B): every firewall node holds a
+// part of the policy and sees every packet.  A node here is a wave holding
+// partition p, the rules [p*S, min(R, (p+1)*S)); its 64 lanes take 64 of them
+// at a time into registers, and kRsPackets packets at a time are broadcast to
+// all lanes through scalar registers, so each vector test checks one packet
+// against 64 rules.  A packet is finished in this partition at the first
+// 64-rule chunk where any lane matches; the partition's first match is the
+// wave minimum (DPP) of the lanes' matches, and the partitions meet through
+// atomicMin on the 32-bit index (0xFFFFFFFF = none).
+constexpr uint32_t kRsPackets = 8;
 
-template <int LP>
 __global__ __launch_bounds__(kScanBlock) void k_rule_split(const RuleRec* __restrict__ rules,
-                                                    uint32_t n_rules, uint32_t P, uint32_t S,
-                                                    uint32_t wpp, PacketsDev pk, size_t n,
-                                                    int32_t* __restrict__ out_idx,
-                                                    uint8_t* __restrict__ out_act,
-                                                    uint32_t dflt, int use_atomic) {
+                                                          uint32_t n_rules, uint32_t P,
+                                                          uint32_t S, PacketsDev pk, size_t n,
+                                                          uint32_t* __restrict__ idx) {
     const uint32_t lane = threadIdx.x & 63u;
     const size_t wave = size_t(blockIdx.x) * (kScanBlock / 64) + wave_in_group();
-    const size_t group = wave / wpp;
-    const uint32_t blk = uint32_t(wave % wpp);
-    const uint32_t slot = lane / LP, sub = lane % LP;
-    const size_t i = group * (64u / LP) + slot;
-    if (group * (64u / LP) >= n) return;  // wave-uniform
-    const uint32_t part = blk * 64u + sub;
-    const bool valid = i < n && part < P;
+    const uint32_t part = uint32_t(wave % P);
+    const size_t p0 = (wave / P) * kRsPackets;
+    if (p0 >= n) return;  // wave-uniform
+    const uint64_t b64 = uint64_t(part) * S;
+    const uint32_t begin = uint32_t(b64 < n_rules ? b64 : n_rules);
+    const uint32_t end = uint32_t(b64 + S < n_rules ? b64 + S : n_rules);
+    if (begin >= end) return;  // empty partition
 
-    uint32_t src = 0, dst = 0, pp = 0, pr = 0;
-    if (i < n) {
-        src = pk.src[i];
-        dst = pk.dst[i];
-        pp = (uint32_t(pk.sport[i]) << 16) | pk.dport[i];
-        pr = pk.proto[i];
-    }
-    const uint64_t r0 = valid ? uint64_t(part) * S : 0;
-    const uint32_t begin = uint32_t(r0 < n_rules ? r0 : n_rules);
-    const uint32_t end = uint32_t(r0 + S < n_rules ? r0 + S : n_rules);
-    uint32_t r = begin;
-    bool done = !valid || begin >= end;
-    uint32_t best = kNoMatch;
-
-    for (;;) {
+    // the packets, one per lane, then broadcast one at a time
+    const size_t mine = p0 + (lane < kRsPackets ? lane : 0u);
+    const bool have = lane < kRsPackets && mine < n;
+    const uint32_t v_src = have ? pk.src[mine] : 0u, v_dst = have ? pk.dst[mine] : 0u;
+    const uint32_t v_pp = have ? ((uint32_t(pk.sport[mine]) << 16) | pk.dport[mine]) : 0u;
+    const uint32_t v_pr = have ? uint32_t(pk.proto[mine]) : 0u;
+    uint32_t src[kRsPackets], dst[kRsPackets], pp[kRsPackets], pr[kRsPackets];
+    uint32_t done = 0;
 #pragma unroll
-        for (int t = 0; t < kPrune; ++t) {
-            if (!done) {
-                if (r >= end) {
-                    done = true;
-                } else {
-                    const RuleRec q = rules[r];
-                    if (full_match(q, src, dst, pp, pr)) {
-                        best = r;
-                        done = true;
-                    }
-                    ++r;
-                }
-            }
-        }
-        const uint32_t gm = group_min<LP>(best);
-        if (gm < r) done = true;
-        if (ballot(!done) == 0) break;
+    for (uint32_t g = 0; g < kRsPackets; ++g) {
+        src[g] = __builtin_amdgcn_readlane(int(v_src), int(g));
+        dst[g] = __builtin_amdgcn_readlane(int(v_dst), int(g));
+        pp[g] = __builtin_amdgcn_readlane(int(v_pp), int(g));
+        pr[g] = __builtin_amdgcn_readlane(int(v_pr), int(g));
+        if (p0 + g >= n) done |= 1u << g;
     }
-    const uint32_t gm = group_min<LP>(best);
-    if (sub == 0 && i < n) {
-        if (use_atomic) {
-            atomicMin(reinterpret_cast<uint32_t*>(out_idx) + i, gm);
-        } else {
-            out_idx[i] = int32_t(gm);
-            out_act[i] = uint8_t(gm == kNoMatch ? dflt : rule_action(rules[gm].proto));
+    const uint32_t all = (1u << kRsPackets) - 1u;
+    uint32_t best[kRsPackets];
+#pragma unroll
+    for (uint32_t g = 0; g < kRsPackets; ++g) best[g] = kNoMatch;
+
+    for (uint32_t k = begin; k < end && done != all; k += 64u) {
+        const uint32_t r = k + lane;
+        const bool ok = r < end;
+        const RuleRec q = rules[ok ? r : begin];
+#pragma unroll
+        for (uint32_t g = 0; g < kRsPackets; ++g) {
+            if ((done >> g) & 1u) continue;  // wave-uniform
+            const bool m = (unsigned(ok) & unsigned(full_match(q, src[g], dst[g], pp[g], pr[g]))) != 0u;
+            if (m) best[g] = r;              // at most one chunk per packet matches
+            if (ballot(m) != 0) done |= 1u << g;
         }
+    }
+#pragma unroll
+    for (uint32_t g = 0; g < kRsPackets; ++g) {
+        if (p0 + g >= n) break;
+        const uint32_t m = wave_min(best[g]);
+        if (lane == 0 && m != kNoMatch) atomicMin(idx + p0 + g, m);
     }
 }
 
@@ -224,36 +213,18 @@ hipError_t launch_rule_split(const RuleRec* rules, uint32_t n_rules, uint32_t P,
                              size_t n, int32_t* out_idx, uint8_t* out_act,
                              uint8_t default_action, hipStream_t stream) {
     if (n == 0) return hipSuccess;
-    constexpr uint32_t kBlock = kScanBlock;
-    const uint32_t S = n_rules == 0 ? 1u : ceil_div(n_rules, P);
-    uint32_t LP = 1;
-    while (LP < P && LP < 64) LP <<= 1;
-    const uint32_t wpp = P > 64 ? ceil_div(P, 64) : 1u;
-    const uint64_t groups = (n + (64 / LP) - 1) / (64 / LP);
-    const uint64_t waves = groups * wpp;
-    const uint32_t grid = ceil_div(waves * 64, kBlock);
-    const int atomic = wpp > 1;
-    if (atomic) {
-        hipLaunchKernelGGL(k_fill_u32, dim3(ceil_div(n, 256)), dim3(256), 0, stream,
-                           reinterpret_cast<uint32_t*>(out_idx), n, kNoMatch);
+    hipLaunchKernelGGL(k_fill_u32, dim3(ceil_div(n, 256)), dim3(256), 0, stream,
+                       reinterpret_cast<uint32_t*>(out_idx), n, kNoMatch);
+    if (n_rules > 0) {
+        const uint32_t S = ceil_div(n_rules, P);
+        const uint64_t waves = uint64_t(P) * ((n + kRsPackets - 1) / kRsPackets);
+        const uint64_t blocks = (waves + (kScanBlock / 64) - 1) / (kScanBlock / 64);
+        if (blocks > 0x7FFFFFFFull) return hipErrorInvalidConfiguration;
+        hipLaunchKernelGGL(k_rule_split, dim3(uint32_t(blocks)), dim3(kScanBlock), 0, stream,
+                           rules, n_rules, P, S, pk, n, reinterpret_cast<uint32_t*>(out_idx));
     }
-#define FW_RS(L)                                                                          \
-    hipLaunchKernelGGL(k_rule_split<L>, dim3(grid), dim3(kBlock), 0, stream, rules, n_rules, \
-                       P, S, wpp, pk, n, out_idx, out_act, uint32_t(default_action), atomic)
-    switch (LP) {
-        case 1: FW_RS(1); break;
-        case 2: FW_RS(2); break;
-        case 4: FW_RS(4); break;
-        case 8: FW_RS(8); break;
-        case 16: FW_RS(16); break;
-        case 32: FW_RS(32); break;
-        default: FW_RS(64); break;
-    }
-#undef FW_RS
-    if (atomic) {
-        hipLaunchKernelGGL(k_apply_action, dim3(ceil_div(n, 256)), dim3(256), 0, stream, rules,
-                           out_idx, n, out_act, uint32_t(default_action));
-    }
+    hipLaunchKernelGGL(k_apply_action, dim3(ceil_div(n, 256)), dim3(256), 0, stream, rules,
+                       out_idx, n, out_act, uint32_t(default_action));
     return hipGetLastError();
 }
 

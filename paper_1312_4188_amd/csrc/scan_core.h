@@ -99,6 +99,24 @@ static_assert(kPairPadding >= kPairBlock, "pair arrays must be padded by a whole
 // done after 2K vector ops (3K for the port pair).  Otherwise the full record
 // is read and the remaining fields are tested the same way; matched lanes
 // take the rule through a select on the wave mask itself.
+// Load through the vector memory path even when the address is wave-uniform:
+// the empty asm moves the pointer into VGPRs, so the compiler can no longer
+// use a scalar load.  Every lane reads the same bytes (one cache line per
+// wave); the value lands in a VGPR.
+template <class T>
+__device__ __forceinline__ T vector_load(const T* p) {
+    static_assert(sizeof(T) % 8 == 0 && alignof(T) >= 8, "whole 8-byte words");
+    asm volatile("" : "+v"(p));
+    using Word = const __attribute__((address_space(1))) uint64_t;   // global memory
+    Word* g = (Word*)__builtin_assume_aligned(p, 8);
+    uint64_t w[sizeof(T) / 8];
+#pragma unroll
+    for (size_t i = 0; i < sizeof(T) / 8; ++i) w[i] = g[i];
+    T out;
+    __builtin_memcpy(&out, w, sizeof(T));
+    return out;
+}
+
 template <int K>
 struct WaveScan {
     uint32_t src[K], dst[K], pp[K], pr[K];
@@ -232,6 +250,52 @@ struct WaveScan {
             if (live_any == 0) return false;
         }
         return true;
+    }
+
+    // The same first-match scan with the rule operands read by vector loads
+    // (every lane the same address) instead of scalar loads: the pairs of
+    // the next block of 8 rules are fetched while the current block is
+    // tested, as in scan(), but they arrive in VGPRs through the vector
+    // cache.  Destination-first, rule index = position.
+    __device__ __forceinline__ bool scan_vector(const uint2* __restrict__ first,
+                                                const RuleRec* __restrict__ rules,
+                                                uint32_t count) {
+        if (live_any == 0) return false;
+        uint32_t r = 0;
+        if (count >= kPairBlock) {
+            uint2 cur[kPairBlock];
+#pragma unroll
+            for (uint32_t u = 0; u < kPairBlock; ++u) cur[u] = vector_load(first + u);
+            for (; r + kPairBlock <= count; r += kPairBlock) {
+                uint2 nxt[kPairBlock];
+#pragma unroll
+                for (uint32_t u = 0; u < kPairBlock; ++u)
+                    nxt[u] = vector_load(first + r + kPairBlock + u);
+#pragma unroll
+                for (uint32_t u = 0; u < kPairBlock; ++u) vector_step(cur[u], rules, r + u);
+                if (live_any == 0) return false;
+#pragma unroll
+                for (uint32_t u = 0; u < kPairBlock; ++u) cur[u] = nxt[u];
+            }
+        }
+        for (; r < count; ++r) {
+            vector_step(vector_load(first + r), rules, r);
+            if (live_any == 0) return false;
+        }
+        return true;
+    }
+
+    __device__ __forceinline__ void vector_step(uint2 f, const RuleRec* __restrict__ rules,
+                                                uint32_t r) {
+        uint64_t c[K];
+        uint64_t any = 0;
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            c[s] = ballot(first_test<FirstField::Dst>(s, f));
+            any |= c[s];
+        }
+        if (__builtin_expect((any & live_any) != 0, 0))
+            finish<FirstField::Dst, false>(c, vector_load(rules + r), r);
     }
 
     // Grouped scan (ScanPlan).  The catch-all tail seeds every valid lane's
