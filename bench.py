@@ -82,29 +82,36 @@ def learned_work(rs, pk, idx, hidden: int = 32):
 
     Candidate checks of packet p: the entries of its destination interval's
     list, of its source interval's list (destination-wildcard rules that
-    specify a source) and of the fully wildcard shared list, each up to and
-    including p's first match (all of them when nothing matches).  Lane-ops:
-    2 per candidate check (one subtract, one compare: the first field test),
-    6H per packet for the two networks (per hidden unit a multiply-add, a max
-    and a multiply-add, in each stage) and 2 per binary-search probe (the mean
-    error window, plus the source-interval search).  Bytes: the packet in, the
-    result out, and a 32-byte record gathered per check of a per-lane list.
+    specify a source) and of the address-wildcard rules past the first 64 (the
+    grouped scan), each up to and including p's first match (all of them when
+    nothing matches).  Lane-ops: 2 per candidate check (one subtract, one
+    compare: the first field test); 6H per packet for the two networks (per
+    hidden unit a multiply-add, a max and a multiply-add, in each stage); 2 per
+    binary-search probe (the mean error window, plus the source-interval
+    search); for the port/protocol table of the first 64 address-wildcard
+    rules, 2 per table read (the two high-byte tables, the walk steps, three
+    masks, the rule entry) and 3 for combining the masks (two ANDs, one bit
+    scan).  Bytes: the packet in, the result out, and a 32-byte record
+    gathered per check of a per-lane list.
     """
     e = lambda w: rs.export(w).astype(np.int64)
     B, off, L, err = e(0), e(1), e(2), rs.export(4).astype(np.float64)
     Bs, soff, S, Gw = e(6), e(7), e(8), e(9)
+    pt_count, steps_s, steps_d = (int(x) for x in rs.export(11))
+    rest = Gw[pt_count:]                 # the table holds the first pt_count entries
     ans = np.where(idx < 0, 1 << 40, idx.astype(np.int64))
     n_l = _list_checks(B, off, L, pk.dst_ip.astype(np.int64), ans)
     n_s = _list_checks(Bs, soff, S, pk.src_ip.astype(np.int64), ans)
-    n_g = np.searchsorted(Gw, ans, side="right")
+    n_g = np.searchsorted(rest, ans, side="right")
     checks = int(n_l.sum() + n_s.sum() + n_g.sum())
     probes = (math.ceil(math.log2(2.0 * float(err.mean()) + 1.0)) + 1
               + math.ceil(math.log2(max(len(Bs), 1))) + 1)
-    ops = 2 * checks + len(pk) * (6 * hidden + 2 * probes)
+    table_ops = (2 * (2 + steps_s + steps_d + 4) + 3) if pt_count else 0
+    ops = 2 * checks + len(pk) * (6 * hidden + 2 * probes + table_ops)
     gathered = int(n_l.sum() + n_s.sum())
     nbytes = len(pk) * BYTES_PER_PACKET + gathered * RECORD_BYTES
     return {"candidate_checks": checks, "list_checks": gathered, "lane_ops": ops,
-            "bytes": nbytes, "probes_per_packet": probes}
+            "bytes": nbytes, "probes_per_packet": probes, "table_ops_per_packet": table_ops}
 
 
 def log(msg: str):
@@ -402,6 +409,23 @@ def main():
             results[name]["window_misses"] = miss
         log(f"  {name}: {ms:.3f} ms/step, {n / ms / 1e3:.1f} Mpps")
     ref = ref[0]
+
+    # what the trained network gains: window width, interval lookup alone, end to end
+    gain = {}
+    if "learned" in results:
+        M = index_stats["n_boundaries"]
+        variants = (("trained", rs, 0, index_stats, "learned"),
+                    ("untrained", rs_un, 0, untrained_stats, "learned_untrained"),
+                    ("no_network", rs, 1, index_stats, "learned_binary_search"))
+        for name, ruleset, lookup, st, mode in variants:
+            ms_l, _ = time_steps(lambda: ruleset.lookup_intervals(dp.dst_ip, lookup=lookup,
+                                                                  stream=stream),
+                                 args.steps, args.warmup, stream)
+            gain[name] = {"mean_window": (2 * st["err_mean"] + 1) if lookup == 0 else M,
+                          "lookup_ns_per_packet": ms_l * 1e6 / n,
+                          "mpps": results.get(mode, {}).get("mpps")}
+            log(f"  lookup {name}: {ms_l * 1e6 / n:.4f} ns/packet")
+        gain["scan"] = {"mpps": results.get("packet_split", {}).get("mpps")}
     checks = int(np.where(ref < 0, R, ref.astype(np.int64) + 1).sum())
     for name in [m for m in ("packet_split", "rule_split_p16", "hybrid_p16") if m in results]:
         results[name]["rule_checks_per_s"] = checks / (results[name]["ms"] * 1e-3)
@@ -483,7 +507,7 @@ def main():
         "p50_us": latency.get(head, {}).get("p50_us"),
         "modes": results, "latency": latency,
         "scan_rule_checks": checks, "learned_candidate_checks": work["candidate_checks"],
-        "index": index_stats, "index_untrained": untrained_stats,
+        "index": index_stats, "index_untrained": untrained_stats, "network_gain": gain,
         "roofline": roofline, "scan_roofline": scan_roofline, "serving": serving,
         "multichain": multichain, "ingest": ingest,
         "cpu_baseline": cpu,

@@ -225,7 +225,16 @@ fw_status fw_index_lookup(const fw_ruleset *rs, const uint32_t *keys, size_t n,
  *  7 = their per-source-interval list offsets (uint32, count of 6 + 1);
  *  8 = their per-source-interval list entries (uint32 rule indices);
  *  9 = the candidates with source and destination both unspecified (uint32
- *      rule indices), scanned by every packet.
+ *      rule indices), tested for every packet: the first 64 that are not
+ *      catch-alls through a port/protocol bit-vector table, the rest by a scan;
+ * 10 = that table as bytes: uint64 protocol masks [256], source-port interval
+ *      masks [130], destination-port interval masks [130], uint32 interval
+ *      starts per port field [132] each (unused entries 0x10000), uint32 rule
+ *      entries [68] (rule index | action << 24, 0xFFFFFFFF = none), uint8
+ *      high-byte tables [256] per port field (source first); bit r of a mask
+ *      stands for the table's r-th rule;
+ * 11 = the table's shape (uint32 [3]: rules in it, walk steps per source port,
+ *      per destination port).
  * Lists 2, 8 and 9 are cut where no later entry can be a first match (after a
  * rule that matches every packet reaching the list, and past the shared
  * list's first catch-all).
@@ -243,14 +252,16 @@ fw_status fw_index_export(const fw_ruleset *rs, uint32_t what, void *host, size_
  * pointers are HOST memory; the call copies in, runs forward and backward on
  * the device (with bf16 MFMA weight-gradient products when use_mfma != 0)
  * and copies the gradient (E * (3H + 1) floats) and per-network loss (E
- * floats, may be NULL) back.  Synchronous. */
+ * floats, may be NULL) back.  Synchronous.  Errors: FW_E_INVAL (E or H out
+ * of range, NULL argument, an expert index >= E, n above 2^31). */
 fw_status fw_rmi_gradients(uint32_t E, uint32_t H, const float *params, size_t n,
                            const float *u, const float *t, const uint32_t *expert,
                            uint32_t use_mfma, float *grad, float *loss);
 
 /* One Adam step (Kingma and Ba, bias-corrected) on `count` parameters with the
  * library's optimiser kernel.  Host pointers; params, m and v are updated in
- * place.  `step` counts from 1.  Synchronous. */
+ * place.  `step` counts from 1.  Synchronous.  Errors: FW_E_INVAL (NULL
+ * argument, step 0, count above 2^31). */
 fw_status fw_rmi_adam_step(size_t count, float *params, const float *grad, float *m,
                            float *v, uint32_t step, float lr, float beta1, float beta2,
                            float eps);

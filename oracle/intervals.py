@@ -115,3 +115,49 @@ def first_match_via_candidates(rules, B, cand, packets):
                 out[i] = r
                 break
     return out
+
+
+# ---- port/protocol masks of address-wildcard rules (TEST INFRASTRUCTURE)
+#
+# A rule that leaves both addresses unspecified matches a packet exactly when
+# the packet's source port, destination port and protocol pass its tests.  For
+# a port field, the same boundary construction as above over [0, 65535] gives
+# elementary port intervals, and interval i's mask has bit k set when the k-th
+# rule's port range contains the whole interval.  Written from that definition.
+
+PORT_TOP = 65535
+
+
+def port_boundaries(lo: np.ndarray, hi: np.ndarray) -> np.ndarray:
+    """{0} together with every lo and every hi + 1 <= 65535, sorted and de-duplicated."""
+    lo = np.asarray(lo, dtype=np.int64)
+    hi = np.asarray(hi, dtype=np.int64)
+    ends = hi[hi < PORT_TOP] + 1
+    return np.unique(np.concatenate([np.zeros(1, np.int64), lo, ends]))
+
+
+def port_masks(lo: np.ndarray, hi: np.ndarray):
+    """Boundaries of one port field and, per interval, the bit mask (python int) of the rules
+    (bit k = k-th rule) whose range [lo_k, hi_k] contains the whole interval."""
+    B = port_boundaries(lo, hi)
+    end = np.concatenate([B[1:] - 1, [PORT_TOP]])
+    masks = []
+    for i in range(len(B)):
+        m = 0
+        for k in range(len(lo)):
+            if int(lo[k]) <= int(B[i]) and int(end[i]) <= int(hi[k]):
+                m |= 1 << k
+        masks.append(m)
+    return B, masks
+
+
+def proto_masks(proto: np.ndarray, proto_any: np.ndarray):
+    """Per protocol value 0..255, the bit mask of the rules whose protocol test it passes."""
+    out = []
+    for p in range(256):
+        m = 0
+        for k in range(len(proto)):
+            if int(proto_any[k]) != 0 or int(proto[k]) == p:
+                m |= 1 << k
+        out.append(m)
+    return out

@@ -42,6 +42,9 @@ struct LearnedIndex {
     uint32_t* d_soff = nullptr;
     RuleRec* d_S = nullptr;
     std::vector<uint32_t> Bs, soff, S_idx, Gw_idx;
+    PortTable pt{};               // the first address-wildcard candidates (host copy)
+    uint32_t pt_shape[3] = {0, 0, 0};   // rules in the table, walk steps per port field
+    PortTable* d_pt = nullptr;
     float* d_w1 = nullptr;
     uint16_t* d_w2 = nullptr;
     ExpertMeta* d_meta = nullptr;
@@ -237,7 +240,8 @@ void free_index_memory(LearnedIndex* ix) {
                     static_cast<void*>(ix->d_L), static_cast<void*>(ix->d_Bs),
                     static_cast<void*>(ix->d_soff), static_cast<void*>(ix->d_S),
                     static_cast<void*>(ix->d_w1), static_cast<void*>(ix->d_w2),
-                    static_cast<void*>(ix->d_meta), static_cast<void*>(ix->d_miss)})
+                    static_cast<void*>(ix->d_meta), static_cast<void*>(ix->d_miss),
+                    static_cast<void*>(ix->d_pt)})
         if (p) (void)hipFree(p);
 }
 
@@ -252,6 +256,10 @@ LookupArgs args_of(const LearnedIndex* ix, uint32_t use_net) {
     a.off = ix->d_off;
     a.L = ix->d_L;
     a.G = ix->gplan.plan;
+    a.pt = ix->d_pt;
+    a.pt_count = ix->pt_shape[0];
+    a.pt_steps_s = ix->pt_shape[1];
+    a.pt_steps_d = ix->pt_shape[2];
     a.Bs = ix->d_Bs;
     a.Ms = ix->Ms;
     a.soff = ix->d_soff;
@@ -317,6 +325,71 @@ fw_status interval_lists(const RuleRec* recs, const std::vector<uint32_t>& sel, 
             out->push_back(recs[r]);
         }
     return FW_OK;
+}
+
+// Port/protocol table (see PortTable) of the first kPtRules entries of the
+// address-wildcard list `gw` that are not catch-alls; *rest receives the
+// entries after them (ending with the catch-all, if any).  Ranges come from
+// the packed records: sport = [port_lo >> 16, + port_w >> 16], dport the low
+// halves, protocol (p - lo) <= w.
+void build_port_table(const std::vector<RuleRec>& gw, PortTable* t, uint32_t* count,
+                      uint32_t* steps_s, uint32_t* steps_d, std::vector<RuleRec>* rest) {
+    std::memset(t, 0, sizeof *t);
+    std::vector<RuleRec> tab;
+    rest->clear();
+    for (const RuleRec& q : gw) {
+        if (tab.size() < kPtRules && !full_match_all(q))
+            tab.push_back(q);
+        else
+            rest->push_back(q);
+    }
+    *count = uint32_t(tab.size());
+    for (uint32_t r = 0; r < kPtRules + 4; ++r)
+        t->rule[r] = r < tab.size() ? (tab[r].idx | (((tab[r].proto >> 16) & 0xFFu) << 24))
+                                    : kPtNone;
+    for (uint32_t p = 0; p < 256; ++p) {
+        uint64_t m = 0;
+        for (uint32_t r = 0; r < tab.size(); ++r) {
+            const uint32_t lo = tab[r].proto & 0xFFu, w = (tab[r].proto >> 8) & 0xFFu;
+            if (p - lo <= w) m |= uint64_t(1) << r;
+        }
+        t->mask_p[p] = m;
+    }
+    // one port field: boundaries, masks, high-byte table, longest walk
+    auto field = [&](int shift, uint64_t* mask, uint32_t* b, uint8_t* bucket, uint32_t* steps) {
+        std::vector<uint32_t> bs{0u};
+        for (const RuleRec& q : tab) {
+            const uint32_t lo = (q.port_lo >> shift) & 0xFFFFu, w = (q.port_w >> shift) & 0xFFFFu;
+            bs.push_back(lo);
+            if (lo + w < 0xFFFFu) bs.push_back(lo + w + 1u);
+        }
+        std::sort(bs.begin(), bs.end());
+        bs.erase(std::unique(bs.begin(), bs.end()), bs.end());
+        const uint32_t n = uint32_t(bs.size());   // <= 2 * kPtRules + 1
+        for (uint32_t i = 0; i < kPtMaxIv + 2; ++i) b[i] = i < n ? bs[i] : 0x10000u;
+        for (uint32_t i = 0; i < kPtMaxIv; ++i) {
+            uint64_t m = 0;
+            if (i < n)
+                for (uint32_t r = 0; r < tab.size(); ++r) {
+                    const uint32_t lo = (tab[r].port_lo >> shift) & 0xFFFFu;
+                    const uint32_t w = (tab[r].port_w >> shift) & 0xFFFFu;
+                    if (bs[i] - lo <= w) m |= uint64_t(1) << r;   // interval i inside the range
+                }
+            mask[i] = m;
+        }
+        uint32_t longest = 0;
+        for (uint32_t h = 0; h < 256; ++h) {
+            const uint32_t first = h << 8;
+            const uint32_t i0 = uint32_t(std::upper_bound(bs.begin(), bs.end(), first) - bs.begin()) - 1u;
+            const uint32_t i1 =
+                uint32_t(std::upper_bound(bs.begin(), bs.end(), first + 255u) - bs.begin()) - 1u;
+            bucket[h] = uint8_t(i0);
+            longest = std::max(longest, i1 - i0);
+        }
+        *steps = longest;
+    };
+    field(16, t->mask_s, t->b_s, t->bucket_s, steps_s);
+    field(0, t->mask_d, t->b_d, t->bucket_d, steps_d);
 }
 
 // Destination intervals with their per-interval lists L_j (rules with a
@@ -406,10 +479,13 @@ fw_status build_index(const fw_rule* rules, const RuleRec* recs, uint32_t n_rule
 
     LearnedIndex* ix = new (std::nothrow) LearnedIndex();
     if (!ix) return fail(FW_E_NOMEM, "host allocation failed");
-    std::vector<RuleRec> L, S, G;
+    std::vector<RuleRec> L, S, Gw, G;
     fw_status st;
     try {
-        st = build_lists(recs, n_rules, ix, &L, &S, &G);
+        st = build_lists(recs, n_rules, ix, &L, &S, &Gw);
+        if (st == FW_OK)
+            build_port_table(Gw, &ix->pt, &ix->pt_shape[0], &ix->pt_shape[1], &ix->pt_shape[2],
+                             &G);
     } catch (const std::bad_alloc&) {
         st = fail(FW_E_NOMEM, "host allocation failed while building candidate lists");
     }
@@ -426,7 +502,8 @@ fw_status build_index(const fw_rule* rules, const RuleRec* recs, uint32_t n_rule
                           uint64_t(ix->Ms) * 8 + 4 + ix->nS * sizeof(RuleRec) +
                           uint64_t(ix->nG ? ix->nG : 1) * sizeof(RuleRec) +
                           (uint64_t(ix->nG) + kPairPadding) * 8 + kGradCols * 4 +
-                          uint64_t(E) * kInferStride * 2 + uint64_t(E) * sizeof(ExpertMeta) + 8;
+                          uint64_t(E) * kInferStride * 2 + uint64_t(E) * sizeof(ExpertMeta) + 8 +
+                          sizeof(PortTable);
     if (o.mem_budget && keep > o.mem_budget) {
         delete ix;
         return fail(FW_E_NOMEM, "learned index needs %llu bytes, budget is %llu",
@@ -450,14 +527,18 @@ fw_status build_index(const fw_rule* rules, const RuleRec* recs, uint32_t n_rule
         (e = dalloc(&ix->d_w1, kGradCols, &bytes)) != hipSuccess ||
         (e = dalloc(&ix->d_w2, size_t(E) * kInferStride, &bytes)) != hipSuccess ||
         (e = dalloc(&ix->d_meta, E, &bytes)) != hipSuccess ||
-        (e = dalloc(&ix->d_miss, 1, &bytes)) != hipSuccess)
+        (e = dalloc(&ix->d_miss, 1, &bytes)) != hipSuccess ||
+        (e = dalloc(&ix->d_pt, 1, &bytes)) != hipSuccess)
         return bail(e, "allocating the learned index");
     ix->device_bytes = bytes;
     if ((e = upload(ix->d_B, ix->B, s)) != hipSuccess ||
         (e = upload(ix->d_off, ix->off, s)) != hipSuccess ||
         (e = upload(ix->d_L, L, s)) != hipSuccess || (e = upload(ix->d_Bs, ix->Bs, s)) != hipSuccess ||
         (e = upload(ix->d_soff, ix->soff, s)) != hipSuccess ||
-        (e = upload(ix->d_S, S, s)) != hipSuccess || (e = hipStreamSynchronize(s)) != hipSuccess ||
+        (e = upload(ix->d_S, S, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(ix->d_pt, &ix->pt, sizeof(PortTable), hipMemcpyHostToDevice, s)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess ||
         (e = make_plan(G.data(), uint32_t(G.size()), &ix->gplan)) != hipSuccess)
         return bail(e, "uploading the learned index");
     ix->device_bytes += ix->gplan.bytes;
@@ -713,6 +794,8 @@ fw_status index_export(const LearnedIndex* ix, uint32_t what, void* host, size_t
         case 7: src = ix->soff.data(); bytes = ix->soff.size() * 4; break;
         case 8: src = ix->S_idx.data(); bytes = ix->S_idx.size() * 4; break;
         case 9: src = ix->Gw_idx.data(); bytes = ix->Gw_idx.size() * 4; break;
+        case 10: src = &ix->pt; bytes = sizeof(PortTable); break;
+        case 11: src = ix->pt_shape; bytes = sizeof ix->pt_shape; break;
         default: return fail(FW_E_INVAL, "unknown export %u", what);
     }
     if (size) *size = bytes;
@@ -733,6 +816,7 @@ fw_status fw_rmi_gradients(uint32_t E, uint32_t H, const float* params, size_t n
     if (H == 0 || H > kMaxHidden) return fail(FW_E_INVAL, "H must be 1..%u", kMaxHidden);
     if (!params || !grad || (n && (!u || !t || !expert)))
         return fail(FW_E_INVAL, "NULL argument");
+    if (n > (size_t(1) << 31)) return fail(FW_E_INVAL, "at most 2^31 samples");
     for (size_t k = 0; k < n; ++k)
         if (expert[k] >= E) return fail(FW_E_INVAL, "sample %zu: network index out of range", k);
     const uint32_t P = 3 * H + 1;
@@ -765,6 +849,7 @@ fw_status fw_rmi_adam_step(size_t count, float* params, const float* grad, float
                            uint32_t step, float lr, float beta1, float beta2, float eps) {
     if (!params || !grad || !m || !v) return fail(FW_E_INVAL, "NULL argument");
     if (step == 0) return fail(FW_E_INVAL, "step counts from 1");
+    if (count > (size_t(1) << 31)) return fail(FW_E_INVAL, "at most 2^31 parameters");
     if (count == 0) return FW_OK;
     float* d = nullptr;
     hipError_t e = hipMalloc(&d, sizeof(float) * count * 4);

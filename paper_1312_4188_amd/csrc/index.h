@@ -51,6 +51,31 @@ constexpr uint32_t kNoExpert = 0xFFFFFFFFu;
 // padded to 104 entries (a multiple of 8); hidden units past H are zero.
 constexpr uint32_t kInferStride = 104;
 
+// Port/protocol table of the first (up to 64) candidates that leave both
+// addresses unspecified: such a rule matches a packet exactly when both of
+// its port ranges and its protocol test pass.  Per port field, the rules'
+// range ends cut [0, 65535] into elementary intervals (each range is a union
+// of whole intervals) and interval i carries the 64-bit mask of the rules
+// whose range contains it; the protocol gets a mask per value.  The AND of
+// the packet's three masks is the set of these rules it matches, and the
+// lowest set bit is the first of them (bits follow rule order).  A port's
+// interval is found from a 256-entry table on its high byte plus at most
+// `steps` forward steps.  Fixed size, so it is staged into LDS as one block.
+constexpr uint32_t kPtRules = 64;
+constexpr uint32_t kPtMaxIv = 2 * kPtRules + 2;       // intervals per port field, rounded up
+struct alignas(16) PortTable {
+    uint64_t mask_p[256];           // per protocol value
+    uint64_t mask_s[kPtMaxIv];      // per source-port interval
+    uint64_t mask_d[kPtMaxIv];      // per destination-port interval
+    uint32_t b_s[kPtMaxIv + 2];     // interval starts; unused entries (and one past the last) 0x10000
+    uint32_t b_d[kPtMaxIv + 2];
+    uint32_t rule[kPtRules + 4];    // bit r -> rule index | action << 24; entry kPtRules = none
+    uint8_t bucket_s[256];          // interval holding port h << 8
+    uint8_t bucket_d[256];
+};
+static_assert(sizeof(PortTable) % 16 == 0, "staged as 16-byte words");
+constexpr uint32_t kPtNone = 0xFFFFFFFFu;
+
 // Everything the lookup kernel reads.
 struct LookupArgs {
     const uint32_t* B;        // M boundaries
@@ -61,7 +86,11 @@ struct LookupArgs {
     uint32_t E;
     const uint32_t* off;      // M + 1 per-interval list offsets
     const RuleRec* L;         // per-interval candidate records
-    ScanPlan G;               // source- and destination-wildcard candidates (grouped plan)
+    const PortTable* pt;      // the first address-wildcard candidates (see PortTable)
+    uint32_t pt_count;        // rules in the table (0: none)
+    uint32_t pt_steps_s;      // forward steps after the high-byte table, per port field
+    uint32_t pt_steps_d;
+    ScanPlan G;               // the remaining address-wildcard candidates (grouped plan)
     const uint32_t* Bs;       // source intervals of the other destination-wildcard candidates
     uint32_t Ms;
     const uint32_t* soff;     // Ms + 1 per-source-interval list offsets

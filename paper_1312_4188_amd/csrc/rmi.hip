@@ -15,6 +15,9 @@
 // product S^T * A, which runs on the matrix cores as bf16 x bf16 -> fp32 MFMA
 // (S is exact in bf16).  A plain fp32 reduction computes the same sums for
 // checking.
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <type_traits>
 
 #include "device_util.h"
@@ -304,6 +307,21 @@ __global__ void k_err_bound(LookupArgs a, const uint32_t* __restrict__ keys,
     atomicMax(err + e, uint32_t(d < 0 ? -d : d));
 }
 
+// First rule of a port/protocol table that the packet matches, as
+// rule index | action << 24, or kPtNone.  pp = source port << 16 | destination
+// port.  Each port's interval: the high-byte table gives the interval holding
+// the bucket's first port, then `steps` forward steps (an interval start past
+// the port stops the walk; the entry after the last interval is 0x10000).
+__device__ __forceinline__ uint32_t port_table_first(const PortTable& t, uint32_t steps_s,
+                                                     uint32_t steps_d, uint32_t pp, uint32_t pr) {
+    const uint32_t sp = pp >> 16, dp = pp & 0xFFFFu;
+    uint32_t is = t.bucket_s[sp >> 8], id = t.bucket_d[dp >> 8];
+    for (uint32_t k = 0; k < steps_s; ++k) is += t.b_s[is + 1u] <= sp ? 1u : 0u;
+    for (uint32_t k = 0; k < steps_d; ++k) id += t.b_d[id + 1u] <= dp ? 1u : 0u;
+    const uint64_t m = t.mask_s[is] & t.mask_d[id] & t.mask_p[pr & 0xFFu];
+    return t.rule[m ? uint32_t(__builtin_ctzll(m)) : kPtRules];
+}
+
 // ------------------------------------------------------------------ lookup + candidate scan
 // Persistent work-groups of 16 waves.  Each stages the stage-1 weights, the
 // experts' records and bf16 weights, and (when it fits) the boundary array
@@ -314,17 +332,19 @@ __global__ void k_err_bound(LookupArgs a, const uint32_t* __restrict__ keys,
 //   3. locate the source interval i among the destination-wildcard candidates
 //      that specify a source, and scan i's list per lane the same way (ports
 //      and protocol tested; destination and source are implied);
-//   4. scan the remaining candidates (source and destination both
-//      unspecified, a grouped scan plan) with the packet-split wave scan,
-//      seeded with the best of steps 2-3, so each lane keeps the smallest of
-//      the partial first matches;
+//   4. the candidates with both addresses unspecified: the first 64 through
+//      the port/protocol table (three masks ANDed, lowest bit), the rest
+//      with the packet-split wave scan over a grouped plan; every step is
+//      seeded with the best so far, so each lane keeps the smallest of the
+//      partial first matches (the table runs before the lists, so they can
+//      stop early);
 //   5. write the index and action.
 constexpr uint32_t kLearnedBlock = 1024;
 constexpr uint32_t kLearnedK = 2;     // default packets per lane in the classify kernel
 
 __host__ __device__ inline size_t lds_layout(uint32_t E, uint32_t M, uint32_t Ms, bool b_lds,
                                              bool w2_f32, size_t* off_meta, size_t* off_w2,
-                                             size_t* off_b, size_t* off_bs) {
+                                             size_t* off_pt, size_t* off_b, size_t* off_bs) {
     size_t o = kInferStride * sizeof(float);
     *off_meta = o;
     o += size_t(E) * sizeof(ExpertMeta);
@@ -332,6 +352,8 @@ __host__ __device__ inline size_t lds_layout(uint32_t E, uint32_t M, uint32_t Ms
     *off_w2 = o;
     o += size_t(E) * kInferStride * (w2_f32 ? sizeof(float) : sizeof(uint16_t));
     o = (o + 15) & ~size_t(15);
+    *off_pt = o;
+    o += sizeof(PortTable);
     *off_b = o;
     if (b_lds) o += size_t(M) * sizeof(uint32_t);
     *off_bs = o;
@@ -346,6 +368,7 @@ struct IndexView {
     const W2* w2;
     const uint32_t* B;
     const uint32_t* Bs;
+    const PortTable* pt;
 };
 
 // Stage the index into LDS; stage-2 weights stay bf16 (W2 = uint16_t) or are
@@ -353,8 +376,9 @@ struct IndexView {
 template <bool B_LDS, class W2>
 __device__ __forceinline__ IndexView<W2> stage_index(const LookupArgs& a, unsigned char* smem) {
     constexpr bool kF32 = sizeof(W2) == 4;
-    size_t o_meta, o_w2, o_b, o_bs;
-    lds_layout(a.E, a.M, a.Ms, B_LDS, kF32, &o_meta, &o_w2, &o_b, &o_bs);
+    size_t o_meta, o_w2, o_pt, o_b, o_bs;
+    lds_layout(a.E, a.M, a.Ms, B_LDS, kF32, &o_meta, &o_w2, &o_pt, &o_b, &o_bs);
+    PortTable* s_pt = reinterpret_cast<PortTable*>(smem + o_pt);
     float* s_w1 = reinterpret_cast<float*>(smem);
     ExpertMeta* s_meta = reinterpret_cast<ExpertMeta*>(smem + o_meta);
     W2* s_w2 = reinterpret_cast<W2*>(smem + o_w2);
@@ -371,12 +395,16 @@ __device__ __forceinline__ IndexView<W2> stage_index(const LookupArgs& a, unsign
         for (uint32_t k = tid; k < a.E * kInferStride / 2u; k += kLearnedBlock)
             reinterpret_cast<uint32_t*>(s_w2)[k] = reinterpret_cast<const uint32_t*>(a.w2)[k];
     }
+    if (a.pt_count) {
+        for (uint32_t k = tid; k < sizeof(PortTable) / 16u; k += kLearnedBlock)
+            reinterpret_cast<uint4*>(s_pt)[k] = reinterpret_cast<const uint4*>(a.pt)[k];
+    }
     if constexpr (B_LDS) {
         for (uint32_t k = tid; k < a.M; k += kLearnedBlock) s_b[k] = a.B[k];
         for (uint32_t k = tid; k < a.Ms; k += kLearnedBlock) s_bs[k] = a.Bs[k];
     }
     __syncthreads();
-    return IndexView<W2>{s_w1, s_meta, s_w2, B_LDS ? s_b : a.B, B_LDS ? s_bs : a.Bs};
+    return IndexView<W2>{s_w1, s_meta, s_w2, B_LDS ? s_b : a.B, B_LDS ? s_bs : a.Bs, s_pt};
 }
 
 // With one or two packets per lane, two work-groups per CU (the LDS footprint
@@ -399,43 +427,61 @@ __global__ __launch_bounds__(kLearnedBlock, K >= 4 ? 4 : 8) void k_learned(Looku
     for (size_t base = wave0 * 64u * K; base < n; base += waves * 64u * K) {
         WaveScan<K> w;
         w.init(pk, base, n, dflt);
-        uint32_t lbest[K], lact[K];
+        uint32_t lbest[K], lact[K], jj[K], si[K];
+        // every packet's destination and source intervals first: the K
+        // lookups are independent, so their LDS round trips overlap
 #pragma unroll
         for (int s = 0; s < K; ++s) {
             const bool valid = w.p0 + s < n;
             bool miss = false;
-            const uint32_t j = locate(v.B, a.M, v.w1, v.w2, v.meta, a.E, a.use_net, w.dst[s],
-                                      &miss);
+            jj[s] = locate(v.B, a.M, v.w1, v.w2, v.meta, a.E, a.use_net, w.dst[s], &miss);
             if (a.miss) {
                 const uint64_t mm = ballot(valid && miss);
                 if (lane == 0 && mm) atomicAdd(a.miss, (unsigned long long)__popcll(mm));
             }
+            si[s] = search_le(v.Bs, 0, a.Ms - 1u, w.src[s]);
             lbest[s] = kNoMatch;
             lact[s] = dflt;
-            if (valid) {
-                const uint32_t kb = a.off[j], ke = a.off[j + 1u];
-                for (uint32_t k = kb; k < ke; ++k) {
-                    const RuleRec q = a.L[k];
-                    if (match_no_dst(q, w.src[s], w.pp[s], w.pr[s])) {
-                        lbest[s] = q.idx;
-                        lact[s] = rule_action(q.proto);
-                        break;
-                    }
+        }
+        // the port/protocol table of the first address-wildcard candidates
+        if (a.pt_count) {
+#pragma unroll
+            for (int s = 0; s < K; ++s) {
+                const uint32_t e = port_table_first(*v.pt, a.pt_steps_s, a.pt_steps_d, w.pp[s],
+                                                    w.pr[s]);
+                if (e != kPtNone) {
+                    lbest[s] = e & 0xFFFFFFu;
+                    lact[s] = e >> 24;
                 }
-                // destination-wildcard candidates with a specified source: the
-                // packet's source interval lists exactly those whose source
-                // test it passes; stop at the first match or past lbest
-                const uint32_t si = search_le(v.Bs, 0, a.Ms - 1u, w.src[s]);
-                const uint32_t sb = a.soff[si], se = a.soff[si + 1u];
-                for (uint32_t k = sb; k < se; ++k) {
-                    const RuleRec q = a.S[k];
-                    if (q.idx > lbest[s]) break;
-                    if (ports_in(w.pp[s], q.port_lo, q.port_w) &&
-                        in_range(w.pr[s], proto_lo(q.proto), proto_w(q.proto))) {
-                        lbest[s] = q.idx;
-                        lact[s] = rule_action(q.proto);
-                        break;
-                    }
+            }
+        }
+        // the per-lane lists, each ascending: stop at the first match or once
+        // an entry can no longer beat the best so far
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            if (w.p0 + s >= n) continue;
+            const uint32_t kb = a.off[jj[s]], ke = a.off[jj[s] + 1u];
+            for (uint32_t k = kb; k < ke; ++k) {
+                const RuleRec q = a.L[k];
+                if (q.idx > lbest[s]) break;
+                if (match_no_dst(q, w.src[s], w.pp[s], w.pr[s])) {
+                    lbest[s] = q.idx;
+                    lact[s] = rule_action(q.proto);
+                    break;
+                }
+            }
+            // destination-wildcard candidates with a specified source: the
+            // packet's source interval lists exactly those whose source test
+            // it passes
+            const uint32_t sb = a.soff[si[s]], se = a.soff[si[s] + 1u];
+            for (uint32_t k = sb; k < se; ++k) {
+                const RuleRec q = a.S[k];
+                if (q.idx > lbest[s]) break;
+                if (ports_in(w.pp[s], q.port_lo, q.port_w) &&
+                    in_range(w.pr[s], proto_lo(q.proto), proto_w(q.proto))) {
+                    lbest[s] = q.idx;
+                    lact[s] = rule_action(q.proto);
+                    break;
                 }
             }
         }
@@ -479,13 +525,43 @@ struct LearnedLaunchCache {
 };
 thread_local LearnedLaunchCache g_cache;
 
+// Resident work-groups per CU for (kernel, device, dynamic LDS bytes), and the
+// largest dynamic LDS size granted to each kernel so far.  Queried once: a
+// small batch's latency should not pay for occupancy queries on every call.
+// The granted size only grows, so a launch never finds it lowered by another
+// thread's smaller request.
+std::mutex g_launch_mu;
+std::map<std::tuple<const void*, int, size_t>, int> g_per_cu;
+std::map<std::pair<const void*, int>, size_t> g_lds_granted;
+
+template <class Kern>
+hipError_t blocks_per_cu(Kern kern, size_t lds, int* per_cu) {
+    const void* f = reinterpret_cast<const void*>(kern);
+    std::lock_guard<std::mutex> lk(g_launch_mu);
+    const auto key = std::make_tuple(f, g_cache.device, lds);
+    const auto it = g_per_cu.find(key);
+    if (it != g_per_cu.end()) {
+        *per_cu = it->second;
+        return hipSuccess;
+    }
+    size_t& granted = g_lds_granted[std::make_pair(f, g_cache.device)];
+    if (lds > granted) {
+        const hipError_t e =
+            hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+        granted = lds;
+    }
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, kern, kLearnedBlock,
+                                                                      lds);
+    if (e != hipSuccess) return e;
+    g_per_cu[key] = *per_cu;
+    return hipSuccess;
+}
+
 template <class Kern, class... Args>
 hipError_t launch_persistent(Kern kern, size_t lds, size_t tiles, hipStream_t s, Args... args) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-    if (e != hipSuccess) return e;
     int per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kLearnedBlock, lds);
+    const hipError_t e = blocks_per_cu(kern, lds, &per_cu);
     if (e != hipSuccess) return e;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
     const size_t want = (tiles + (kLearnedBlock / 64) - 1) / (kLearnedBlock / 64);
@@ -566,8 +642,8 @@ hipError_t launch_err_bound(const LookupArgs& a, const uint32_t* keys, const int
 }
 
 size_t learned_lds_bytes(const LookupArgs& a, bool b_in_lds, bool w2_f32) {
-    size_t o1, o2, o3, o4;
-    return lds_layout(a.E, a.M, a.Ms, b_in_lds, w2_f32, &o1, &o2, &o3, &o4);
+    size_t o1, o2, o3, o4, o5;
+    return lds_layout(a.E, a.M, a.Ms, b_in_lds, w2_f32, &o1, &o2, &o3, &o4, &o5);
 }
 
 hipError_t launch_learned(const LookupArgs& a, PacketsDev pk, size_t n, int32_t* out_idx,

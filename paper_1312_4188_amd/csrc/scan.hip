@@ -186,46 +186,95 @@ __global__ __launch_bounds__(1024) void k_hybrid(const uint2* __restrict__ pairs
 
 inline uint32_t ceil_div(uint64_t a, uint64_t b) { return uint32_t((a + b - 1) / b); }
 
+// A dispatch's grid size is a 32-bit count of work-items per dimension, so
+// one launch covers fewer than 2^32 of them.  Batches that would need more
+// are launched in chunks; every chunk size is a multiple of 64 packets, so
+// the offset arrays stay 16-byte aligned.
+constexpr uint64_t kMaxLaunchItems = (uint64_t(1) << 32) - 1024;
+
+PacketsDev advance(const PacketsDev& pk, size_t o) {
+    return PacketsDev{pk.src + o, pk.dst + o, pk.sport + o, pk.dport + o, pk.proto + o};
+}
+
+// Largest chunk of packets (a multiple of 64) whose launch needs at most
+// kMaxLaunchItems work-items when each packet costs items_per_packet of them.
+size_t chunk_packets(double items_per_packet) {
+    const double c = double(kMaxLaunchItems) / items_per_packet;
+    const size_t k = size_t(c) / 64u * 64u;
+    return k < 64u ? 64u : k;
+}
+
+template <class F>
+hipError_t in_chunks(size_t n, size_t chunk, F launch) {
+    for (size_t o = 0; o < n; o += chunk) {
+        const hipError_t e = launch(o, n - o < chunk ? n - o : chunk);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t fill_no_match(uint32_t* idx, size_t n, hipStream_t stream) {
+    return in_chunks(n, chunk_packets(1.0), [&](size_t o, size_t c) {
+        hipLaunchKernelGGL(k_fill_u32, dim3(ceil_div(c, 256)), dim3(256), 0, stream, idx + o, c,
+                           kNoMatch);
+        return hipGetLastError();
+    });
+}
+
+hipError_t apply_action(const RuleRec* rules, const int32_t* idx, size_t n, uint8_t* out_act,
+                        uint8_t default_action, hipStream_t stream) {
+    return in_chunks(n, chunk_packets(1.0), [&](size_t o, size_t c) {
+        hipLaunchKernelGGL(k_apply_action, dim3(ceil_div(c, 256)), dim3(256), 0, stream, rules,
+                           idx + o, c, out_act + o, uint32_t(default_action));
+        return hipGetLastError();
+    });
+}
+
 }  // namespace
 
 hipError_t launch_packet_split(const ScanPlan& plan, PacketsDev pk, size_t n, int32_t* out_idx,
                                uint8_t* out_act, uint8_t default_action, int packets_per_lane,
                                hipStream_t stream) {
     if (n == 0) return hipSuccess;
-    constexpr uint32_t kBlock = kScanBlock;
     const int K = packets_per_lane;
-    const uint64_t per_block = uint64_t(kBlock) * K;
-    const uint32_t grid = ceil_div(n, per_block);
+    const uint64_t per_block = uint64_t(kScanBlock) * K;
     const uint32_t dflt = default_action;
-    if (K == 4)
-        hipLaunchKernelGGL(k_packet_split<4>, dim3(grid), dim3(kBlock), 0, stream, plan, pk, n,
-                           out_idx, out_act, dflt);
-    else if (K == 2)
-        hipLaunchKernelGGL(k_packet_split<2>, dim3(grid), dim3(kBlock), 0, stream, plan, pk, n,
-                           out_idx, out_act, dflt);
-    else
-        hipLaunchKernelGGL(k_packet_split<1>, dim3(grid), dim3(kBlock), 0, stream, plan, pk, n,
-                           out_idx, out_act, dflt);
-    return hipGetLastError();
+    return in_chunks(n, chunk_packets(1.0 / K), [&](size_t o, size_t c) {
+        const uint32_t grid = ceil_div(c, per_block);
+        const PacketsDev p = advance(pk, o);
+        if (K == 4)
+            hipLaunchKernelGGL(k_packet_split<4>, dim3(grid), dim3(kScanBlock), 0, stream, plan,
+                               p, c, out_idx + o, out_act + o, dflt);
+        else if (K == 2)
+            hipLaunchKernelGGL(k_packet_split<2>, dim3(grid), dim3(kScanBlock), 0, stream, plan,
+                               p, c, out_idx + o, out_act + o, dflt);
+        else
+            hipLaunchKernelGGL(k_packet_split<1>, dim3(grid), dim3(kScanBlock), 0, stream, plan,
+                               p, c, out_idx + o, out_act + o, dflt);
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_rule_split(const RuleRec* rules, uint32_t n_rules, uint32_t P, PacketsDev pk,
                              size_t n, int32_t* out_idx, uint8_t* out_act,
                              uint8_t default_action, hipStream_t stream) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill_u32, dim3(ceil_div(n, 256)), dim3(256), 0, stream,
-                       reinterpret_cast<uint32_t*>(out_idx), n, kNoMatch);
+    uint32_t* idx = reinterpret_cast<uint32_t*>(out_idx);
+    hipError_t e = fill_no_match(idx, n, stream);
+    if (e != hipSuccess) return e;
     if (n_rules > 0) {
         const uint32_t S = ceil_div(n_rules, P);
-        const uint64_t waves = uint64_t(P) * ((n + kRsPackets - 1) / kRsPackets);
-        const uint64_t blocks = (waves + (kScanBlock / 64) - 1) / (kScanBlock / 64);
-        if (blocks > 0x7FFFFFFFull) return hipErrorInvalidConfiguration;
-        hipLaunchKernelGGL(k_rule_split, dim3(uint32_t(blocks)), dim3(kScanBlock), 0, stream,
-                           rules, n_rules, P, S, pk, n, reinterpret_cast<uint32_t*>(out_idx));
+        // P waves of 64 lanes per kRsPackets packets
+        e = in_chunks(n, chunk_packets(64.0 * P / kRsPackets), [&](size_t o, size_t c) {
+            const uint64_t waves = uint64_t(P) * ((c + kRsPackets - 1) / kRsPackets);
+            const uint64_t blocks = (waves + (kScanBlock / 64) - 1) / (kScanBlock / 64);
+            hipLaunchKernelGGL(k_rule_split, dim3(uint32_t(blocks)), dim3(kScanBlock), 0, stream,
+                               rules, n_rules, P, S, advance(pk, o), c, idx + o);
+            return hipGetLastError();
+        });
+        if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_apply_action, dim3(ceil_div(n, 256)), dim3(256), 0, stream, rules,
-                       out_idx, n, out_act, uint32_t(default_action));
-    return hipGetLastError();
+    return apply_action(rules, out_idx, n, out_act, default_action, stream);
 }
 
 hipError_t launch_hybrid(const uint2* pairs, const RuleRec* rules, uint32_t n_rules, uint32_t P,
@@ -234,9 +283,13 @@ hipError_t launch_hybrid(const uint2* pairs, const RuleRec* rules, uint32_t n_ru
                          hipStream_t stream) {
     if (n == 0) return hipSuccess;
     const uint32_t S = n_rules == 0 ? 1u : ceil_div(n_rules, P);
-    hipLaunchKernelGGL(k_hybrid, dim3(ceil_div(n, 64)), dim3(64 * P), 0, stream, pairs, rules,
-                       n_rules, S, pk, n, out_idx, out_act, uint32_t(default_action));
-    return hipGetLastError();
+    // a work-group of 64*P lanes per 64 packets
+    return in_chunks(n, chunk_packets(double(P)), [&](size_t o, size_t c) {
+        hipLaunchKernelGGL(k_hybrid, dim3(ceil_div(c, 64)), dim3(64 * P), 0, stream, pairs,
+                           rules, n_rules, S, advance(pk, o), c, out_idx + o, out_act + o,
+                           uint32_t(default_action));
+        return hipGetLastError();
+    });
 }
 
 }  // namespace fw

@@ -24,12 +24,19 @@ class _FakeIndex:
         self.S = [gsel[c] for c in Cs]
         self.Gw = np.nonzero(wild_dst & wild_src)[0]
         self.B, self.Bs = B, Bs
+        catch = ((np.asarray(rules.sport_lo) == 0) & (np.asarray(rules.sport_hi) == 65535)
+                 & (np.asarray(rules.dport_lo) == 0) & (np.asarray(rules.dport_hi) == 65535)
+                 & (np.asarray(rules.proto_any) != 0))
+        if (catch[self.Gw]).any():                  # the list ends at its first catch-all
+            self.Gw = self.Gw[: np.argmax(catch[self.Gw]) + 1]
+        self.table = min(64, int((~catch[self.Gw]).sum()))
 
     def export(self, what):
         off = lambda lists: np.concatenate([[0], np.cumsum([len(x) for x in lists])])
         cat = lambda lists: (np.concatenate(lists) if lists else np.zeros(0, np.int64))
         return {0: self.B, 1: off(self.L), 2: cat(self.L), 4: np.array([3.0, 5.0]),
-                6: self.Bs, 7: off(self.S), 8: cat(self.S), 9: self.Gw}[what]
+                6: self.Bs, 7: off(self.S), 8: cat(self.S), 9: self.Gw,
+                11: np.array([self.table, 2, 3])}[what]
 
 
 def test_candidate_checks_match_brute_force():
@@ -42,7 +49,7 @@ def test_candidate_checks_match_brute_force():
     i = iv.interval_of(fake.Bs, pk.src_ip)
     brute = 0
     for p in range(len(pk)):
-        for lst in (fake.L[j[p]], fake.S[i[p]], fake.Gw):
+        for lst in (fake.L[j[p]], fake.S[i[p]], fake.Gw[fake.table:]):
             lst = np.asarray(lst)
             brute += int(np.sum(lst <= idx[p])) if idx[p] >= 0 else len(lst)
     assert work["candidate_checks"] == brute

@@ -248,3 +248,84 @@ def test_source_lists_match_definition(seed, R):
         want = mapped[iv.truncated(C[i], full)]
         assert set(want.tolist()) <= set(got.tolist()) <= set(mapped[C[i]].tolist()), i
         assert np.all(np.diff(got.astype(np.int64)) > 0)
+
+
+_PT_DTYPE = np.dtype([("mask_p", "<u8", 256), ("mask_s", "<u8", 130), ("mask_d", "<u8", 130),
+                      ("b_s", "<u4", 132), ("b_d", "<u4", 132), ("rule", "<u4", 68),
+                      ("bucket_s", "u1", 256), ("bucket_d", "u1", 256)])
+
+
+def _address_wildcard_heavy(R, seed, frac):
+    """Random rules with a fraction made address-wildcard (both prefixes /0); those are kept
+    from being catch-alls so the wildcard list stays long."""
+    rules = gen.make_rules(R, seed)
+    rng = np.random.Generator(np.random.PCG64(seed + 99))
+    pick = rng.random(R) < frac
+    rules.src_plen[pick] = 0
+    rules.dst_plen[pick] = 0
+    catch = (pick & (rules.sport_lo == 0) & (rules.sport_hi == 65535) & (rules.dport_lo == 0)
+             & (rules.dport_hi == 65535) & (rules.proto_any != 0))
+    rules.proto_any[catch] = 0
+    rules.proto[catch] = 6
+    return rules
+
+
+def _wildcard_list(rules):
+    """Address-wildcard rules up to and including the first catch-all (definition)."""
+    wild = (rules.src_plen == 0) & (rules.dst_plen == 0)
+    catch = (wild & (rules.sport_lo == 0) & (rules.sport_hi == 65535) & (rules.dport_lo == 0)
+             & (rules.dport_hi == 65535) & (rules.proto_any != 0))
+    idx = np.nonzero(wild)[0]
+    if catch.any():
+        idx = idx[idx <= np.argmax(catch)]
+    return idx, catch
+
+
+@pytest.mark.parametrize("seed,R,frac", [(1, 10000, 0.0), (4, 600, 0.3), (5, 300, 1.0),
+                                         (6, 40, 0.5)])
+def test_port_table_matches_definition(seed, R, frac):
+    """The port/protocol table of the first 64 address-wildcard candidates against the
+    oracle's masks, and the high-byte walk against the interval of every port value."""
+    fw = fwmod()
+    rules = (gen.make_rules(R, seed, skew=True) if frac == 0.0
+             else _address_wildcard_heavy(R, seed, frac))
+    say(f"port table seed={seed} R={R} frac={frac}")
+    with fw.Ruleset(rules) as rs:
+        rs.build_learned_index(**FAST)
+        Gw, raw, shape = rs.export(9), rs.export(10), rs.export(11)
+    gw_def, catch = _wildcard_list(rules)
+    np.testing.assert_array_equal(Gw, gw_def)
+    sel = np.array([r for r in gw_def if not catch[r]][:64], dtype=np.int64)
+    t = np.frombuffer(raw.tobytes(), dtype=_PT_DTYPE, count=1)[0]
+    assert int(shape[0]) == len(sel)
+    want_rule = [int(r) | (int(rules.action[r]) << 24) for r in sel]
+    assert [int(x) for x in t["rule"][:len(sel)]] == want_rule
+    assert np.all(t["rule"][len(sel):] == 0xFFFFFFFF)
+    assert [int(x) for x in t["mask_p"]] == iv.proto_masks(rules.proto[sel], rules.proto_any[sel])
+    ports = np.arange(65536, dtype=np.int64)
+    for name, lo, hi, steps in (("s", rules.sport_lo[sel], rules.sport_hi[sel], int(shape[1])),
+                                ("d", rules.dport_lo[sel], rules.dport_hi[sel], int(shape[2]))):
+        B, masks = iv.port_masks(lo, hi) if len(sel) else (np.zeros(1, np.int64), [0])
+        b = t[f"b_{name}"].astype(np.int64)
+        np.testing.assert_array_equal(b[:len(B)], B)
+        assert np.all(b[len(B):] == 0x10000)
+        assert [int(x) for x in t[f"mask_{name}"][:len(B)]] == masks
+        # the kernel's walk: high-byte table, then `steps` forward steps
+        i = t[f"bucket_{name}"].astype(np.int64)[ports >> 8]
+        for _ in range(steps):
+            i = i + (b[i + 1] <= ports)
+        np.testing.assert_array_equal(i, np.searchsorted(B, ports, side="right") - 1)
+
+
+@pytest.mark.parametrize("seed,R,frac", [(7, 400, 0.5), (8, 1500, 0.2), (9, 64, 1.0),
+                                         (10, 65, 1.0)])
+def test_learned_with_many_address_wildcard_rules(seed, R, frac):
+    """Long address-wildcard lists: more than 64 such candidates put the rest on the grouped
+    scan after the port/protocol table.  Every packet against the oracle."""
+    rules = _address_wildcard_heavy(R, seed, frac)
+    pk = gen.make_packets(rules, 50_000, seed)
+    say(f"learned, address-wildcard heavy seed={seed} R={R} frac={frac}")
+    want = oracle.classify(rules, pk)
+    for ppl in (1, 2, 4):
+        got, _, _ = _learned_np(rules, pk, packets_per_lane=ppl)
+        assert_same(got, want, f"seed={seed} R={R} K={ppl}")

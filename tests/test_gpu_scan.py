@@ -62,6 +62,44 @@ def test_1000_rules_full_batch(kw):
     assert_same(classify_np(rules, pk, **kw), want, f"1000x1M {kw}")
 
 
+def test_rule_split_launch_chunks():
+    """16,384 partitions need 64 * 16,384 / 8 work-items per packet: one launch holds fewer
+    than 2^32 work-items, so 100,000 packets go in four launches.  Every packet against the
+    oracle."""
+    say("rule split, 16384 partitions, 100000 packets (chunked launches)")
+    rules = gen.make_rules(1000, 31)
+    pk = gen.make_packets(rules, 100_000, 31)
+    want = oracle.classify(rules, pk, threads=16)
+    assert_same(classify_np(rules, pk, mode="rule_split", partitions=16384), want,
+                "rule split P=16384")
+
+
+def test_hybrid_launch_chunks():
+    """Hybrid with 16 partitions takes 16 work-items per packet, so one launch covers
+    268,435,392 packets; a batch just above that runs in two launches.  The batch tiles
+    1,048,576 distinct packets, so every output is checked against the oracle's answer for
+    its tile position."""
+    import torch
+    fw = fwmod()
+    rules = gen.make_rules(100, 41)
+    base = gen.make_packets(rules, 1 << 20, 41)
+    want_idx, want_act = oracle.classify(rules, base, threads=16)
+    n = 268_435_392 + 10_000
+    reps = -(-n // (1 << 20))
+    small = fw.DevicePackets.from_host(base)
+    dp = fw.DevicePackets(*(t.repeat(reps)[:n] for t in (small.src_ip, small.dst_ip,
+                                                          small.sport, small.dport,
+                                                          small.proto)))
+    say(f"hybrid P=16 over {n} packets (two launches)")
+    with fw.Ruleset(rules) as rs:
+        idx, act = rs.classify(dp, mode="hybrid", partitions=16)
+        torch.cuda.synchronize()
+    wi = torch.from_numpy(want_idx).cuda().repeat(reps)[:n]
+    wa = torch.from_numpy(want_act).cuda().repeat(reps)[:n]
+    bad = torch.nonzero((idx != wi) | (act != wa))
+    assert bad.numel() == 0, f"{bad.numel()} mismatches, first at {int(bad[0])}"
+
+
 @pytest.mark.parametrize("n", [0, 1, 3, 63, 64, 65, 255, 257, 1023, 4099])
 @pytest.mark.parametrize("kw", SCAN_MODES[:5] + SCAN_MODES[8:9], ids=_id)
 def test_ragged_sizes(n, kw):

@@ -147,3 +147,28 @@ def test_adam_first_step_closed_form():
     np.testing.assert_allclose(new, th - 0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12)
     np.testing.assert_allclose(m, 0.1 * g)
     np.testing.assert_allclose(v, 0.001 * g * g)
+
+
+def test_port_masks_against_every_port():
+    """Port masks pinned by brute force: for every port value p, the mask of p's interval
+    holds exactly the rules whose range contains p (the covering argument on 16 bits)."""
+    rng = np.random.Generator(np.random.PCG64(11))
+    lo = rng.integers(0, 65536, 40)
+    hi = np.minimum(lo + rng.integers(0, 3000, 40), 65535)
+    lo[:3] = [0, 0, 65535]
+    hi[:3] = [65535, 0, 65535]                      # wildcard, [0,0], [65535,65535]
+    B, masks = iv.port_masks(lo, hi)
+    assert B[0] == 0 and np.all(np.diff(B) > 0) and B[-1] <= 65535
+    ports = np.arange(65536)
+    j = np.searchsorted(B, ports, side="right") - 1
+    want = np.zeros(65536, dtype=object)
+    for k in range(len(lo)):
+        inside = (ports >= lo[k]) & (ports <= hi[k])
+        want[inside] = want[inside] + (1 << k)
+    got = np.array([masks[i] for i in j], dtype=object)
+    assert np.array_equal(got, want)
+
+
+def test_proto_masks_definition():
+    pm = iv.proto_masks(np.array([6, 17, 0, 6]), np.array([0, 0, 0, 1]))
+    assert pm[6] == 0b1001 and pm[17] == 0b1010 and pm[0] == 0b1100 and pm[1] == 0b1000
