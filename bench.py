@@ -87,8 +87,9 @@ def learned_work(rs, pk, idx, hidden: int = 32):
     nothing matches).  Lane-ops: 2 per candidate check (one subtract, one
     compare: the first field test); 6H per packet for the two networks (per
     hidden unit a multiply-add, a max and a multiply-add, in each stage); 2 per
-    binary-search probe (the mean error window, plus the source-interval
-    search); for the port/protocol table of the first 64 address-wildcard
+    binary-search probe of the mean error window and 2 per probe of the
+    source-interval lookup (bucket-table read plus its walk steps, or a
+    binary search when the index has no bucket table); for the port/protocol table of the first 64 address-wildcard
     rules, 2 per table read (the two high-byte tables, the walk steps, three
     masks, the rule entry) and 3 for combining the masks (two ANDs, one bit
     scan).  Bytes: the packet in, the result out, and a 32-byte record
@@ -97,15 +98,15 @@ def learned_work(rs, pk, idx, hidden: int = 32):
     e = lambda w: rs.export(w).astype(np.int64)
     B, off, L, err = e(0), e(1), e(2), rs.export(4).astype(np.float64)
     Bs, soff, S, Gw = e(6), e(7), e(8), e(9)
-    pt_count, steps_s, steps_d = (int(x) for x in rs.export(11))
+    pt_count, steps_s, steps_d, bs_bits, bs_steps = (int(x) for x in rs.export(11))
     rest = Gw[pt_count:]                 # the table holds the first pt_count entries
     ans = np.where(idx < 0, 1 << 40, idx.astype(np.int64))
     n_l = _list_checks(B, off, L, pk.dst_ip.astype(np.int64), ans)
     n_s = _list_checks(Bs, soff, S, pk.src_ip.astype(np.int64), ans)
     n_g = np.searchsorted(rest, ans, side="right")
     checks = int(n_l.sum() + n_s.sum() + n_g.sum())
-    probes = (math.ceil(math.log2(2.0 * float(err.mean()) + 1.0)) + 1
-              + math.ceil(math.log2(max(len(Bs), 1))) + 1)
+    src_probes = (1 + bs_steps) if bs_bits else math.ceil(math.log2(max(len(Bs), 1))) + 1
+    probes = math.ceil(math.log2(2.0 * float(err.mean()) + 1.0)) + 1 + src_probes
     table_ops = (2 * (2 + steps_s + steps_d + 4) + 3) if pt_count else 0
     ops = 2 * checks + len(pk) * (6 * hidden + 2 * probes + table_ops)
     gathered = int(n_l.sum() + n_s.sum())

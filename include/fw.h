@@ -233,8 +233,11 @@ fw_status fw_index_lookup(const fw_ruleset *rs, const uint32_t *keys, size_t n,
  *      entries [68] (rule index | action << 24, 0xFFFFFFFF = none), uint8
  *      high-byte tables [256] per port field (source first); bit r of a mask
  *      stands for the table's r-th rule;
- * 11 = the table's shape (uint32 [3]: rules in it, walk steps per source port,
- *      per destination port).
+ * 11 = lookup-table shapes (uint32 [5]: rules in the port/protocol table, its
+ *      walk steps per source port and per destination port; bits and walk
+ *      steps of the source-address bucket table, bits 0 = none);
+ * 12 = the source-address bucket table (uint16 [2^bits]): entry h is the
+ *      source interval (of 6) holding address h << (32 - bits).
  * Lists 2, 8 and 9 are cut where no later entry can be a first match (after a
  * rule that matches every packet reaching the list, and past the shared
  * list's first catch-all).

@@ -43,7 +43,10 @@ struct LearnedIndex {
     RuleRec* d_S = nullptr;
     std::vector<uint32_t> Bs, soff, S_idx, Gw_idx;
     PortTable pt{};               // the first address-wildcard candidates (host copy)
-    uint32_t pt_shape[3] = {0, 0, 0};   // rules in the table, walk steps per port field
+    // rules in the port table, its walk steps per port field; source bucket bits and steps
+    uint32_t pt_shape[5] = {0, 0, 0, 0, 0};
+    std::vector<uint16_t> bs_bucket;
+    uint16_t* d_bs_bucket = nullptr;
     PortTable* d_pt = nullptr;
     float* d_w1 = nullptr;
     uint16_t* d_w2 = nullptr;
@@ -241,7 +244,7 @@ void free_index_memory(LearnedIndex* ix) {
                     static_cast<void*>(ix->d_soff), static_cast<void*>(ix->d_S),
                     static_cast<void*>(ix->d_w1), static_cast<void*>(ix->d_w2),
                     static_cast<void*>(ix->d_meta), static_cast<void*>(ix->d_miss),
-                    static_cast<void*>(ix->d_pt)})
+                    static_cast<void*>(ix->d_pt), static_cast<void*>(ix->d_bs_bucket)})
         if (p) (void)hipFree(p);
 }
 
@@ -255,11 +258,16 @@ LookupArgs args_of(const LearnedIndex* ix, uint32_t use_net) {
     a.E = ix->E;
     a.off = ix->d_off;
     a.L = ix->d_L;
+    a.nL = uint32_t(ix->nL);
+    a.nS = uint32_t(ix->nS);
     a.G = ix->gplan.plan;
     a.pt = ix->d_pt;
     a.pt_count = ix->pt_shape[0];
     a.pt_steps_s = ix->pt_shape[1];
     a.pt_steps_d = ix->pt_shape[2];
+    a.bs_bucket = ix->d_bs_bucket;
+    a.bs_bits = ix->pt_shape[3];
+    a.bs_steps = ix->pt_shape[4];
     a.Bs = ix->d_Bs;
     a.Ms = ix->Ms;
     a.soff = ix->d_soff;
@@ -392,6 +400,41 @@ void build_port_table(const std::vector<RuleRec>& gw, PortTable* t, uint32_t* co
     field(0, t->mask_d, t->b_d, t->bucket_d, steps_d);
 }
 
+// Bucket table over the top `bits` bits of a 32-bit key for sorted interval
+// starts B (B[0] = 0): entry h is the interval holding key h << (32 - bits),
+// and `steps` forward steps from there reach the interval of any key of the
+// bucket (the most starts inside one bucket).  Bits are chosen for about four
+// buckets per interval, at most 12 (8 KiB of uint16); no table (bits = 0)
+// when the intervals do not fit uint16 or some bucket would need more than 8
+// steps, and the kernel then binary-searches B.
+void build_bucket_table(const std::vector<uint32_t>& B, std::vector<uint16_t>* table,
+                        uint32_t* bits, uint32_t* steps) {
+    table->clear();
+    *bits = 0;
+    *steps = 0;
+    const size_t M = B.size();
+    if (M < 2 || M > 0xFFFFu) return;
+    uint32_t b = 8;
+    while (b < 12 && (size_t(1) << b) < 4 * M) ++b;
+    const uint32_t shift = 32 - b;
+    table->resize(size_t(1) << b);
+    uint32_t longest = 0;
+    for (uint64_t h = 0; h < (uint64_t(1) << b); ++h) {
+        const uint32_t first = uint32_t(h << shift);
+        const uint32_t last = uint32_t(((h + 1) << shift) - 1);
+        const uint32_t i0 = uint32_t(std::upper_bound(B.begin(), B.end(), first) - B.begin()) - 1u;
+        const uint32_t i1 = uint32_t(std::upper_bound(B.begin(), B.end(), last) - B.begin()) - 1u;
+        (*table)[h] = uint16_t(i0);
+        longest = std::max(longest, i1 - i0);
+    }
+    if (longest > 8) {
+        table->clear();
+        return;
+    }
+    *bits = b;
+    *steps = longest;
+}
+
 // Destination intervals with their per-interval lists L_j (rules with a
 // specified destination), the shared destination-wildcard candidates G cut
 // at the first catch-all, and G split once more: rules of G with a specified
@@ -483,15 +526,22 @@ fw_status build_index(const fw_rule* rules, const RuleRec* recs, uint32_t n_rule
     fw_status st;
     try {
         st = build_lists(recs, n_rules, ix, &L, &S, &Gw);
-        if (st == FW_OK)
+        if (st == FW_OK) {
             build_port_table(Gw, &ix->pt, &ix->pt_shape[0], &ix->pt_shape[1], &ix->pt_shape[2],
                              &G);
+            build_bucket_table(ix->Bs, &ix->bs_bucket, &ix->pt_shape[3], &ix->pt_shape[4]);
+        }
     } catch (const std::bad_alloc&) {
         st = fail(FW_E_NOMEM, "host allocation failed while building candidate lists");
     }
     if (st != FW_OK) {
         delete ix;
         return st;
+    }
+    if (ix->nL * sizeof(RuleRec) > kMaxListBytes || ix->nS * sizeof(RuleRec) > kMaxListBytes) {
+        delete ix;
+        return fail(FW_E_NOMEM, "candidate lists exceed %llu bytes",
+                    (unsigned long long)kMaxListBytes);
     }
     const uint32_t M = ix->M, E = o.experts, H = o.hidden, P = 3 * H + 1;
     ix->E = E;
@@ -503,7 +553,7 @@ fw_status build_index(const fw_rule* rules, const RuleRec* recs, uint32_t n_rule
                           uint64_t(ix->nG ? ix->nG : 1) * sizeof(RuleRec) +
                           (uint64_t(ix->nG) + kPairPadding) * 8 + kGradCols * 4 +
                           uint64_t(E) * kInferStride * 2 + uint64_t(E) * sizeof(ExpertMeta) + 8 +
-                          sizeof(PortTable);
+                          sizeof(PortTable) + (uint64_t(1) << 12) * 2;
     if (o.mem_budget && keep > o.mem_budget) {
         delete ix;
         return fail(FW_E_NOMEM, "learned index needs %llu bytes, budget is %llu",
@@ -528,7 +578,8 @@ fw_status build_index(const fw_rule* rules, const RuleRec* recs, uint32_t n_rule
         (e = dalloc(&ix->d_w2, size_t(E) * kInferStride, &bytes)) != hipSuccess ||
         (e = dalloc(&ix->d_meta, E, &bytes)) != hipSuccess ||
         (e = dalloc(&ix->d_miss, 1, &bytes)) != hipSuccess ||
-        (e = dalloc(&ix->d_pt, 1, &bytes)) != hipSuccess)
+        (e = dalloc(&ix->d_pt, 1, &bytes)) != hipSuccess ||
+        (e = dalloc(&ix->d_bs_bucket, ix->bs_bucket.size(), &bytes)) != hipSuccess)
         return bail(e, "allocating the learned index");
     ix->device_bytes = bytes;
     if ((e = upload(ix->d_B, ix->B, s)) != hipSuccess ||
@@ -536,6 +587,7 @@ fw_status build_index(const fw_rule* rules, const RuleRec* recs, uint32_t n_rule
         (e = upload(ix->d_L, L, s)) != hipSuccess || (e = upload(ix->d_Bs, ix->Bs, s)) != hipSuccess ||
         (e = upload(ix->d_soff, ix->soff, s)) != hipSuccess ||
         (e = upload(ix->d_S, S, s)) != hipSuccess ||
+        (e = upload(ix->d_bs_bucket, ix->bs_bucket, s)) != hipSuccess ||
         (e = hipMemcpyAsync(ix->d_pt, &ix->pt, sizeof(PortTable), hipMemcpyHostToDevice, s)) !=
             hipSuccess ||
         (e = hipStreamSynchronize(s)) != hipSuccess ||
@@ -796,6 +848,7 @@ fw_status index_export(const LearnedIndex* ix, uint32_t what, void* host, size_t
         case 9: src = ix->Gw_idx.data(); bytes = ix->Gw_idx.size() * 4; break;
         case 10: src = &ix->pt; bytes = sizeof(PortTable); break;
         case 11: src = ix->pt_shape; bytes = sizeof ix->pt_shape; break;
+        case 12: src = ix->bs_bucket.data(); bytes = ix->bs_bucket.size() * 2; break;
         default: return fail(FW_E_INVAL, "unknown export %u", what);
     }
     if (size) *size = bytes;

@@ -76,6 +76,13 @@ struct alignas(16) PortTable {
 static_assert(sizeof(PortTable) % 16 == 0, "staged as 16-byte words");
 constexpr uint32_t kPtNone = 0xFFFFFFFFu;
 
+// The per-lane lists are read with 32-bit buffer offsets: each list array is
+// kept below kMaxListBytes, and kListPastEnd (above it) marks a lane with
+// nothing to load.
+constexpr uint64_t kMaxListBytes = 0x7FFF0000ull;
+constexpr uint32_t kListPastEnd = 0x7FFFFFF0u;
+static_assert(kListPastEnd > kMaxListBytes + 32, "past-the-end offset must be out of range");
+
 // Everything the lookup kernel reads.
 struct LookupArgs {
     const uint32_t* B;        // M boundaries
@@ -86,6 +93,7 @@ struct LookupArgs {
     uint32_t E;
     const uint32_t* off;      // M + 1 per-interval list offsets
     const RuleRec* L;         // per-interval candidate records
+    uint32_t nL;              // records in L
     const PortTable* pt;      // the first address-wildcard candidates (see PortTable)
     uint32_t pt_count;        // rules in the table (0: none)
     uint32_t pt_steps_s;      // forward steps after the high-byte table, per port field
@@ -93,8 +101,12 @@ struct LookupArgs {
     ScanPlan G;               // the remaining address-wildcard candidates (grouped plan)
     const uint32_t* Bs;       // source intervals of the other destination-wildcard candidates
     uint32_t Ms;
+    const uint16_t* bs_bucket; // interval holding the first address of each top-bits bucket
+    uint32_t bs_bits;         // bucket bits (0: binary search over Bs instead)
+    uint32_t bs_steps;        // forward steps after the bucket table
     const uint32_t* soff;     // Ms + 1 per-source-interval list offsets
     const RuleRec* S;         // per-source-interval candidate records
+    uint32_t nS;              // records in S
     uint32_t use_net;         // 0: full binary search only
     unsigned long long* miss; // optional window-miss counter
 };

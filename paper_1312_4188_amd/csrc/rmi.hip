@@ -15,6 +15,7 @@
 // product S^T * A, which runs on the matrix cores as bf16 x bf16 -> fp32 MFMA
 // (S is exact in bf16).  A plain fp32 reduction computes the same sums for
 // checking.
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -262,16 +263,31 @@ __device__ __forceinline__ uint32_t search_le(const uint32_t* B, uint32_t lo, ui
     return lo;
 }
 
+// Interval of x among the M sorted starts B (B[0] = 0) through a bucket table
+// over its top `bits` bits: the bucket's entry is the interval holding the
+// bucket's first key, and `steps` forward steps (never past the last
+// interval) reach x's interval.
+__device__ __forceinline__ uint32_t bucket_walk(const uint16_t* bucket, const uint32_t* B,
+                                                uint32_t M, uint32_t bits, uint32_t steps,
+                                                uint32_t x) {
+    uint32_t i = bucket[x >> (32u - bits)];
+    for (uint32_t k = 0; k < steps; ++k) i += (i + 1u < M && B[i + 1u] <= x) ? 1u : 0u;
+    return i;
+}
+
 // Interval of x: the window [p - err, p + err] of the predicted position first,
 // checked by B[j] <= x < B[j+1]; a miss falls back to the full range.
-template <class W2>
+// Expert rows and records may sit at a padded stride (W2_STRIDE weights,
+// META_BYTES bytes) in LDS; see lds_layout.
+template <uint32_t W2_STRIDE, uint32_t META_BYTES, class W2>
 __device__ __forceinline__ uint32_t locate(const uint32_t* B, uint32_t M, const float* w1,
                                            const W2* w2, const ExpertMeta* meta, uint32_t E,
                                            uint32_t use_net, uint32_t x, bool* miss) {
     if (use_net) {
         const uint32_t e = route(w1, E, x);
-        const ExpertMeta m = meta[e];
-        const int32_t p = position(w2 + size_t(e) * kInferStride, m, x);
+        const ExpertMeta m = *reinterpret_cast<const ExpertMeta*>(
+            reinterpret_cast<const unsigned char*>(meta) + size_t(e) * META_BYTES);
+        const int32_t p = position(w2 + size_t(e) * W2_STRIDE, m, x);
         const int64_t lo = int64_t(p) - int64_t(m.err), hi = int64_t(p) + int64_t(m.err);
         const uint32_t l = uint32_t(lo < 0 ? 0 : (lo >= int64_t(M) ? M - 1 : lo));
         const uint32_t h = uint32_t(hi < int64_t(l) ? l : (hi >= int64_t(M) ? M - 1 : hi));
@@ -305,6 +321,46 @@ __global__ void k_err_bound(LookupArgs a, const uint32_t* __restrict__ keys,
     const int32_t p = position(a.w2 + size_t(e) * kInferStride, a.meta[e], x);
     const int32_t d = p - pos[i];
     atomicMax(err + e, uint32_t(d < 0 ? -d : d));
+}
+
+// Per-lane list records through buffer loads.  The resource covers the
+// list's bytes; a byte offset of kPastEnd (beyond any list the index
+// accepts) is out of range, and an out-of-range buffer load returns zeros
+// without touching memory.
+constexpr uint32_t kPastEnd = kListPastEnd;
+constexpr uint32_t kBufferDword3 = 0x00020000u;   // raw buffer, gfx9-family format bits
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t list_rsrc(const RuleRec* base, uint32_t count) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<RuleRec*>(base), 0,
+                                             int(count * uint32_t(sizeof(RuleRec))),
+                                             int(kBufferDword3));
+}
+
+__device__ __forceinline__ RuleRec list_record(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+    const uint4 lo = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, int(byte_off), 0, 0));
+    const uint4 hi = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, int(byte_off + 16u), 0, 0));
+    RuleRec q;
+    q.src_lo = lo.x;
+    q.src_w = lo.y;
+    q.dst_lo = lo.z;
+    q.dst_w = lo.w;
+    q.port_lo = hi.x;
+    q.port_w = hi.y;
+    q.proto = hi.z;
+    q.idx = hi.w;
+    return q;
+}
+
+// Only the second half (ports, protocol, index): enough for lists whose
+// address tests are implied.
+__device__ __forceinline__ RuleRec list_record_tail(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+    const uint4 hi = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, int(byte_off + 16u), 0, 0));
+    RuleRec q{};
+    q.port_lo = hi.x;
+    q.port_w = hi.y;
+    q.proto = hi.z;
+    q.idx = hi.w;
+    return q;
 }
 
 // First rule of a port/protocol table that the packet matches, as
@@ -342,23 +398,48 @@ __device__ __forceinline__ uint32_t port_table_first(const PortTable& t, uint32_
 constexpr uint32_t kLearnedBlock = 1024;
 constexpr uint32_t kLearnedK = 2;     // default packets per lane in the classify kernel
 
-__host__ __device__ inline size_t lds_layout(uint32_t E, uint32_t M, uint32_t Ms, bool b_lds,
-                                             bool w2_f32, size_t* off_meta, size_t* off_w2,
-                                             size_t* off_pt, size_t* off_b, size_t* off_bs) {
+// LDS strides of the per-expert data, chosen so that lanes reading different
+// experts spread over all LDS banks: a row of fp32 weights at 104 dwords
+// would put every expert on one of only 4 bank offsets (104 e mod 32 takes
+// 4 values), at 100 dwords on 8 (32 banks) or 16 (64 banks), each 16-byte
+// read covering 4 banks.  bf16 rows (52 dwords) and 48-byte expert records
+// (12 dwords) spread the same way.
+constexpr uint32_t kLdsStrideF32 = 100;     // >= 97 weights used per row, 16-byte multiple
+constexpr uint32_t kLdsStrideBf16 = kInferStride;
+constexpr uint32_t kLdsMetaBytes = 48;
+static_assert(kLdsStrideF32 >= 3 * 32 + 1 && kLdsStrideF32 % 4 == 0, "fp32 row layout");
+static_assert(kLdsMetaBytes >= sizeof(ExpertMeta) && kLdsMetaBytes % 16 == 0, "record layout");
+
+__host__ __device__ inline size_t lds_layout(uint32_t E, uint32_t M, uint32_t Ms, uint32_t bs_bits,
+                                             bool b_lds, bool w2_f32, size_t* off_meta,
+                                             size_t* off_w2, size_t* off_pt, size_t* off_bk,
+                                             size_t* off_b, size_t* off_bs) {
     size_t o = kInferStride * sizeof(float);
     *off_meta = o;
-    o += size_t(E) * sizeof(ExpertMeta);
+    o += size_t(E) * kLdsMetaBytes;
     o = (o + 15) & ~size_t(15);
     *off_w2 = o;
-    o += size_t(E) * kInferStride * (w2_f32 ? sizeof(float) : sizeof(uint16_t));
+    o += size_t(E) * (w2_f32 ? kLdsStrideF32 * sizeof(float) : kLdsStrideBf16 * sizeof(uint16_t));
     o = (o + 15) & ~size_t(15);
     *off_pt = o;
     o += sizeof(PortTable);
+    *off_bk = o;
+    if (bs_bits) o += (size_t(2) << bs_bits);
     *off_b = o;
     if (b_lds) o += size_t(M) * sizeof(uint32_t);
     *off_bs = o;
     if (b_lds) o += size_t(Ms) * sizeof(uint32_t);
     return o;
+}
+
+// With the boundary arrays in LDS, the list offsets (off: M + 1, soff:
+// Ms + 1 entries) follow them there, so a packet's list bounds cost no
+// global load.
+__host__ __device__ inline size_t lds_offsets(uint32_t M, uint32_t Ms, size_t end, size_t* off_off,
+                                              size_t* off_soff) {
+    *off_off = end;
+    *off_soff = end + (size_t(M) + 1) * sizeof(uint32_t);
+    return *off_soff + (size_t(Ms) + 1) * sizeof(uint32_t);
 }
 
 template <class W2>
@@ -369,6 +450,9 @@ struct IndexView {
     const uint32_t* B;
     const uint32_t* Bs;
     const PortTable* pt;
+    const uint16_t* bs_bucket;
+    const uint32_t* off;
+    const uint32_t* soff;
 };
 
 // Stage the index into LDS; stage-2 weights stay bf16 (W2 = uint16_t) or are
@@ -376,9 +460,14 @@ struct IndexView {
 template <bool B_LDS, class W2>
 __device__ __forceinline__ IndexView<W2> stage_index(const LookupArgs& a, unsigned char* smem) {
     constexpr bool kF32 = sizeof(W2) == 4;
-    size_t o_meta, o_w2, o_pt, o_b, o_bs;
-    lds_layout(a.E, a.M, a.Ms, B_LDS, kF32, &o_meta, &o_w2, &o_pt, &o_b, &o_bs);
+    size_t o_meta, o_w2, o_pt, o_bk, o_b, o_bs, o_off, o_soff;
+    const size_t end = lds_layout(a.E, a.M, a.Ms, a.bs_bits, B_LDS, kF32, &o_meta, &o_w2, &o_pt,
+                                  &o_bk, &o_b, &o_bs);
+    lds_offsets(a.M, a.Ms, end, &o_off, &o_soff);
+    uint32_t* s_off = reinterpret_cast<uint32_t*>(smem + o_off);
+    uint32_t* s_soff = reinterpret_cast<uint32_t*>(smem + o_soff);
     PortTable* s_pt = reinterpret_cast<PortTable*>(smem + o_pt);
+    uint16_t* s_bk = reinterpret_cast<uint16_t*>(smem + o_bk);
     float* s_w1 = reinterpret_cast<float*>(smem);
     ExpertMeta* s_meta = reinterpret_cast<ExpertMeta*>(smem + o_meta);
     W2* s_w2 = reinterpret_cast<W2*>(smem + o_w2);
@@ -386,11 +475,14 @@ __device__ __forceinline__ IndexView<W2> stage_index(const LookupArgs& a, unsign
     uint32_t* s_bs = reinterpret_cast<uint32_t*>(smem + o_bs);
     const uint32_t tid = threadIdx.x;
     for (uint32_t k = tid; k < kInferStride; k += kLearnedBlock) s_w1[k] = a.w1[k];
-    for (uint32_t k = tid; k < a.E * 8u; k += kLearnedBlock)
-        reinterpret_cast<uint32_t*>(s_meta)[k] = reinterpret_cast<const uint32_t*>(a.meta)[k];
+    for (uint32_t k = tid; k < a.E * 8u; k += kLearnedBlock)   // 8 words per record
+        reinterpret_cast<uint32_t*>(smem + o_meta)[(k >> 3) * (kLdsMetaBytes / 4u) + (k & 7u)] =
+            reinterpret_cast<const uint32_t*>(a.meta)[k];
     if constexpr (kF32) {
-        for (uint32_t k = tid; k < a.E * kInferStride; k += kLearnedBlock)
-            s_w2[k] = bf16_to_f32(a.w2[k]);
+        for (uint32_t k = tid; k < a.E * kLdsStrideF32; k += kLearnedBlock) {
+            const uint32_t e = k / kLdsStrideF32, c = k % kLdsStrideF32;
+            s_w2[k] = bf16_to_f32(a.w2[e * kInferStride + c]);   // c < 100 <= 104
+        }
     } else {
         for (uint32_t k = tid; k < a.E * kInferStride / 2u; k += kLearnedBlock)
             reinterpret_cast<uint32_t*>(s_w2)[k] = reinterpret_cast<const uint32_t*>(a.w2)[k];
@@ -399,26 +491,33 @@ __device__ __forceinline__ IndexView<W2> stage_index(const LookupArgs& a, unsign
         for (uint32_t k = tid; k < sizeof(PortTable) / 16u; k += kLearnedBlock)
             reinterpret_cast<uint4*>(s_pt)[k] = reinterpret_cast<const uint4*>(a.pt)[k];
     }
+    if (a.bs_bits) {   // 2^bits uint16 entries, bits >= 8: whole 16-byte words
+        for (uint32_t k = tid; k < (1u << a.bs_bits) / 8u; k += kLearnedBlock)
+            reinterpret_cast<uint4*>(s_bk)[k] = reinterpret_cast<const uint4*>(a.bs_bucket)[k];
+    }
     if constexpr (B_LDS) {
         for (uint32_t k = tid; k < a.M; k += kLearnedBlock) s_b[k] = a.B[k];
         for (uint32_t k = tid; k < a.Ms; k += kLearnedBlock) s_bs[k] = a.Bs[k];
+        for (uint32_t k = tid; k <= a.M; k += kLearnedBlock) s_off[k] = a.off[k];
+        for (uint32_t k = tid; k <= a.Ms; k += kLearnedBlock) s_soff[k] = a.soff[k];
     }
     __syncthreads();
-    return IndexView<W2>{s_w1, s_meta, s_w2, B_LDS ? s_b : a.B, B_LDS ? s_bs : a.Bs, s_pt};
+    return IndexView<W2>{s_w1, s_meta, s_w2, B_LDS ? s_b : a.B, B_LDS ? s_bs : a.Bs, s_pt, s_bk,
+                         B_LDS ? s_off : a.off, B_LDS ? s_soff : a.soff};
 }
 
 // With one or two packets per lane, two work-groups per CU (the LDS footprint
 // allows two): eight waves per SIMD, so at most 64 VGPRs.  Four packets per
-// lane need more registers and run one work-group per CU.
-template <bool B_LDS, int K>
+// lane need more registers and run one work-group per CU.  W2F32: the expert
+// weights are widened to fp32 while staged (exact), so the loop reads them
+// without converting; chosen whenever the LDS budget has room.
+template <bool B_LDS, int K, bool W2F32>
 __global__ __launch_bounds__(kLearnedBlock, K >= 4 ? 4 : 8) void k_learned(LookupArgs a, PacketsDev pk, size_t n,
                                                            int32_t* __restrict__ out_idx,
                                                            uint8_t* __restrict__ out_act,
                                                            uint32_t dflt) {
     extern __shared__ __align__(16) unsigned char smem[];
-    // four packets per lane already limit the kernel to one work-group per CU,
-    // so the LDS can hold fp32 expert weights (no widening in the loop)
-    using W2 = typename std::conditional<(K >= 4), float, uint16_t>::type;
+    using W2 = typename std::conditional<W2F32, float, uint16_t>::type;
     const IndexView<W2> v = stage_index<B_LDS, W2>(a, smem);
     const uint32_t lane = threadIdx.x & 63u;
     constexpr uint32_t kWaves = kLearnedBlock / 64;   // compile-time: keeps the loop scalar
@@ -434,12 +533,14 @@ __global__ __launch_bounds__(kLearnedBlock, K >= 4 ? 4 : 8) void k_learned(Looku
         for (int s = 0; s < K; ++s) {
             const bool valid = w.p0 + s < n;
             bool miss = false;
-            jj[s] = locate(v.B, a.M, v.w1, v.w2, v.meta, a.E, a.use_net, w.dst[s], &miss);
+            jj[s] = locate<W2F32 ? kLdsStrideF32 : kLdsStrideBf16, kLdsMetaBytes>(
+                v.B, a.M, v.w1, v.w2, v.meta, a.E, a.use_net, w.dst[s], &miss);
             if (a.miss) {
                 const uint64_t mm = ballot(valid && miss);
                 if (lane == 0 && mm) atomicAdd(a.miss, (unsigned long long)__popcll(mm));
             }
-            si[s] = search_le(v.Bs, 0, a.Ms - 1u, w.src[s]);
+            si[s] = a.bs_bits ? bucket_walk(v.bs_bucket, v.Bs, a.Ms, a.bs_bits, a.bs_steps, w.src[s])
+                              : search_le(v.Bs, 0, a.Ms - 1u, w.src[s]);
             lbest[s] = kNoMatch;
             lact[s] = dflt;
         }
@@ -455,33 +556,70 @@ __global__ __launch_bounds__(kLearnedBlock, K >= 4 ? 4 : 8) void k_learned(Looku
                 }
             }
         }
-        // the per-lane lists, each ascending: stop at the first match or once
-        // an entry can no longer beat the best so far
+        // The per-lane lists: the destination-interval list, and the source-
+        // interval list of the destination-wildcard candidates with a
+        // specified source (a packet's source interval lists exactly those
+        // whose source test it passes).  Each is ascending and ends at its
+        // first match or at the first entry that can no longer beat the best
+        // so far, so the answer is the minimum over lists.  All K packets'
+        // lists advance together, one entry each per round, so the round's
+        // 2K record loads are in flight at once.
+        const __amdgpu_buffer_rsrc_t rl = list_rsrc(a.L, a.nL);
+        const __amdgpu_buffer_rsrc_t rs_ = list_rsrc(a.S, a.nS);
+        uint32_t lk[K], le[K], sk[K], se[K];
 #pragma unroll
-        for (int s = 0; s < K; ++s) {
-            if (w.p0 + s >= n) continue;
-            const uint32_t kb = a.off[jj[s]], ke = a.off[jj[s] + 1u];
-            for (uint32_t k = kb; k < ke; ++k) {
-                const RuleRec q = a.L[k];
-                if (q.idx > lbest[s]) break;
-                if (match_no_dst(q, w.src[s], w.pp[s], w.pr[s])) {
-                    lbest[s] = q.idx;
-                    lact[s] = rule_action(q.proto);
-                    break;
-                }
+        for (int s = 0; s < K; ++s) {   // plain loads, all issued before the first use
+            const uint32_t l0 = v.off[jj[s]], l1 = v.off[jj[s] + 1u];
+            const uint32_t s0 = v.soff[si[s]], s1 = v.soff[si[s] + 1u];
+            const bool valid = w.p0 + s < n;
+            lk[s] = l0;
+            le[s] = valid ? l1 : l0;
+            sk[s] = s0;
+            se[s] = valid ? s1 : s0;
+        }
+        for (;;) {
+            bool more = false;
+#pragma unroll
+            for (int s = 0; s < K; ++s) more = more || lk[s] < le[s] || sk[s] < se[s];
+            if (ballot(more) == 0) break;
+            // Buffer loads: a lane whose list is exhausted passes an offset
+            // past the end of the array, so its load returns zeros without a
+            // memory access, and no branch separates the loads.
+            RuleRec ql[K], qs[K];
+#pragma unroll
+            for (int s = 0; s < K; ++s) {
+                ql[s] = list_record(rl, lk[s] < le[s] ? lk[s] * uint32_t(sizeof(RuleRec)) : kPastEnd);
+                qs[s] = list_record_tail(rs_, sk[s] < se[s] ? sk[s] * uint32_t(sizeof(RuleRec))
+                                                            : kPastEnd);
             }
-            // destination-wildcard candidates with a specified source: the
-            // packet's source interval lists exactly those whose source test
-            // it passes
-            const uint32_t sb = a.soff[si[s]], se = a.soff[si[s] + 1u];
-            for (uint32_t k = sb; k < se; ++k) {
-                const RuleRec q = a.S[k];
-                if (q.idx > lbest[s]) break;
-                if (ports_in(w.pp[s], q.port_lo, q.port_w) &&
-                    in_range(w.pr[s], proto_lo(q.proto), proto_w(q.proto))) {
-                    lbest[s] = q.idx;
-                    lact[s] = rule_action(q.proto);
-                    break;
+            // straight-line updates (selects, no branches), so no load is
+            // sunk into a conditional block behind another's wait
+#pragma unroll
+            for (int s = 0; s < K; ++s) {
+                {
+                    const RuleRec& q = ql[s];
+                    const bool on = lk[s] < le[s];
+                    const bool beats = q.idx < lbest[s];
+                    const bool m = (unsigned(on) & unsigned(beats) &
+                                    unsigned(in_range(w.src[s], q.src_lo, q.src_w)) &
+                                    unsigned(ports_in(w.pp[s], q.port_lo, q.port_w)) &
+                                    unsigned(in_range(w.pr[s], proto_lo(q.proto),
+                                                      proto_w(q.proto)))) != 0u;
+                    lbest[s] = m ? q.idx : lbest[s];
+                    lact[s] = m ? rule_action(q.proto) : lact[s];
+                    lk[s] = on ? ((m | !beats) ? le[s] : lk[s] + 1u) : lk[s];
+                }
+                {
+                    const RuleRec& q = qs[s];
+                    const bool on = sk[s] < se[s];
+                    const bool beats = q.idx < lbest[s];
+                    const bool m = (unsigned(on) & unsigned(beats) &
+                                    unsigned(ports_in(w.pp[s], q.port_lo, q.port_w)) &
+                                    unsigned(in_range(w.pr[s], proto_lo(q.proto),
+                                                      proto_w(q.proto)))) != 0u;
+                    lbest[s] = m ? q.idx : lbest[s];
+                    lact[s] = m ? rule_action(q.proto) : lact[s];
+                    sk[s] = on ? ((m | !beats) ? se[s] : sk[s] + 1u) : sk[s];
                 }
             }
         }
@@ -496,13 +634,14 @@ __global__ __launch_bounds__(kLearnedBlock, K >= 4 ? 4 : 8) void k_learned(Looku
 }
 
 // Interval lookup only, one key per lane.
-template <bool B_LDS>
+template <bool B_LDS, bool W2F32>
 __global__ __launch_bounds__(kLearnedBlock) void k_lookup(LookupArgs a,
                                                           const uint32_t* __restrict__ keys,
                                                           size_t n,
                                                           int32_t* __restrict__ out_interval) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const IndexView<uint16_t> v = stage_index<B_LDS, uint16_t>(a, smem);
+    using W2 = typename std::conditional<W2F32, float, uint16_t>::type;
+    const IndexView<W2> v = stage_index<B_LDS, W2>(a, smem);
     constexpr uint32_t kWaves = kLearnedBlock / 64;   // compile-time: keeps the loop scalar
     const size_t waves = size_t(gridDim.x) * kWaves;
     const size_t wave0 = size_t(blockIdx.x) * kWaves + wave_in_group();
@@ -510,8 +649,8 @@ __global__ __launch_bounds__(kLearnedBlock) void k_lookup(LookupArgs a,
         const size_t i = base + (threadIdx.x & 63u);
         const bool valid = i < n;
         bool miss = false;
-        const uint32_t j = locate(v.B, a.M, v.w1, v.w2, v.meta, a.E, a.use_net,
-                                  valid ? keys[i] : 0u, &miss);
+        const uint32_t j = locate<W2F32 ? kLdsStrideF32 : kLdsStrideBf16, kLdsMetaBytes>(
+            v.B, a.M, v.w1, v.w2, v.meta, a.E, a.use_net, valid ? keys[i] : 0u, &miss);
         if (valid) out_interval[i] = int32_t(j);
     }
 }
@@ -642,8 +781,10 @@ hipError_t launch_err_bound(const LookupArgs& a, const uint32_t* keys, const int
 }
 
 size_t learned_lds_bytes(const LookupArgs& a, bool b_in_lds, bool w2_f32) {
-    size_t o1, o2, o3, o4, o5;
-    return lds_layout(a.E, a.M, a.Ms, b_in_lds, w2_f32, &o1, &o2, &o3, &o4, &o5);
+    size_t o1, o2, o3, o4, o5, o6, o7, o8;
+    const size_t end =
+        lds_layout(a.E, a.M, a.Ms, a.bs_bits, b_in_lds, w2_f32, &o1, &o2, &o3, &o4, &o5, &o6);
+    return b_in_lds ? lds_offsets(a.M, a.Ms, end, &o7, &o8) : end;
 }
 
 hipError_t launch_learned(const LookupArgs& a, PacketsDev pk, size_t n, int32_t* out_idx,
@@ -661,32 +802,37 @@ hipError_t launch_learned(const LookupArgs& a, PacketsDev pk, size_t n, int32_t*
         if (e != hipSuccess) return e;
         g_cache.device = dev;
     }
-    // keep two work-groups of 16 waves per CU: boundary arrays in LDS up to 80 KiB in all
+    // One or two packets per lane keep two work-groups of 16 waves per CU, so
+    // the staged index must stay within 80 KiB; four per lane run one
+    // work-group per CU and may use up to 150 KiB.  In that budget the
+    // boundary arrays and list offsets come first (the binary searches probe
+    // them, every packet reads its list bounds), fp32 expert weights second.
     const uint32_t K = packets_per_lane ? packets_per_lane : kLearnedK;
-    const bool f32 = !keys && K >= 4;
-    // one or two packets per lane: keep two work-groups of 16 waves per CU, so
-    // the boundary arrays go to LDS only while everything stays within 80 KiB;
-    // four per lane run one work-group per CU and may use up to 150 KiB
-    const size_t budget = f32 ? 150u * 1024u : 80u * 1024u;
-    const size_t with_b = learned_lds_bytes(a, true, f32);
-    const bool b_lds = with_b <= size_t(g_cache.max_lds) && with_b <= budget;
-    const size_t lds = b_lds ? with_b : learned_lds_bytes(a, false, f32);
+    const size_t cap = std::min<size_t>(K >= 4 ? 150u * 1024u : 80u * 1024u,
+                                        size_t(g_cache.max_lds));
+    bool b_lds = false, f32 = false;
+    size_t lds = 0;
+    for (int option = 0; option < 4; ++option) {
+        b_lds = option < 2;
+        f32 = option % 2 == 0;
+        lds = learned_lds_bytes(a, b_lds, f32);
+        if (lds <= cap) break;
+    }
     if (keys) {
         const size_t tiles = (n + 63) / 64;
-        return b_lds ? launch_persistent(k_lookup<true>, lds, tiles, s, a, keys, n, out_interval)
-                     : launch_persistent(k_lookup<false>, lds, tiles, s, a, keys, n, out_interval);
+#define FW_LOOKUP(BL, F) launch_persistent(k_lookup<BL, F>, lds, tiles, s, a, keys, n, out_interval)
+        if (b_lds) return f32 ? FW_LOOKUP(true, true) : FW_LOOKUP(true, false);
+        return f32 ? FW_LOOKUP(false, true) : FW_LOOKUP(false, false);
+#undef FW_LOOKUP
     }
     const size_t tiles = (n + 64 * K - 1) / (64 * K);
-#define FW_LEARNED(BL, KK) \
-    launch_persistent(k_learned<BL, KK>, lds, tiles, s, a, pk, n, out_idx, out_act, dflt)
-    if (b_lds) {
-        if (K == 1) return FW_LEARNED(true, 1);
-        if (K == 2) return FW_LEARNED(true, 2);
-        return FW_LEARNED(true, 4);
-    }
-    if (K == 1) return FW_LEARNED(false, 1);
-    if (K == 2) return FW_LEARNED(false, 2);
-    return FW_LEARNED(false, 4);
+#define FW_LEARNED(BL, KK, F) \
+    launch_persistent(k_learned<BL, KK, F>, lds, tiles, s, a, pk, n, out_idx, out_act, dflt)
+#define FW_LEARNED_K(BL, F)                          \
+    (K == 1 ? FW_LEARNED(BL, 1, F) : K == 2 ? FW_LEARNED(BL, 2, F) : FW_LEARNED(BL, 4, F))
+    if (b_lds) return f32 ? FW_LEARNED_K(true, true) : FW_LEARNED_K(true, false);
+    return f32 ? FW_LEARNED_K(false, true) : FW_LEARNED_K(false, false);
+#undef FW_LEARNED_K
 #undef FW_LEARNED
 }
 

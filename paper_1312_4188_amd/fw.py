@@ -297,7 +297,7 @@ class Ruleset:
 
     _EXPORT = {0: np.uint32, 1: np.uint32, 2: np.uint32, 3: np.uint32, 4: np.uint32,
                5: np.float32, 6: np.uint32, 7: np.uint32, 8: np.uint32, 9: np.uint32,
-               10: np.uint8, 11: np.uint32}
+               10: np.uint8, 11: np.uint32, 12: np.uint16}
 
     def export(self, what: int) -> np.ndarray:
         lib = load_library()

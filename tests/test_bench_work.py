@@ -36,7 +36,7 @@ class _FakeIndex:
         cat = lambda lists: (np.concatenate(lists) if lists else np.zeros(0, np.int64))
         return {0: self.B, 1: off(self.L), 2: cat(self.L), 4: np.array([3.0, 5.0]),
                 6: self.Bs, 7: off(self.S), 8: cat(self.S), 9: self.Gw,
-                11: np.array([self.table, 2, 3])}[what]
+                11: np.array([self.table, 2, 3, 0, 0])}[what]
 
 
 def test_candidate_checks_match_brute_force():

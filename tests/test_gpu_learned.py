@@ -329,3 +329,30 @@ def test_learned_with_many_address_wildcard_rules(seed, R, frac):
     for ppl in (1, 2, 4):
         got, _, _ = _learned_np(rules, pk, packets_per_lane=ppl)
         assert_same(got, want, f"seed={seed} R={R} K={ppl}")
+
+
+@pytest.mark.parametrize("seed,R", [(1, 10000), (2, 3000), (3, 200)])
+def test_source_bucket_table(seed, R):
+    """The source-address bucket table plus its walk gives the interval of every key the
+    textbook upper_bound gives: at every boundary and its neighbours, at every bucket start,
+    and at random keys."""
+    fw = fwmod()
+    rules = gen.make_rules(R, seed, skew=True)
+    with fw.Ruleset(rules) as rs:
+        rs.build_learned_index(**FAST)
+        Bs, shape, table = rs.export(6), rs.export(11), rs.export(12)
+    bits, steps = int(shape[3]), int(shape[4])
+    if bits == 0:
+        assert table.size == 0
+        return
+    assert table.size == 1 << bits and steps <= 8
+    B = Bs.astype(np.int64)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    keys = np.unique(np.concatenate([B, B - 1, B + 1, np.arange(1 << bits) << (32 - bits),
+                                     rng.integers(0, 1 << 32, 100_000), [0, (1 << 32) - 1]]))
+    keys = keys[(keys >= 0) & (keys < (1 << 32))]
+    i = table.astype(np.int64)[keys >> (32 - bits)]
+    for _ in range(steps):
+        nxt = np.minimum(i + 1, len(B) - 1)
+        i = i + ((i + 1 < len(B)) & (B[nxt] <= keys))
+    np.testing.assert_array_equal(i, np.searchsorted(B, keys, side="right") - 1)
