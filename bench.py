@@ -206,8 +206,9 @@ def serving_leg(seed: int, n_req: int, loads, log_fn):
     ta, out_a = pinned(total, torch.uint8)
     out = {"chains": build, "requests": n_req, "packets": total, "modes": {}}
     mean_batch = total / n_req
-    for mode in ("auto", "packet_split"):
-        with fw.Server(rsets, slots=8, mode=mode) as sv:
+    for mode, slots, pipe in (("auto", 8, False), ("auto", 4, False), ("auto", 4, True),
+                              ("packet_split", 8, False)):
+        with fw.Server(rsets, slots=slots, mode=mode, pipeline=pipe) as sv:
             zero = np.zeros(n_req)
             sv.replay(zero[:32], chain[:32], offset[:32], sizes[:32], pool, out_i, out_a)
             t = sv.replay(zero, chain, offset, sizes, pool, out_i, out_a)
@@ -224,9 +225,12 @@ def serving_leg(seed: int, n_req: int, loads, log_fn):
                                      "achieved_mpps": total / span / 1e6,
                                      "p50_us": float(np.percentile(lat, 50)),
                                      "p99_us": float(np.percentile(lat, 99))})
-                log_fn(f"  serving {mode} load {frac:.0%}: p50 {res['loads'][-1]['p50_us']:.0f} us "
+                log_fn(f"  serving {mode} {slots} slots{' pipeline' if pipe else ''} load {frac:.0%}: "
+                       f"p50 {res['loads'][-1]['p50_us']:.0f} us "
                        f"p99 {res['loads'][-1]['p99_us']:.0f} us")
-            out["modes"]["learned" if mode == "auto" else mode] = res
+            res["slots"], res["pipeline"] = slots, pipe
+            key = ("learned" if mode == "auto" else mode) + ("" if slots == 8 else f"_{slots}slots")
+            out["modes"][key + ("_pipeline" if pipe else "")] = res
     for rs in rsets:
         rs.close()
     return out
@@ -257,16 +261,17 @@ def ingest_leg(rs, pk, ref_idx, chunk: int, log_fn):
     chain = np.zeros(len(sizes), dtype=np.uint32)
     zero = np.zeros(len(sizes))
     out = {"packets": n, "chunk": chunk, "bytes_per_packet": BYTES_PER_PACKET}
-    for slots in (1, 8):
-        with fw.Server([rs], slots=slots, mem_budget=1 << 30) as sv:
+    for slots, pipe in ((1, False), (2, False), (4, False), (8, False), (2, True), (4, True)):
+        with fw.Server([rs], slots=slots, mem_budget=1 << 30, pipeline=pipe) as sv:
             sv.replay(zero[:2], chain[:2], offset[:2], sizes[:2], pool, out_i, out_a)  # warm
             out_i[:] = -2
             t = sv.replay(zero, chain, offset, sizes, pool, out_i, out_a)
             span = float(t[:, 2].max() - t[:, 0].min())
-            out[f"slots_{slots}"] = {"s": span, "mpps": n / span / 1e6,
-                                     "pcie_gbs": n * BYTES_PER_PACKET / span / 1e9,
-                                     "same_as_device": bool(np.array_equal(out_i, ref_idx))}
-            log_fn(f"  ingest {slots} slot(s): {n / span / 1e6:.0f} Mpps "
+            name = f"slots_{slots}" + ("_pipeline" if pipe else "")
+            out[name] = {"s": span, "mpps": n / span / 1e6,
+                         "pcie_gbs": n * BYTES_PER_PACKET / span / 1e9,
+                         "same_as_device": bool(np.array_equal(out_i, ref_idx))}
+            log_fn(f"  ingest {name}: {n / span / 1e6:.0f} Mpps "
                    f"({n * BYTES_PER_PACKET / span / 1e9:.1f} GB/s over PCIe)")
     return out
 

@@ -323,7 +323,11 @@ typedef struct fw_server_opts {
     uint32_t slots;         /* requests in flight at once, 1..64; 0 = 8 */
     uint32_t mode;          /* fw_mode used for every request (AUTO picks per chain) */
     uint32_t partitions;    /* for rule split / hybrid; 0 = 16 */
-    uint32_t _reserved;
+    uint32_t pipeline;      /* 0: each request copies in and out on its own slot's stream;
+                               1: all copies in go through one shared stream and all copies
+                               out through another, in admission order, chained to the
+                               slots' classification by events (copies never compete with
+                               each other, and still overlap other requests' compute) */
     uint64_t mem_budget;    /* device bytes for in-flight packets and results; 0 = 256 MiB */
 } fw_server_opts;
 

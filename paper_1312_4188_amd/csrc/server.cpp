@@ -3,9 +3,12 @@
 //
 // One worker thread owns the device side.  A request waits in a FIFO queue
 // until a slot (stream) is free and the arena can hold its packets and
-// results; it is then copied in, classified and copied out on its slot's
-// stream, and an event marks its completion.  Requests on different slots
-// overlap on the device; each is classified exactly as it would be alone.
+// results; it is then copied in, classified and copied out, and an event
+// marks its completion.  Requests on different slots overlap on the device;
+// each is classified exactly as it would be alone.  Copies run either on the
+// request's slot stream, or (pipeline mode) on one shared upload stream and
+// one shared download stream in admission order, with events ordering
+// upload -> classification (slot stream) -> download.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -104,6 +107,8 @@ struct fw_server {
     std::unique_ptr<fw::Arena> arena;
     std::vector<hipStream_t> streams;
     std::vector<hipEvent_t> events;
+    hipStream_t up = nullptr, down = nullptr;        // pipeline mode: shared copy streams
+    std::vector<hipEvent_t> ev_up, ev_comp;          // pipeline mode: per-slot stage events
     std::vector<std::shared_ptr<fw::Request>> slot_req;   // worker-owned
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -129,11 +134,15 @@ fw_status launch_request(fw_server* sv, Request& r) {
     auto* pr = reinterpret_cast<uint8_t*>(base + round256(4 * n) * 2 + round256(2 * n) * 2);
     auto* oi = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(pr) + round256(n));
     auto* oa = reinterpret_cast<uint8_t*>(reinterpret_cast<char*>(oi) + round256(4 * n));
-    hipError_t e = hipMemcpyAsync(src, r.pk.src_ip, 4 * n, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(dst, r.pk.dst_ip, 4 * n, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(sp, r.pk.src_port, 2 * n, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(dp, r.pk.dst_port, 2 * n, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(pr, r.pk.proto, n, hipMemcpyHostToDevice, s);
+    const bool pipe = sv->o.pipeline != 0;
+    hipStream_t in = pipe ? sv->up : s, out = pipe ? sv->down : s;
+    hipError_t e = hipMemcpyAsync(src, r.pk.src_ip, 4 * n, hipMemcpyHostToDevice, in);
+    if (e == hipSuccess) e = hipMemcpyAsync(dst, r.pk.dst_ip, 4 * n, hipMemcpyHostToDevice, in);
+    if (e == hipSuccess) e = hipMemcpyAsync(sp, r.pk.src_port, 2 * n, hipMemcpyHostToDevice, in);
+    if (e == hipSuccess) e = hipMemcpyAsync(dp, r.pk.dst_port, 2 * n, hipMemcpyHostToDevice, in);
+    if (e == hipSuccess) e = hipMemcpyAsync(pr, r.pk.proto, n, hipMemcpyHostToDevice, in);
+    if (pipe && e == hipSuccess) e = hipEventRecord(sv->ev_up[r.slot], in);
+    if (pipe && e == hipSuccess) e = hipStreamWaitEvent(s, sv->ev_up[r.slot], 0);
     if (e != hipSuccess) return hip_fail(e, "copying packets in");
     const fw_packets pk{src, dst, sp, dp, pr};
     fw_classify_opts co{};
@@ -142,9 +151,14 @@ fw_status launch_request(fw_server* sv, Request& r) {
     co.stream = s;
     const fw_status st = fw_classify_ex(sv->chains[r.chain], &pk, n, oi, oa, &co);
     if (st != FW_OK) return st;
-    e = hipMemcpyAsync(r.out_idx, oi, 4 * n, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(r.out_act, oa, n, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipEventRecord(sv->events[r.slot], s);
+    if (pipe) {
+        e = hipEventRecord(sv->ev_comp[r.slot], s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(out, sv->ev_comp[r.slot], 0);
+        if (e != hipSuccess) return hip_fail(e, "ordering the copy out");
+    }
+    e = hipMemcpyAsync(r.out_idx, oi, 4 * n, hipMemcpyDeviceToHost, out);
+    if (e == hipSuccess) e = hipMemcpyAsync(r.out_act, oa, n, hipMemcpyDeviceToHost, out);
+    if (e == hipSuccess) e = hipEventRecord(sv->events[r.slot], out);
     if (e != hipSuccess) return hip_fail(e, "copying results out");
     return FW_OK;
 }
@@ -200,7 +214,13 @@ void worker_main(fw_server* sv) {
                 }
             }
             if (complete) {
-                if (r->status != FW_OK) (void)hipStreamSynchronize(sv->streams[k]);
+                if (r->status != FW_OK) {
+                    (void)hipStreamSynchronize(sv->streams[k]);
+                    if (sv->o.pipeline) {
+                        (void)hipStreamSynchronize(sv->up);
+                        (void)hipStreamSynchronize(sv->down);
+                    }
+                }
                 r->times.done = now_s();
                 finished.push_back(r);
                 free_slots.push_back(int(k));
@@ -241,6 +261,7 @@ fw_status fw_server_create(fw_ruleset* const* chains, uint32_t n_chains, const f
     if (o.slots > 64) return fail(FW_E_INVAL, "at most 64 slots");
     if (o.mem_budget == 0) o.mem_budget = uint64_t(256) << 20;
     if (o.mode > FW_MODE_HYBRID) return fail(FW_E_INVAL, "unknown mode %u", o.mode);
+    if (o.pipeline > 1) return fail(FW_E_INVAL, "pipeline must be 0 or 1");
     fw_server* sv = new (std::nothrow) fw_server();
     if (!sv) return fail(FW_E_NOMEM, "host allocation failed");
     sv->chains.assign(chains, chains + n_chains);
@@ -255,15 +276,27 @@ fw_status fw_server_create(fw_ruleset* const* chains, uint32_t n_chains, const f
     sv->streams.assign(o.slots, nullptr);
     sv->events.assign(o.slots, nullptr);
     sv->slot_req.assign(o.slots, nullptr);
+    sv->ev_up.assign(o.pipeline ? o.slots : 0, nullptr);
+    sv->ev_comp.assign(o.pipeline ? o.slots : 0, nullptr);
     for (uint32_t k = 0; k < o.slots && e == hipSuccess; ++k) {
         e = hipStreamCreateWithFlags(&sv->streams[k], hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&sv->events[k], hipEventDisableTiming);
+        if (o.pipeline && e == hipSuccess)
+            e = hipEventCreateWithFlags(&sv->ev_up[k], hipEventDisableTiming);
+        if (o.pipeline && e == hipSuccess)
+            e = hipEventCreateWithFlags(&sv->ev_comp[k], hipEventDisableTiming);
     }
+    if (o.pipeline && e == hipSuccess) e = hipStreamCreateWithFlags(&sv->up, hipStreamNonBlocking);
+    if (o.pipeline && e == hipSuccess)
+        e = hipStreamCreateWithFlags(&sv->down, hipStreamNonBlocking);
     if (e != hipSuccess) {
         for (auto s : sv->streams)
             if (s) (void)hipStreamDestroy(s);
-        for (auto ev : sv->events)
-            if (ev) (void)hipEventDestroy(ev);
+        for (auto s : {sv->up, sv->down})
+            if (s) (void)hipStreamDestroy(s);
+        for (auto& evs : {sv->events, sv->ev_up, sv->ev_comp})
+            for (auto ev : evs)
+                if (ev) (void)hipEventDestroy(ev);
         (void)hipFree(sv->arena_base);
         delete sv;
         return hip_fail(e, "creating server streams");
@@ -372,7 +405,13 @@ fw_status fw_server_destroy(fw_server* sv) {
         const hipError_t e2 = hipStreamDestroy(s);
         if (e == hipSuccess) e = e2;
     }
-    for (auto ev : sv->events) (void)hipEventDestroy(ev);
+    for (auto s : {sv->up, sv->down}) {
+        if (!s) continue;
+        const hipError_t e2 = hipStreamDestroy(s);
+        if (e == hipSuccess) e = e2;
+    }
+    for (auto& evs : {sv->events, sv->ev_up, sv->ev_comp})
+        for (auto ev : evs) (void)hipEventDestroy(ev);
     const hipError_t e3 = hipFree(sv->arena_base);
     if (e == hipSuccess) e = e3;
     delete sv;

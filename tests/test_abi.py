@@ -111,6 +111,12 @@ def test_argument_errors(fw):
     out = ctypes.c_void_p()
     assert lib.fw_server_create(None, 0, None, ctypes.byref(out)) == fw.E_INVAL
     assert out.value is None
+    # options are validated before any device work (the chain handle is never touched)
+    fake = (ctypes.c_void_p * 1)(1)
+    for opts in (fw.ServerOpts(65, 0, 0, 0, 0), fw.ServerOpts(8, 9, 0, 0, 0),
+                 fw.ServerOpts(8, 0, 0, 2, 0)):
+        assert lib.fw_server_create(fake, 1, ctypes.byref(opts), ctypes.byref(out)) == fw.E_INVAL
+        assert out.value is None
     assert lib.fw_server_submit(None, 0, None, 0, None, None, None) == fw.E_INVAL
     assert lib.fw_server_wait(None, 1, None) == fw.E_INVAL
     assert lib.fw_server_destroy(None) == fw.OK
