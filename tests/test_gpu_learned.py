@@ -356,3 +356,39 @@ def test_source_bucket_table(seed, R):
         nxt = np.minimum(i + 1, len(B) - 1)
         i = i + ((i + 1 < len(B)) & (B[nxt] <= keys))
     np.testing.assert_array_equal(i, np.searchsorted(B, keys, side="right") - 1)
+
+
+def test_large_index_global_boundaries():
+    """A destination index too large for LDS (about 45,000 boundaries): the kernels search the
+    boundary array in global memory.  Every packet against the oracle, at 1, 2 and 4 packets
+    per lane."""
+    rules = gen.make_rules(30_000, 12, skew=True)
+    rules.dst_plen[rules.dst_plen == 0] = 24          # every rule specifies a destination
+    pk = gen.make_packets(rules, 200_000, 12)
+    say("learned, 30000 rules with specified destinations (boundaries in global memory)")
+    want = oracle.classify(rules, pk, threads=16)
+    for ppl in (1, 2, 4):
+        got, miss, st = _learned_np(rules, pk, packets_per_lane=ppl)
+        assert st["n_boundaries"] * 4 > 80 * 1024
+        assert_same(got, want, f"large index K={ppl}")
+
+
+def test_source_bucket_fallback_to_binary_search():
+    """Source prefixes crowded into one bucket of the top-bits table (more than 8 boundaries
+    in one /12) make the index fall back to a binary search over source intervals."""
+    rules = gen.make_rules(400, 13)
+    rng = np.random.Generator(np.random.PCG64(13))
+    pick = np.arange(0, 400, 10)                       # 40 destination-wildcard rules
+    rules.dst_plen[pick] = 0
+    rules.src_plen[pick] = 32
+    rules.src_ip[pick] = (0x0A000000 + rng.integers(0, 1 << 20, len(pick))).astype(np.uint32)
+    pk = gen.make_packets(rules, 50_000, 13)
+    fw = fwmod()
+    with fw.Ruleset(rules) as rs:
+        rs.build_learned_index(**FAST)
+        shape = rs.export(11)
+    assert int(shape[3]) == 0, "expected no bucket table"
+    want = oracle.classify(rules, pk)
+    for ppl in (1, 2, 4):
+        got, _, _ = _learned_np(rules, pk, packets_per_lane=ppl)
+        assert_same(got, want, f"binary-search sources K={ppl}")
