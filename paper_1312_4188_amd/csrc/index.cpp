@@ -117,6 +117,37 @@ void init_network(float* p, uint32_t H, SplitMix& rng) {
     p[3 * H] = 0.0f;
 }
 
+// Fold each hidden unit's ReLU into a clamp to [0, 1].  Unit (w1, b1, w2)
+// on inputs v in [0, 1] has pre-activation z = w1 v + b1 <= |w1| + |b1| < 2^k
+// for the k below; scaling w1 and b1 by 2^-k and w2 by 2^k leaves w2 max(z, 0)
+// unchanged, and since scaling by a power of two is exact in floating point
+// (bf16 and fp32 share the exponent range), the fp32 products and sums the
+// lookup forms are bit for bit those of the unscaled unit; the scaled
+// pre-activation is at most 1, so max(z, 0) equals clamp(z, 0, 1), which the
+// hardware applies to the multiply-add for free.  A unit whose scaled values
+// would not round-trip (far outside any trained range) is left as it is; the
+// error bounds are measured with the lookup's own arithmetic either way.
+// `row` is one network in the inference layout (32-slot segments).
+template <class Get, class Put>
+void fold_relu(Get get, Put put) {
+    for (uint32_t i = 0; i < 32; ++i) {
+        const float a = get(i), b = get(32 + i), c = get(64 + i);
+        const float m = std::fabs(a) + std::fabs(b);
+        if (!(m > 0.0f) || !std::isfinite(m)) continue;
+        int k = 0;
+        std::frexp(m, &k);                    // m < 2^k
+        const float a2 = std::ldexp(a, -k), b2 = std::ldexp(b, -k), c2 = std::ldexp(c, k);
+        const bool exact = std::ldexp(a2, k) == a && std::ldexp(b2, k) == b &&
+                           std::ldexp(c2, -k) == c && std::isfinite(c2) &&
+                           (a2 == 0.0f || std::isnormal(a2)) && (b2 == 0.0f || std::isnormal(b2)) &&
+                           (c2 == 0.0f || std::isnormal(c2));
+        if (!exact) continue;
+        put(i, a2);
+        put(32 + i, b2);
+        put(64 + i, c2);
+    }
+}
+
 // Slot of parameter k of the training layout [w1 (H), b1 (H), w2 (H), b2] in
 // the inference layout of 32-slot segments.
 uint32_t infer_slot(uint32_t k, uint32_t H) {
@@ -668,6 +699,8 @@ fw_status build_index(const fw_rule* rules, const RuleRec* recs, uint32_t n_rule
     // quantise to bf16; the lookup uses the widened bf16 values
     std::vector<float> w1q(kGradCols, 0.0f);   // inference layout, see kInferStride
     for (uint32_t k = 0; k < P; ++k) w1q[infer_slot(k, H)] = from_bf16(to_bf16(w1[k]));
+    std::vector<float> w1_trained(w1q);        // exported as trained; the lookup gets the fold
+    fold_relu([&](uint32_t k) { return w1q[k]; }, [&](uint32_t k, float v) { w1q[k] = v; });
     if ((e = upload(ix->d_w1, w1q, s)) != hipSuccess)
         return fail_train(e, "uploading stage-1 weights");
 
@@ -745,13 +778,17 @@ fw_status build_index(const fw_rule* rules, const RuleRec* recs, uint32_t n_rule
     }
     std::vector<uint16_t> w2q(size_t(E) * kInferStride, 0);
     ix->weights.assign(size_t(P) * (E + 1), 0.0f);
-    for (uint32_t k = 0; k < P; ++k) ix->weights[k] = w1q[infer_slot(k, H)];
-    for (uint32_t ex = 0; ex < E; ++ex)
+    for (uint32_t k = 0; k < P; ++k) ix->weights[k] = w1_trained[infer_slot(k, H)];
+    for (uint32_t ex = 0; ex < E; ++ex) {
         for (uint32_t k = 0; k < P; ++k) {
             const uint16_t b = to_bf16(w2[size_t(ex) * P + k]);
             w2q[size_t(ex) * kInferStride + infer_slot(k, H)] = b;
             ix->weights[size_t(ex + 1) * P + k] = from_bf16(b);
         }
+        uint16_t* row = w2q.data() + size_t(ex) * kInferStride;
+        fold_relu([&](uint32_t k) { return from_bf16(row[k]); },
+                  [&](uint32_t k, float v) { row[k] = to_bf16(v); });   // exact: v is bf16
+    }
     if ((e = upload(ix->d_w2, w2q, s)) != hipSuccess ||
         (e = upload(ix->d_meta, meta, s)) != hipSuccess)
         return fail_train(e, "uploading stage-2 weights");

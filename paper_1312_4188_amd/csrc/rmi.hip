@@ -198,13 +198,18 @@ __global__ void k_fill(uint32_t* p, size_t n, uint32_t v) {
 // arithmetic.
 constexpr uint32_t kSeg = 32;
 
+// ReLU of a pre-activation the index build has scaled into (-inf, 1] (see
+// the unit scaling at quantisation): max(z, 0) = clamp(z, 0, 1), which the
+// compiler folds into the producing multiply-add's clamp modifier.
+__device__ __forceinline__ float relu01(float z) { return __builtin_amdgcn_fmed3f(z, 0.0f, 1.0f); }
+
 // Stage 1: u = x / 2^32 -> expert index in [0, E).
 __device__ __forceinline__ uint32_t route(const float* w1, uint32_t E, uint32_t x) {
     const float u = float(x) * 0x1p-32f;
     float y = w1[3 * kSeg];
 #pragma unroll
     for (uint32_t k = 0; k < kSeg; ++k)
-        y = fmaf(w1[2 * kSeg + k], fmaxf(fmaf(w1[k], u, w1[kSeg + k]), 0.0f), y);
+        y = fmaf(w1[2 * kSeg + k], relu01(fmaf(w1[k], u, w1[kSeg + k])), y);
     const float s = y * float(E);
     // NaN and negatives go to expert 0, overflow to the last expert
     return s >= 1.0f ? (s < float(E) ? uint32_t(s) : E - 1u) : 0u;
@@ -224,7 +229,7 @@ __device__ __forceinline__ int32_t position(const uint16_t* w2e, const ExpertMet
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const float z = fmaf(bf16_to_f32(a[i]), v, bf16_to_f32(b[i]));
-            y = fmaf(bf16_to_f32(o[i]), fmaxf(z, 0.0f), y);
+            y = fmaf(bf16_to_f32(o[i]), relu01(z), y);
         }
     }
     const float q = fminf(fmaxf(y * m.pos_span, 0.0f), m.pos_span);  // NaN -> 0
@@ -241,10 +246,10 @@ __device__ __forceinline__ int32_t position(const float* w2e, const ExpertMeta& 
         const float4 a = *reinterpret_cast<const float4*>(w2e + c);
         const float4 b = *reinterpret_cast<const float4*>(w2e + kSeg + c);
         const float4 o = *reinterpret_cast<const float4*>(w2e + 2 * kSeg + c);
-        y = fmaf(o.x, fmaxf(fmaf(a.x, v, b.x), 0.0f), y);
-        y = fmaf(o.y, fmaxf(fmaf(a.y, v, b.y), 0.0f), y);
-        y = fmaf(o.z, fmaxf(fmaf(a.z, v, b.z), 0.0f), y);
-        y = fmaf(o.w, fmaxf(fmaf(a.w, v, b.w), 0.0f), y);
+        y = fmaf(o.x, relu01(fmaf(a.x, v, b.x)), y);
+        y = fmaf(o.y, relu01(fmaf(a.y, v, b.y)), y);
+        y = fmaf(o.z, relu01(fmaf(a.z, v, b.z)), y);
+        y = fmaf(o.w, relu01(fmaf(a.w, v, b.w)), y);
     }
     const float q = fminf(fmaxf(y * m.pos_span, 0.0f), m.pos_span);  // NaN -> 0
     return m.pos_lo + int32_t(rintf(q));
