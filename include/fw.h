@@ -8,7 +8,7 @@
  * destination IPv4 address, source and destination port, protocol -- plus an
  * action, and a field that a rule leaves unspecified matches every value.
  *
- * Three ways to compute the same result are offered:
+ * Four ways to compute the same result are offered:
  *  - packet split: every GPU lane owns whole packets and walks the whole
  *    rule list (the paper's data-parallel firewall, Section IV-A: each node
  *    holds a duplicate of the policy, each packet goes to one node);
@@ -21,8 +21,13 @@
  *    here the merge runs on the GPU);
  *  - learned index: a small network trained on the rule list's destination
  *    interval boundaries locates each packet's destination interval, and
- *    only that interval's exact candidate rules are scanned.  Not in the
- *    paper; its results are identical to the scan by construction.
+ *    only exact candidate lists are scanned: the interval's own list, the
+ *    list of the packet's source interval among destination-wildcard rules,
+ *    and a port/protocol bit-vector table for rules that leave both
+ *    addresses unspecified.  Not in the paper; its results are identical to
+ *    the scan by construction.
+ *  - hybrid: a work-group per 64 packets whose waves split the rule list
+ *    (the paper's Section IV-C).
  *
  * Conventions for every entry point:
  *  - all integers are host byte order: 10.0.0.1 is 0x0A000001;
