@@ -47,6 +47,7 @@ struct LearnedIndex {
     uint32_t pt_shape[5] = {0, 0, 0, 0, 0};
     std::vector<uint16_t> bs_bucket;
     uint16_t* d_bs_bucket = nullptr;
+    uint4* d_image[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // LDS images, see LdsLayout
     PortTable* d_pt = nullptr;
     float* d_w1 = nullptr;
     uint16_t* d_w2 = nullptr;
@@ -275,7 +276,9 @@ void free_index_memory(LearnedIndex* ix) {
                     static_cast<void*>(ix->d_soff), static_cast<void*>(ix->d_S),
                     static_cast<void*>(ix->d_w1), static_cast<void*>(ix->d_w2),
                     static_cast<void*>(ix->d_meta), static_cast<void*>(ix->d_miss),
-                    static_cast<void*>(ix->d_pt), static_cast<void*>(ix->d_bs_bucket)})
+                    static_cast<void*>(ix->d_pt), static_cast<void*>(ix->d_bs_bucket),
+                    static_cast<void*>(ix->d_image[0][0]), static_cast<void*>(ix->d_image[0][1]),
+                    static_cast<void*>(ix->d_image[1][0]), static_cast<void*>(ix->d_image[1][1])})
         if (p) (void)hipFree(p);
 }
 
@@ -297,6 +300,8 @@ LookupArgs args_of(const LearnedIndex* ix, uint32_t use_net) {
     a.pt_steps_s = ix->pt_shape[1];
     a.pt_steps_d = ix->pt_shape[2];
     a.bs_bucket = ix->d_bs_bucket;
+    for (int b = 0; b < 2; ++b)
+        for (int f = 0; f < 2; ++f) a.image[b][f] = ix->d_image[b][f];
     a.bs_bits = ix->pt_shape[3];
     a.bs_steps = ix->pt_shape[4];
     a.Bs = ix->d_Bs;
@@ -464,6 +469,42 @@ void build_bucket_table(const std::vector<uint32_t>& B, std::vector<uint16_t>* t
     }
     *bits = b;
     *steps = longest;
+}
+
+// The lookup kernel's LDS image for one layout variant, byte for byte (see
+// LdsLayout): w1 and w2 are the inference weights (scaled units), meta holds
+// the final error bounds.
+std::vector<uint8_t> lds_image(const LearnedIndex* ix, const std::vector<float>& w1q,
+                               const std::vector<ExpertMeta>& meta,
+                               const std::vector<uint16_t>& w2q, bool b_lds, bool f32) {
+    const uint32_t E = ix->E;
+    const LdsLayout L(E, ix->M, ix->Ms, ix->pt_shape[3], b_lds, f32);
+    std::vector<uint8_t> img(L.bytes, 0);
+    auto put = [&](size_t at, const void* src, size_t bytes) {
+        if (bytes) std::memcpy(img.data() + at, src, bytes);
+    };
+    put(L.w1, w1q.data(), kInferStride * sizeof(float));
+    for (uint32_t e = 0; e < E; ++e) put(L.meta + size_t(e) * kLdsMetaBytes, &meta[e], sizeof(ExpertMeta));
+    for (uint32_t e = 0; e < E; ++e) {
+        if (f32) {
+            for (uint32_t c = 0; c < kLdsStrideF32; ++c) {
+                const float v = from_bf16(w2q[size_t(e) * kInferStride + c]);
+                put(L.w2 + (size_t(e) * kLdsStrideF32 + c) * 4, &v, 4);
+            }
+        } else {
+            put(L.w2 + size_t(e) * kLdsStrideBf16 * 2, w2q.data() + size_t(e) * kInferStride,
+                kInferStride * 2);
+        }
+    }
+    put(L.pt, &ix->pt, sizeof(PortTable));
+    put(L.bk, ix->bs_bucket.data(), ix->bs_bucket.size() * 2);
+    if (b_lds) {
+        put(L.b, ix->B.data(), ix->B.size() * 4);
+        put(L.bs, ix->Bs.data(), ix->Bs.size() * 4);
+        put(L.off, ix->off.data(), ix->off.size() * 4);
+        put(L.soff, ix->soff.data(), ix->soff.size() * 4);
+    }
+    return img;
 }
 
 // Destination intervals with their per-interval lists L_j (rules with a
@@ -805,6 +846,18 @@ fw_status build_index(const fw_rule* rules, const RuleRec* recs, uint32_t n_rule
     for (uint32_t ex = 0; ex < E; ++ex) meta[ex].err = ix->err[ex];
     if ((e = upload(ix->d_meta, meta, s)) != hipSuccess || (e = hipStreamSynchronize(s)) != hipSuccess)
         return fail_train(e, "uploading error bounds");
+    // the kernel's LDS images, one per layout variant
+    for (int b = 0; b < 2 && e == hipSuccess; ++b)
+        for (int f = 0; f < 2 && e == hipSuccess; ++f) {
+            const std::vector<uint8_t> img = lds_image(ix, w1q, meta, w2q, b != 0, f != 0);
+            uint8_t* d = nullptr;
+            e = dalloc(&d, img.size(), &ix->device_bytes);
+            ix->d_image[b][f] = reinterpret_cast<uint4*>(d);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(d, img.data(), img.size(), hipMemcpyHostToDevice, s);
+        }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail_train(e, "uploading the LDS images");
     free_scratch();
 
     if (stats) {

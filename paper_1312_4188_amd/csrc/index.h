@@ -83,6 +83,53 @@ constexpr uint64_t kMaxListBytes = 0x7FFF0000ull;
 constexpr uint32_t kListPastEnd = 0x7FFFFFF0u;
 static_assert(kListPastEnd > kMaxListBytes + 32, "past-the-end offset must be out of range");
 
+// LDS strides of the per-expert data, chosen so that lanes reading different
+// experts spread over all LDS banks: a row of fp32 weights at 104 dwords
+// would put every expert on one of only 4 bank offsets (104 e mod 32 takes
+// 4 values), at 100 dwords on 8 (32 banks) or 16 (64 banks), each 16-byte
+// read covering 4 banks.  bf16 rows (52 dwords) and 48-byte expert records
+// (12 dwords) spread the same way.
+constexpr uint32_t kLdsStrideF32 = 100;     // >= 97 weights used per row, 16-byte multiple
+constexpr uint32_t kLdsStrideBf16 = kInferStride;
+constexpr uint32_t kLdsMetaBytes = 48;
+static_assert(kLdsStrideF32 >= 3 * 32 + 1 && kLdsStrideF32 % 4 == 0, "fp32 row layout");
+static_assert(kLdsMetaBytes >= sizeof(ExpertMeta) && kLdsMetaBytes % 16 == 0, "record layout");
+
+// Byte offsets of the lookup kernel's LDS image, every section 16-byte
+// aligned: stage-1 weights (kInferStride fp32), expert records
+// (kLdsMetaBytes each), expert rows (fp32 at kLdsStrideF32 or bf16 at
+// kLdsStrideBf16), the port/protocol table, the source bucket table, and,
+// with the boundary arrays in LDS (b_lds), B, Bs, off and soff.  The index
+// build writes this image once per variant; the kernel copies it whole.
+struct LdsLayout {
+    size_t w1 = 0, meta, w2, pt, bk, b, bs, off, soff, bytes;
+    __host__ __device__ static size_t up16(size_t x) { return (x + 15) & ~size_t(15); }
+    __host__ __device__ LdsLayout(uint32_t E, uint32_t M, uint32_t Ms, uint32_t bs_bits,
+                                  bool b_lds, bool w2_f32) {
+        size_t o = up16(kInferStride * sizeof(float));
+        meta = o;
+        o = up16(o + size_t(E) * kLdsMetaBytes);
+        w2 = o;
+        o = up16(o + size_t(E) * (w2_f32 ? kLdsStrideF32 * sizeof(float)
+                                         : kLdsStrideBf16 * sizeof(uint16_t)));
+        pt = o;
+        o = up16(o + sizeof(PortTable));
+        bk = o;
+        o = up16(o + (bs_bits ? (size_t(2) << bs_bits) : 0));
+        b = bs = off = soff = o;
+        if (b_lds) {
+            o = up16(o + size_t(M) * 4);
+            bs = o;
+            o = up16(o + size_t(Ms) * 4);
+            off = o;
+            o = up16(o + (size_t(M) + 1) * 4);
+            soff = o;
+            o = up16(o + (size_t(Ms) + 1) * 4);
+        }
+        bytes = o;
+    }
+};
+
 // Everything the lookup kernel reads.
 struct LookupArgs {
     const uint32_t* B;        // M boundaries
@@ -107,6 +154,7 @@ struct LookupArgs {
     const uint32_t* soff;     // Ms + 1 per-source-interval list offsets
     const RuleRec* S;         // per-source-interval candidate records
     uint32_t nS;              // records in S
+    const uint4* image[2][2]; // LDS image per [boundaries in LDS][fp32 expert rows]
     uint32_t use_net;         // 0: full binary search only
     unsigned long long* miss; // optional window-miss counter
 };

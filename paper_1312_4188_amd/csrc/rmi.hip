@@ -283,7 +283,7 @@ __device__ __forceinline__ uint32_t bucket_walk(const uint16_t* bucket, const ui
 // Interval of x: the window [p - err, p + err] of the predicted position first,
 // checked by B[j] <= x < B[j+1]; a miss falls back to the full range.
 // Expert rows and records may sit at a padded stride (W2_STRIDE weights,
-// META_BYTES bytes) in LDS; see lds_layout.
+// META_BYTES bytes) in LDS; see LdsLayout.
 template <uint32_t W2_STRIDE, uint32_t META_BYTES, class W2>
 __device__ __forceinline__ uint32_t locate(const uint32_t* B, uint32_t M, const float* w1,
                                            const W2* w2, const ExpertMeta* meta, uint32_t E,
@@ -403,50 +403,6 @@ __device__ __forceinline__ uint32_t port_table_first(const PortTable& t, uint32_
 constexpr uint32_t kLearnedBlock = 1024;
 constexpr uint32_t kLearnedK = 2;     // default packets per lane in the classify kernel
 
-// LDS strides of the per-expert data, chosen so that lanes reading different
-// experts spread over all LDS banks: a row of fp32 weights at 104 dwords
-// would put every expert on one of only 4 bank offsets (104 e mod 32 takes
-// 4 values), at 100 dwords on 8 (32 banks) or 16 (64 banks), each 16-byte
-// read covering 4 banks.  bf16 rows (52 dwords) and 48-byte expert records
-// (12 dwords) spread the same way.
-constexpr uint32_t kLdsStrideF32 = 100;     // >= 97 weights used per row, 16-byte multiple
-constexpr uint32_t kLdsStrideBf16 = kInferStride;
-constexpr uint32_t kLdsMetaBytes = 48;
-static_assert(kLdsStrideF32 >= 3 * 32 + 1 && kLdsStrideF32 % 4 == 0, "fp32 row layout");
-static_assert(kLdsMetaBytes >= sizeof(ExpertMeta) && kLdsMetaBytes % 16 == 0, "record layout");
-
-__host__ __device__ inline size_t lds_layout(uint32_t E, uint32_t M, uint32_t Ms, uint32_t bs_bits,
-                                             bool b_lds, bool w2_f32, size_t* off_meta,
-                                             size_t* off_w2, size_t* off_pt, size_t* off_bk,
-                                             size_t* off_b, size_t* off_bs) {
-    size_t o = kInferStride * sizeof(float);
-    *off_meta = o;
-    o += size_t(E) * kLdsMetaBytes;
-    o = (o + 15) & ~size_t(15);
-    *off_w2 = o;
-    o += size_t(E) * (w2_f32 ? kLdsStrideF32 * sizeof(float) : kLdsStrideBf16 * sizeof(uint16_t));
-    o = (o + 15) & ~size_t(15);
-    *off_pt = o;
-    o += sizeof(PortTable);
-    *off_bk = o;
-    if (bs_bits) o += (size_t(2) << bs_bits);
-    *off_b = o;
-    if (b_lds) o += size_t(M) * sizeof(uint32_t);
-    *off_bs = o;
-    if (b_lds) o += size_t(Ms) * sizeof(uint32_t);
-    return o;
-}
-
-// With the boundary arrays in LDS, the list offsets (off: M + 1, soff:
-// Ms + 1 entries) follow them there, so a packet's list bounds cost no
-// global load.
-__host__ __device__ inline size_t lds_offsets(uint32_t M, uint32_t Ms, size_t end, size_t* off_off,
-                                              size_t* off_soff) {
-    *off_off = end;
-    *off_soff = end + (size_t(M) + 1) * sizeof(uint32_t);
-    return *off_soff + (size_t(Ms) + 1) * sizeof(uint32_t);
-}
-
 template <class W2>
 struct IndexView {
     const float* w1;
@@ -462,53 +418,46 @@ struct IndexView {
 
 // Stage the index into LDS; stage-2 weights stay bf16 (W2 = uint16_t) or are
 // widened to fp32 (W2 = float) on the way in.
+// Copy `words` 16-byte words from global memory to LDS.  Each thread issues
+// all of its loads of a round (four words) before its stores, and the whole
+// index image is one copy, so staging costs about one memory round trip
+// instead of one per array and per stride of the loop.
+__device__ __forceinline__ void stage_words(uint4* __restrict__ dst, const uint4* __restrict__ src,
+                                            uint32_t words) {
+    constexpr uint32_t U = 4;
+    for (uint32_t base = threadIdx.x; base < words; base += U * kLearnedBlock) {
+        uint4 v[U];
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+            const uint32_t k = base + u * kLearnedBlock;
+            v[u] = src[k < words ? k : words - 1u];
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+            const uint32_t k = base + u * kLearnedBlock;
+            if (k < words) dst[k] = v[u];
+        }
+    }
+}
+
+// Stage the index into LDS: the build wrote, for each layout variant, the
+// exact LDS image (see LdsLayout), so staging is one copy.  Stage-2 weights
+// are bf16 (W2 = uint16_t) or fp32 (W2 = float) in the image.
 template <bool B_LDS, class W2>
 __device__ __forceinline__ IndexView<W2> stage_index(const LookupArgs& a, unsigned char* smem) {
     constexpr bool kF32 = sizeof(W2) == 4;
-    size_t o_meta, o_w2, o_pt, o_bk, o_b, o_bs, o_off, o_soff;
-    const size_t end = lds_layout(a.E, a.M, a.Ms, a.bs_bits, B_LDS, kF32, &o_meta, &o_w2, &o_pt,
-                                  &o_bk, &o_b, &o_bs);
-    lds_offsets(a.M, a.Ms, end, &o_off, &o_soff);
-    uint32_t* s_off = reinterpret_cast<uint32_t*>(smem + o_off);
-    uint32_t* s_soff = reinterpret_cast<uint32_t*>(smem + o_soff);
-    PortTable* s_pt = reinterpret_cast<PortTable*>(smem + o_pt);
-    uint16_t* s_bk = reinterpret_cast<uint16_t*>(smem + o_bk);
-    float* s_w1 = reinterpret_cast<float*>(smem);
-    ExpertMeta* s_meta = reinterpret_cast<ExpertMeta*>(smem + o_meta);
-    W2* s_w2 = reinterpret_cast<W2*>(smem + o_w2);
-    uint32_t* s_b = reinterpret_cast<uint32_t*>(smem + o_b);
-    uint32_t* s_bs = reinterpret_cast<uint32_t*>(smem + o_bs);
-    const uint32_t tid = threadIdx.x;
-    for (uint32_t k = tid; k < kInferStride; k += kLearnedBlock) s_w1[k] = a.w1[k];
-    for (uint32_t k = tid; k < a.E * 8u; k += kLearnedBlock)   // 8 words per record
-        reinterpret_cast<uint32_t*>(smem + o_meta)[(k >> 3) * (kLdsMetaBytes / 4u) + (k & 7u)] =
-            reinterpret_cast<const uint32_t*>(a.meta)[k];
-    if constexpr (kF32) {
-        for (uint32_t k = tid; k < a.E * kLdsStrideF32; k += kLearnedBlock) {
-            const uint32_t e = k / kLdsStrideF32, c = k % kLdsStrideF32;
-            s_w2[k] = bf16_to_f32(a.w2[e * kInferStride + c]);   // c < 100 <= 104
-        }
-    } else {
-        for (uint32_t k = tid; k < a.E * kInferStride / 2u; k += kLearnedBlock)
-            reinterpret_cast<uint32_t*>(s_w2)[k] = reinterpret_cast<const uint32_t*>(a.w2)[k];
-    }
-    if (a.pt_count) {
-        for (uint32_t k = tid; k < sizeof(PortTable) / 16u; k += kLearnedBlock)
-            reinterpret_cast<uint4*>(s_pt)[k] = reinterpret_cast<const uint4*>(a.pt)[k];
-    }
-    if (a.bs_bits) {   // 2^bits uint16 entries, bits >= 8: whole 16-byte words
-        for (uint32_t k = tid; k < (1u << a.bs_bits) / 8u; k += kLearnedBlock)
-            reinterpret_cast<uint4*>(s_bk)[k] = reinterpret_cast<const uint4*>(a.bs_bucket)[k];
-    }
-    if constexpr (B_LDS) {
-        for (uint32_t k = tid; k < a.M; k += kLearnedBlock) s_b[k] = a.B[k];
-        for (uint32_t k = tid; k < a.Ms; k += kLearnedBlock) s_bs[k] = a.Bs[k];
-        for (uint32_t k = tid; k <= a.M; k += kLearnedBlock) s_off[k] = a.off[k];
-        for (uint32_t k = tid; k <= a.Ms; k += kLearnedBlock) s_soff[k] = a.soff[k];
-    }
+    const LdsLayout L(a.E, a.M, a.Ms, a.bs_bits, B_LDS, kF32);
+    stage_words(reinterpret_cast<uint4*>(smem), a.image[B_LDS][kF32], uint32_t(L.bytes / 16u));
     __syncthreads();
-    return IndexView<W2>{s_w1, s_meta, s_w2, B_LDS ? s_b : a.B, B_LDS ? s_bs : a.Bs, s_pt, s_bk,
-                         B_LDS ? s_off : a.off, B_LDS ? s_soff : a.soff};
+    return IndexView<W2>{reinterpret_cast<const float*>(smem + L.w1),
+                         reinterpret_cast<const ExpertMeta*>(smem + L.meta),
+                         reinterpret_cast<const W2*>(smem + L.w2),
+                         B_LDS ? reinterpret_cast<const uint32_t*>(smem + L.b) : a.B,
+                         B_LDS ? reinterpret_cast<const uint32_t*>(smem + L.bs) : a.Bs,
+                         reinterpret_cast<const PortTable*>(smem + L.pt),
+                         reinterpret_cast<const uint16_t*>(smem + L.bk),
+                         B_LDS ? reinterpret_cast<const uint32_t*>(smem + L.off) : a.off,
+                         B_LDS ? reinterpret_cast<const uint32_t*>(smem + L.soff) : a.soff};
 }
 
 // With one or two packets per lane, two work-groups per CU (the LDS footprint
@@ -786,10 +735,7 @@ hipError_t launch_err_bound(const LookupArgs& a, const uint32_t* keys, const int
 }
 
 size_t learned_lds_bytes(const LookupArgs& a, bool b_in_lds, bool w2_f32) {
-    size_t o1, o2, o3, o4, o5, o6, o7, o8;
-    const size_t end =
-        lds_layout(a.E, a.M, a.Ms, a.bs_bits, b_in_lds, w2_f32, &o1, &o2, &o3, &o4, &o5, &o6);
-    return b_in_lds ? lds_offsets(a.M, a.Ms, end, &o7, &o8) : end;
+    return LdsLayout(a.E, a.M, a.Ms, a.bs_bits, b_in_lds, w2_f32).bytes;
 }
 
 hipError_t launch_learned(const LookupArgs& a, PacketsDev pk, size_t n, int32_t* out_idx,
