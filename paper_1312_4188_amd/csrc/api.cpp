@@ -204,6 +204,10 @@ fw_status fw_classify_ex(const fw_ruleset* rs, const fw_packets* pk, size_t n,
     const PacketsDev pd = to_dev(pk);
     uint32_t mode = o.mode;
     if (mode == FW_MODE_AUTO) mode = rs->index ? FW_MODE_LEARNED : FW_MODE_PACKET_SPLIT;
+    // the split forms partition the rules up to and including the first catch-all: later
+    // rules can never be a first match
+    const uint32_t reachable =
+        rs->plan.plan.tail_idx == kNoMatch ? rs->n_rules : rs->plan.plan.tail_idx + 1u;
     hipError_t e = hipSuccess;
     switch (mode) {
         case FW_MODE_PACKET_SPLIT:
@@ -212,16 +216,12 @@ fw_status fw_classify_ex(const fw_ruleset* rs, const fw_packets* pk, size_t n,
                                     o.packets_per_lane ? int(o.packets_per_lane) : 4, stream);
             break;
         case FW_MODE_RULE_SPLIT:
-            // rules past the first catch-all can never be a first match
-            e = launch_rule_split(rs->d_rules,
-                                  rs->plan.plan.tail_idx == kNoMatch ? rs->n_rules
-                                                                     : rs->plan.plan.tail_idx + 1u,
-                                  P, pd, n, out_rule_idx, out_action, rs->default_action, stream);
+            e = launch_rule_split(rs->d_rules, reachable, P, pd, n, out_rule_idx, out_action,
+                                  rs->default_action, stream);
             break;
         case FW_MODE_HYBRID:
-            e = launch_hybrid(rs->d_pairs, rs->d_rules, rs->n_rules, P, pd, n, out_rule_idx,
-                              out_action,
-                              rs->default_action, stream);
+            e = launch_hybrid(rs->d_pairs, rs->d_rules, reachable, P, pd, n, out_rule_idx,
+                              out_action, rs->default_action, stream);
             break;
         case FW_MODE_LEARNED:
             return classify_learned(rs->index, rs->default_action, pd, n, out_rule_idx,
