@@ -276,6 +276,43 @@ def ingest_leg(rs, pk, ref_idx, chunk: int, log_fn):
     return out
 
 
+def scan_configs_leg(seed: int, steps: int, log_fn):
+    """The two plain-scan configurations side by side: 100 rules x 10,000 packets and 1,000
+    rules x 1,048,576 packets, packet split and rule split (16 partitions), each checked bit for
+    bit against the CPU oracle.  Rule-checks/s count the scan's algorithmic work (first-match
+    index + 1, or R, per packet); the VALU fraction prices each check at 2 lane-ops against the
+    39.3 T peak; GB/s counts 18 bytes per packet (13 in, 5 out)."""
+    import torch
+    import oracle
+    from synth import gen
+    from paper_1312_4188_amd import fw
+    out = {}
+    for wl in ("scan_100x10k", "scan_1000x1M"):
+        rules, pk = gen.workload(wl, seed=seed)
+        n, R = len(pk), len(rules)
+        want_idx, want_act = oracle.classify(rules, pk, threads=16)
+        checks = int(np.where(want_idx < 0, R, want_idx.astype(np.int64) + 1).sum())
+        dp = fw.DevicePackets.from_host(pk)
+        oi = torch.empty(n, dtype=torch.int32, device="cuda")
+        oa = torch.empty(n, dtype=torch.uint8, device="cuda")
+        stream = torch.cuda.current_stream()
+        res = {"rules": R, "packets": n, "rule_checks": checks}
+        with fw.Ruleset(rules) as rs:
+            for name, kw in (("packet_split", dict(mode="packet_split")),
+                             ("rule_split_p16", dict(mode="rule_split", partitions=16))):
+                ms, _ = time_steps(lambda: rs.classify(dp, stream=stream, out_idx=oi, out_act=oa,
+                                                       **kw), max(steps, 20), 3, stream)
+                exact = bool(np.array_equal(oi.cpu().numpy(), want_idx) and
+                             np.array_equal(oa.cpu().numpy(), want_act))
+                t = ms * 1e-3
+                res[name] = {"ms": ms, "mpps": n / t / 1e6, "rule_checks_per_s": checks / t,
+                             "valu_frac": OPS_PER_CHECK * checks / t / 1e12 / VALU_INT32_PEAK_TOPS,
+                             "hbm_gbs": n * BYTES_PER_PACKET / t / 1e9, "bit_exact": exact}
+                log_fn(f"  {wl} {name}: {ms:.4f} ms, {n / t / 1e6:.0f} Mpps, exact={exact}")
+        out[wl] = res
+    return out
+
+
 def multichain_leg(seed: int, steps: int, log_fn):
     """64 independent chains (32..8,192 rules, 4,096..1,048,576 packets, log-uniform) in one
     persistent launch, autotuned, against one packet-split launch per chain."""
@@ -350,6 +387,8 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=600,
                     help="requests per offered load in the serving leg (0 = skip it)")
     ap.add_argument("--no-multichain", action="store_true", help="skip the 64-chain leg")
+    ap.add_argument("--no-scan-configs", action="store_true",
+                    help="skip the 100x10k and 1000x1M plain-scan leg")
     ap.add_argument("--no-ingest", action="store_true",
                     help="skip the PCIe-inclusive leg (whole batch from pinned host memory)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -451,14 +490,17 @@ def main():
     head = next(iter(modes))
     ms = results[head]["ms"]
     work = learned_work(rs, pk, ref)
-    achieved_tops = work["lane_ops"] / (ms * 1e-3) / 1e12
+    ms_learned = results.get("learned", {}).get("ms", float("nan"))   # the roofline's kernel
+    achieved_tops = work["lane_ops"] / (ms_learned * 1e-3) / 1e12
     traffic = committed_traffic(args.workload)
     roofline = {"bound": "alu", "achieved": achieved_tops, "peak": VALU_INT32_PEAK_TOPS,
                 "unit": "Tops/s", "frac": achieved_tops / VALU_INT32_PEAK_TOPS,
                 "traffic": traffic.get("k_learned"), "kernel": "k_learned<true,2,false>",
                 "algorithmic_lane_ops": work["lane_ops"], "algorithmic_bytes": work["bytes"],
-                "hbm_gbs": work["bytes"] / (ms * 1e-3) / 1e9,
-                "hbm_frac": work["bytes"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                "hbm_gbs": work["bytes"] / (ms_learned * 1e-3) / 1e9,
+                "hbm_frac": work["bytes"] / (ms_learned * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    if "learned" not in results:      # a run without the learned mode has no learned roofline
+        roofline = None
     scan_roofline = None
     if "packet_split" in results:
         scan_ms = results["packet_split"]["ms"]
@@ -488,6 +530,11 @@ def main():
         log("ingest leg: whole batch from pinned host memory")
         ingest = ingest_leg(rs, pk, ref, 1 << 20, log)
 
+    scan_configs = None
+    if not args.no_scan_configs:
+        log("plain-scan configurations")
+        scan_configs = scan_configs_leg(args.seed, args.steps, log)
+
     multichain = None
     if not args.no_multichain:
         log("multi-chain leg")
@@ -515,7 +562,7 @@ def main():
         "scan_rule_checks": checks, "learned_candidate_checks": work["candidate_checks"],
         "index": index_stats, "index_untrained": untrained_stats, "network_gain": gain,
         "roofline": roofline, "scan_roofline": scan_roofline, "serving": serving,
-        "multichain": multichain, "ingest": ingest,
+        "multichain": multichain, "ingest": ingest, "scan_configs": scan_configs,
         "cpu_baseline": cpu,
     }
     rs.close()

@@ -263,7 +263,13 @@ hipError_t launch_rule_split(const RuleRec* rules, uint32_t n_rules, uint32_t P,
     hipError_t e = fill_no_match(idx, n, stream);
     if (e != hipSuccess) return e;
     if (n_rules > 0) {
-        const uint32_t S = ceil_div(n_rules, P);
+        // Partitions of S rules; when they are shorter than a wave's 64 lanes,
+        // one wave takes ceil(64 / S) consecutive partitions (their minimum is
+        // merged inside the wave, exactly as across waves), so no lane idles
+        // for want of a rule.
+        const uint32_t S0 = ceil_div(n_rules, P);
+        const uint32_t S = S0 >= 64u ? S0 : S0 * ceil_div(64u, S0);
+        P = ceil_div(n_rules, S);
         // P waves of 64 lanes per kRsPackets packets
         e = in_chunks(n, chunk_packets(64.0 * P / kRsPackets), [&](size_t o, size_t c) {
             const uint64_t waves = uint64_t(P) * ((c + kRsPackets - 1) / kRsPackets);

@@ -63,15 +63,45 @@ def test_1000_rules_full_batch(kw):
 
 
 def test_rule_split_launch_chunks():
-    """16,384 partitions need 64 * 16,384 / 8 work-items per packet: one launch holds fewer
-    than 2^32 work-items, so 100,000 packets go in four launches.  Every packet against the
-    oracle."""
-    say("rule split, 16384 partitions, 100000 packets (chunked launches)")
-    rules = gen.make_rules(1000, 31)
-    pk = gen.make_packets(rules, 100_000, 31)
-    want = oracle.classify(rules, pk, threads=16)
-    assert_same(classify_np(rules, pk, mode="rule_split", partitions=16384), want,
-                "rule split P=16384")
+    """Rule split over 10,000 rules with no catch-all, asked for 156 partitions: 65 rules each,
+    so 154 non-empty partitions and 64 * 154 / 8 = 1,232 work-items per packet; one launch
+    holds fewer than 2^32, so 3,500,000 packets go in two launches (the first covers 3,486,144).
+    Packets around the launch edge and a random sample against the oracle; the whole batch
+    against the packet-split scan."""
+    import torch
+    fw = fwmod()
+    rules = gen.make_rules(10_000, 31)
+    catch = ((rules.src_plen == 0) & (rules.dst_plen == 0) & (rules.sport_lo == 0)
+             & (rules.sport_hi == 65535) & (rules.dport_lo == 0) & (rules.dport_hi == 65535)
+             & (rules.proto_any != 0))
+    rules.proto_any[catch] = 0                  # no catch-all: every rule stays reachable
+    n = 3_500_000
+    pk = gen.make_packets(rules, n, 31)
+    edge = 3_486_144                            # the first launch's last packet + 1
+    rng = np.random.Generator(np.random.PCG64(31))
+    sample = np.unique(np.concatenate([np.arange(edge - 1000, edge + 1000),
+                                       rng.integers(0, n, 20_000)]))
+    want = oracle.classify(rules, pk.subset(sample), threads=16)
+    say(f"rule split, 156 partitions, {n} packets (two launches)")
+    with fw.Ruleset(rules) as rs:
+        dp = fw.DevicePackets.from_host(pk)
+        got = rs.classify(dp, mode="rule_split", partitions=156)
+        ref = rs.classify(dp, mode="packet_split")
+        torch.cuda.synchronize()
+        gi, ga = got[0].cpu().numpy(), got[1].cpu().numpy()
+        np.testing.assert_array_equal(gi, ref[0].cpu().numpy())
+        np.testing.assert_array_equal(ga, ref[1].cpu().numpy())
+    assert_same((gi[sample], ga[sample]), want, "rule split P=156 sample")
+
+
+def test_rule_split_short_partitions_share_waves():
+    """Partitions shorter than 64 rules are grouped per wave; results are those of the
+    oracle for every partition count around the grouping thresholds."""
+    rules = gen.make_rules(700, 32)
+    pk = gen.make_packets(rules, 30_000, 32)
+    want = oracle.classify(rules, pk)
+    for P in (1, 10, 11, 12, 13, 63, 64, 65, 127, 700, 5000):
+        assert_same(classify_np(rules, pk, mode="rule_split", partitions=P), want, f"P={P}")
 
 
 def test_hybrid_launch_chunks():
