@@ -113,7 +113,9 @@ typedef struct fw_classify_opts {
     uint32_t lookup;        /* learned mode: 0 = network + error window (default),
                                1 = full binary search with the network skipped */
     uint32_t packets_per_lane; /* packet split and learned mode: 1, 2 or 4; 0 = library
-                                  default (4 for packet split, 2 for learned) */
+                                  default: the most (up to 4 for packet split, 2 for learned)
+                                  that still gives the launch 8,192 waves, so small batches
+                                  use fewer per lane */
     uint64_t *window_misses;   /* learned mode, optional HOST pointer: when given the call
                                   waits for its work and stores how many packets' error
                                   window missed (they fell back to a full search) */

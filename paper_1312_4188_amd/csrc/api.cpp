@@ -95,6 +95,15 @@ void ruleset_view(const fw_ruleset* rs, const RuleRec** rules, const uint2** pai
 }
 
 // A device fault in earlier asynchronous work is sticky; report it before new work.
+// Packets per lane when the caller leaves it to the library: the most (up to
+// `most`) that still gives the launch 8,192 waves (8 per SIMD on 256 CUs), so
+// small batches spread over more waves and each wave's scan is shorter.
+static uint32_t default_packets_per_lane(size_t n, uint32_t most) {
+    uint32_t k = most;
+    while (k > 1 && n < size_t(8192) * 64u * k) k /= 2;
+    return k;
+}
+
 static fw_status check_device_state() {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "earlier device work failed");
@@ -213,7 +222,9 @@ fw_status fw_classify_ex(const fw_ruleset* rs, const fw_packets* pk, size_t n,
         case FW_MODE_PACKET_SPLIT:
             e = launch_packet_split(rs->plan.plan, pd, n, out_rule_idx, out_action,
                                     rs->default_action,
-                                    o.packets_per_lane ? int(o.packets_per_lane) : 4, stream);
+                                    o.packets_per_lane ? int(o.packets_per_lane)
+                                                       : int(default_packets_per_lane(n, 4)),
+                                    stream);
             break;
         case FW_MODE_RULE_SPLIT:
             e = launch_rule_split(rs->d_rules, reachable, P, pd, n, out_rule_idx, out_action,
@@ -225,8 +236,10 @@ fw_status fw_classify_ex(const fw_ruleset* rs, const fw_packets* pk, size_t n,
             break;
         case FW_MODE_LEARNED:
             return classify_learned(rs->index, rs->default_action, pd, n, out_rule_idx,
-                                    out_action, o.lookup, o.packets_per_lane, stream,
-                                    o.window_misses);
+                                    out_action, o.lookup,
+                                    o.packets_per_lane ? o.packets_per_lane
+                                                       : default_packets_per_lane(n, 2),
+                                    stream, o.window_misses);
         default:
             return fail(FW_E_INVAL, "unknown mode %u", mode);
     }

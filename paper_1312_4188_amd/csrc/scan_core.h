@@ -304,7 +304,8 @@ struct WaveScan {
     // improve, taking a rule only when it beats the lane's answer.  The
     // answer is the minimum over groups of each group's first match, which is
     // the first match of the whole list.
-    __device__ __forceinline__ void scan_plan(const ScanPlan& plan) {
+    // The plan's catch-all tail seeds every valid lane whose answer it beats.
+    __device__ __forceinline__ void seed_tail(const ScanPlan& plan) {
 #pragma unroll
         for (int s = 0; s < K; ++s) {
             if (__builtin_amdgcn_inverse_ballot_w64(valid[s]) && plan.tail_idx < best[s]) {
@@ -312,15 +313,24 @@ struct WaveScan {
                 act[s] = plan.tail_act;
             }
         }
+    }
+
+    // Entering a group whose first rule has index first_idx: the live lanes
+    // are the valid ones whose answer could still improve.
+    __device__ __forceinline__ void enter_group(uint32_t first_idx) {
+        live_any = 0;
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            live[s] = valid[s] & ballot(best[s] > first_idx);
+            live_any |= live[s];
+        }
+    }
+
+    __device__ __forceinline__ void scan_plan(const ScanPlan& plan) {
+        seed_tail(plan);
         for (uint32_t g = 0; g < plan.n_groups; ++g) {
             const ScanGroup& G = plan.g[g];
-            const uint32_t first_idx = G.recs[0].idx;
-            live_any = 0;
-#pragma unroll
-            for (int s = 0; s < K; ++s) {
-                live[s] = valid[s] & ballot(best[s] > first_idx);
-                live_any |= live[s];
-            }
+            enter_group(G.recs[0].idx);
             switch (G.kind) {
                 case kFirstDst:
                     scan<FirstField::Dst, true, true>(G.pairs, G.recs, G.count, 0u);
