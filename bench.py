@@ -206,9 +206,10 @@ def serving_leg(seed: int, n_req: int, loads, log_fn):
     ta, out_a = pinned(total, torch.uint8)
     out = {"chains": build, "requests": n_req, "packets": total, "modes": {}}
     mean_batch = total / n_req
-    for mode, slots, pipe in (("auto", 8, False), ("auto", 4, False), ("auto", 4, True),
-                              ("packet_split", 8, False)):
-        with fw.Server(rsets, slots=slots, mode=mode, pipeline=pipe) as sv:
+    for mode, slots, pipe, workers in (("auto", 8, False, 4), ("auto", 8, False, 1),
+                                       ("auto", 4, False, 4), ("auto", 4, True, 4),
+                                       ("packet_split", 8, False, 4)):
+        with fw.Server(rsets, slots=slots, mode=mode, pipeline=pipe, workers=workers) as sv:
             zero = np.zeros(n_req)
             sv.replay(zero[:32], chain[:32], offset[:32], sizes[:32], pool, out_i, out_a)
             t = sv.replay(zero, chain, offset, sizes, pool, out_i, out_a)
@@ -225,11 +226,13 @@ def serving_leg(seed: int, n_req: int, loads, log_fn):
                                      "achieved_mpps": total / span / 1e6,
                                      "p50_us": float(np.percentile(lat, 50)),
                                      "p99_us": float(np.percentile(lat, 99))})
-                log_fn(f"  serving {mode} {slots} slots{' pipeline' if pipe else ''} load {frac:.0%}: "
+                log_fn(f"  serving {mode} {slots} slots {workers} workers"
+                       f"{' pipeline' if pipe else ''} load {frac:.0%}: "
                        f"p50 {res['loads'][-1]['p50_us']:.0f} us "
                        f"p99 {res['loads'][-1]['p99_us']:.0f} us")
-            res["slots"], res["pipeline"] = slots, pipe
-            key = ("learned" if mode == "auto" else mode) + ("" if slots == 8 else f"_{slots}slots")
+            res["slots"], res["pipeline"], res["workers"] = slots, pipe, workers
+            key = (("learned" if mode == "auto" else mode) + ("" if slots == 8 else f"_{slots}slots")
+                   + ("" if workers == 4 else f"_{workers}worker"))
             out["modes"][key + ("_pipeline" if pipe else "")] = res
     for rs in rsets:
         rs.close()
@@ -262,7 +265,7 @@ def ingest_leg(rs, pk, ref_idx, chunk: int, log_fn):
     zero = np.zeros(len(sizes))
     out = {"packets": n, "chunk": chunk, "bytes_per_packet": BYTES_PER_PACKET}
     for slots, pipe in ((1, False), (2, False), (4, False), (8, False), (2, True), (4, True)):
-        with fw.Server([rs], slots=slots, mem_budget=1 << 30, pipeline=pipe) as sv:
+        with fw.Server([rs], slots=slots, mem_budget=1 << 30, pipeline=pipe, workers=1) as sv:
             sv.replay(zero[:2], chain[:2], offset[:2], sizes[:2], pool, out_i, out_a)  # warm
             out_i[:] = -2
             t = sv.replay(zero, chain, offset, sizes, pool, out_i, out_a)

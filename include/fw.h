@@ -336,6 +336,10 @@ typedef struct fw_server_opts {
                                slots' classification by events (copies never compete with
                                each other, and still overlap other requests' compute) */
     uint64_t mem_budget;    /* device bytes for in-flight packets and results; 0 = 256 MiB */
+    uint32_t workers;       /* host threads that issue requests, 1..16, each owning an equal
+                               share of the slots and admitting from the one arrival-order
+                               queue; 0 = 4; never more than `slots` */
+    uint32_t _reserved;
 } fw_server_opts;
 
 /* A batch of packet headers in HOST memory (structure of arrays).  Page-locked

@@ -1,10 +1,12 @@
 // Serving runtime: resident rulesets, continuous batching of arriving packet
 // batches over several HIP streams, admission by a device-memory budget.
 //
-// One worker thread owns the device side.  A request waits in a FIFO queue
-// until a slot (stream) is free and the arena can hold its packets and
-// results; it is then copied in, classified and copied out, and an event
-// marks its completion.  Requests on different slots overlap on the device;
+// Worker threads (four by default) own the device side, each an equal share
+// of the slots.  A request waits in one FIFO queue until a worker has a
+// slot (stream) free and the arena can hold its packets and results; it is
+// then copied in, classified and copied out by that worker, and an event
+// marks its completion.  Several workers issue the HIP calls of different
+// requests in parallel, which is what bounds throughput for small requests.  Requests on different slots overlap on the device;
 // each is classified exactly as it would be alone.  Copies run either on the
 // request's slot stream, or (pipeline mode) on one shared upload stream and
 // one shared download stream in admission order, with events ordering
@@ -115,9 +117,8 @@ struct fw_server {
     std::deque<std::shared_ptr<fw::Request>> queue;
     std::unordered_map<uint64_t, std::shared_ptr<fw::Request>> reqs;
     uint64_t next_ticket = 1;
-    uint32_t inflight = 0;
     bool stop = false;
-    std::thread worker;
+    std::vector<std::thread> workers;
 };
 
 namespace fw {
@@ -163,16 +164,17 @@ fw_status launch_request(fw_server* sv, Request& r) {
     return FW_OK;
 }
 
-void worker_main(fw_server* sv) {
+// Worker owning slots [lo, hi).
+void worker_main(fw_server* sv, uint32_t lo, uint32_t hi) {
     (void)hipSetDevice(sv->device);
-    const uint32_t S = sv->o.slots;
     std::vector<int> free_slots;
-    for (int k = int(S) - 1; k >= 0; --k) free_slots.push_back(k);
+    for (int k = int(hi) - 1; k >= int(lo); --k) free_slots.push_back(k);
+    uint32_t mine = 0;   // requests in flight on this worker's slots
     for (;;) {
         std::vector<std::shared_ptr<Request>> admitted;
         {
             std::unique_lock<std::mutex> lk(sv->mu);
-            if (sv->inflight == 0 && sv->queue.empty()) {
+            if (mine == 0 && sv->queue.empty()) {
                 if (sv->stop) break;
                 sv->cv_work.wait(lk, [&] { return sv->stop || !sv->queue.empty(); });
                 continue;
@@ -186,7 +188,6 @@ void worker_main(fw_server* sv) {
                 r->slot = free_slots.back();
                 free_slots.pop_back();
                 r->times.admit = now_s();
-                ++sv->inflight;
                 admitted.push_back(r);
                 sv->queue.pop_front();
             }
@@ -196,10 +197,11 @@ void worker_main(fw_server* sv) {
             sv->slot_req[r->slot] = r;
             r->status = launch_request(sv, *r);
             if (r->status != FW_OK) r->error = g_last_error;
+            ++mine;
         }
         // completions
         std::vector<std::shared_ptr<Request>> finished;
-        for (uint32_t k = 0; k < S; ++k) {
+        for (uint32_t k = lo; k < hi; ++k) {
             auto& r = sv->slot_req[k];
             if (!r) continue;
             bool complete = r->status != FW_OK;
@@ -229,13 +231,14 @@ void worker_main(fw_server* sv) {
         }
         if (!finished.empty()) {
             progressed = true;
+            mine -= uint32_t(finished.size());
             std::lock_guard<std::mutex> lk(sv->mu);
             for (auto& r : finished) {
                 sv->arena->release(r->off, r->bytes);
                 r->done = true;
-                --sv->inflight;
             }
             sv->cv_done.notify_all();
+            sv->cv_work.notify_all();   // freed memory may admit another worker's request
         }
         if (!progressed) std::this_thread::yield();
     }
@@ -262,6 +265,9 @@ fw_status fw_server_create(fw_ruleset* const* chains, uint32_t n_chains, const f
     if (o.mem_budget == 0) o.mem_budget = uint64_t(256) << 20;
     if (o.mode > FW_MODE_HYBRID) return fail(FW_E_INVAL, "unknown mode %u", o.mode);
     if (o.pipeline > 1) return fail(FW_E_INVAL, "pipeline must be 0 or 1");
+    if (o.workers > 16) return fail(FW_E_INVAL, "at most 16 workers");
+    if (o.workers == 0) o.workers = 4;
+    if (o.workers > o.slots) o.workers = o.slots;
     fw_server* sv = new (std::nothrow) fw_server();
     if (!sv) return fail(FW_E_NOMEM, "host allocation failed");
     sv->chains.assign(chains, chains + n_chains);
@@ -301,7 +307,9 @@ fw_status fw_server_create(fw_ruleset* const* chains, uint32_t n_chains, const f
         delete sv;
         return hip_fail(e, "creating server streams");
     }
-    sv->worker = std::thread(worker_main, sv);
+    for (uint32_t w = 0; w < o.workers; ++w)
+        sv->workers.emplace_back(worker_main, sv, w * o.slots / o.workers,
+                                 (w + 1) * o.slots / o.workers);
     *out = sv;
     return FW_OK;
 }
@@ -336,7 +344,7 @@ fw_status fw_server_submit(fw_server* sv, uint32_t chain, const fw_host_packets*
         return FW_OK;
     }
     sv->queue.push_back(r);
-    sv->cv_work.notify_one();
+    sv->cv_work.notify_all();
     return FW_OK;
 }
 
@@ -399,7 +407,7 @@ fw_status fw_server_destroy(fw_server* sv) {
         sv->stop = true;
         sv->cv_work.notify_all();
     }
-    sv->worker.join();
+    for (auto& t : sv->workers) t.join();
     hipError_t e = hipSuccess;
     for (auto s : sv->streams) {
         const hipError_t e2 = hipStreamDestroy(s);

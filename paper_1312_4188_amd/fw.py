@@ -77,7 +77,8 @@ class MultiOpts(ctypes.Structure):
 class ServerOpts(ctypes.Structure):
     _fields_ = [("slots", ctypes.c_uint32), ("mode", ctypes.c_uint32),
                 ("partitions", ctypes.c_uint32), ("pipeline", ctypes.c_uint32),
-                ("mem_budget", ctypes.c_uint64)]
+                ("mem_budget", ctypes.c_uint64), ("workers", ctypes.c_uint32),
+                ("_reserved", ctypes.c_uint32)]
 
 
 class HostPackets(ctypes.Structure):
@@ -374,12 +375,12 @@ class Server:
     """
 
     def __init__(self, rulesets, slots: int = 8, mode="auto", partitions: int = 0,
-                 mem_budget: int = 0, pipeline: bool = False):
+                 mem_budget: int = 0, pipeline: bool = False, workers: int = 0):
         lib = load_library()
         self._chains = list(rulesets)
         arr = (ctypes.c_void_p * len(self._chains))(*[r.handle.value for r in self._chains])
         opts = ServerOpts(int(slots), MODES[mode] if isinstance(mode, str) else int(mode),
-                          int(partitions), int(bool(pipeline)), int(mem_budget))
+                          int(partitions), int(bool(pipeline)), int(mem_budget), int(workers), 0)
         h = ctypes.c_void_p()
         _check(lib.fw_server_create(arr, len(self._chains), ctypes.byref(opts), ctypes.byref(h)))
         self._h = h

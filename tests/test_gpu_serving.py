@@ -46,15 +46,16 @@ def _run(server, reqs):
     return [(k[2], k[3]) for k in keep], times
 
 
-@pytest.mark.parametrize("pipeline", [False, True])
-def test_mix_equals_alone_equals_oracle(pipeline):
+@pytest.mark.parametrize("pipeline,workers", [(False, 1), (True, 1), (False, 4), (True, 3)])
+def test_mix_equals_alone_equals_oracle(pipeline, workers):
     fw = fwmod()
     chains = [gen.make_rules(n, 70 + i, skew=True) for i, n in enumerate((200, 1000, 3000))]
     rs = [fw.Ruleset(c) for c in chains]
     rs[1].build_learned_index(epochs1=300, epochs2=600)
     reqs = _requests(chains, 48, 5)
-    say(f"serving: mix of 48 requests over 3 chains, 8 slots, pipeline={pipeline}")
-    with fw.Server(rs, slots=8, pipeline=pipeline) as sv:
+    say(f"serving: mix of 48 requests over 3 chains, 8 slots, pipeline={pipeline}, "
+        f"workers={workers}")
+    with fw.Server(rs, slots=8, pipeline=pipeline, workers=workers) as sv:
         mix, times = _run(sv, reqs)
     say("serving: the same requests one at a time")
     with fw.Server(rs, slots=1) as sv:
@@ -83,7 +84,7 @@ def test_memory_budget_admission():
     reqs = _requests(chains, 20, 6, max_batch=8192)
     budget = 8192 * 18 + 8 * 256        # room for about one of the largest requests
     say("serving: tight memory budget")
-    with fw.Server(rs, slots=8, mem_budget=budget, pipeline=True) as sv:
+    with fw.Server(rs, slots=8, mem_budget=budget, pipeline=True, workers=4) as sv:
         res, times = _run(sv, reqs)
         big = gen.make_packets(chains[0], 20_000, 3)
         oi = np.empty(20_000, np.int32)
