@@ -253,6 +253,20 @@ fw_status fw_index_lookup(const fw_ruleset *rs, const uint32_t *keys, size_t n,
 fw_status fw_index_export(const fw_ruleset *rs, uint32_t what, void *host, size_t cap,
                           size_t *size);
 
+/* Closed-loop latency probe: classify n_batches batches one after another,
+ * batch k being packets [start[k], start[k] + count[k]) of the DEVICE arrays
+ * `pk` (each start a multiple of 16, so every slice stays 16-byte aligned),
+ * with `opts` (mode, partitions, stream, ...), waiting for each to complete
+ * before the next is enqueued.  seconds[k] (HOST) receives batch k's time from
+ * the start of its fw_classify_ex call to the end of the stream
+ * synchronisation: the library's own enqueue-to-completion latency, with no
+ * binding in between.  Results go to out_rule_idx / out_action at offset 0
+ * (at least max(count) entries each).  Errors: those of fw_classify_ex, and
+ * FW_E_ALIGN for a start that is not a multiple of 16. */
+fw_status fw_closed_loop(const fw_ruleset *rs, const fw_packets *pk, uint32_t n_batches,
+                         const size_t *start, const size_t *count, int32_t *out_rule_idx,
+                         uint8_t *out_action, const fw_classify_opts *opts, double *seconds);
+
 /* ------------------------------------------------------------------ network kernels
  * Direct access to the training kernels, for checking them against a CPU
  * reference.  One stage of E networks 1 -> H -> 1 (ReLU), parameters laid out

@@ -1,6 +1,8 @@
 // C interface: argument checks, ruleset compilation and dispatch to the kernels.
 #include <hip/hip_runtime.h>
 
+#include <chrono>
+
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -251,6 +253,31 @@ fw_status fw_classify_ex(const fw_ruleset* rs, const fw_packets* pk, size_t n,
 fw_status fw_classify(const fw_ruleset* rs, const fw_packets* pk, size_t n,
                       int32_t* out_rule_idx, uint8_t* out_action) {
     return fw_classify_ex(rs, pk, n, out_rule_idx, out_action, nullptr);
+}
+
+fw_status fw_closed_loop(const fw_ruleset* rs, const fw_packets* pk, uint32_t n_batches,
+                         const size_t* start, const size_t* count, int32_t* out_rule_idx,
+                         uint8_t* out_action, const fw_classify_opts* opts, double* seconds) {
+    if (!rs || !pk) return fail(FW_E_INVAL, "ruleset or packets is NULL");
+    if (n_batches == 0) return FW_OK;
+    if (!start || !count || !seconds) return fail(FW_E_INVAL, "NULL argument");
+    fw_classify_opts o{};
+    if (opts) o = *opts;
+    hipStream_t stream = static_cast<hipStream_t>(o.stream);
+    for (uint32_t k = 0; k < n_batches; ++k) {
+        if (start[k] % 16u) return fail(FW_E_ALIGN, "batch %u starts at %zu, not a multiple of 16",
+                                        k, start[k]);
+        const size_t s0 = start[k];
+        const fw_packets sub{pk->src_ip + s0, pk->dst_ip + s0, pk->src_port + s0,
+                             pk->dst_port + s0, pk->proto + s0};
+        const auto t0 = std::chrono::steady_clock::now();
+        const fw_status st = fw_classify_ex(rs, &sub, count[k], out_rule_idx, out_action, &o);
+        if (st != FW_OK) return st;
+        const hipError_t e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return hip_fail(e, "closed-loop batch");
+        seconds[k] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return FW_OK;
 }
 
 fw_status fw_build_learned_index(fw_ruleset* rs, const fw_index_opts* opts,

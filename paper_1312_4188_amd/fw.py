@@ -121,6 +121,8 @@ SIGNATURES = {
     "fw_server_destroy": (ctypes.c_int, [_VP]),
     "fw_server_replay": (ctypes.c_int, [_VP, _U32, _VP, _VP, _VP, _VP,
                                         ctypes.POINTER(HostPackets), _VP, _VP, _VP]),
+    "fw_closed_loop": (ctypes.c_int, [_VP, ctypes.POINTER(Packets), _U32, _VP, _VP, _VP, _VP,
+                                      ctypes.POINTER(ClassifyOpts), _VP]),
     "fw_last_error": (ctypes.c_char_p, []),
 }
 
@@ -289,6 +291,26 @@ class Ruleset:
         _check(load_library().fw_build_learned_index(self._h, ctypes.byref(opts),
                                                      ctypes.byref(st)))
         return {f: getattr(st, f) for f, _ in IndexStats._fields_}
+
+    def closed_loop(self, pk: DevicePackets, starts, counts, mode="auto", partitions: int = 0,
+                    stream=None, packets_per_lane: int = 0, lookup: int = 0) -> np.ndarray:
+        """fw_closed_loop: batches [starts[k], starts[k] + counts[k]) one after another, each
+        waited for; returns (native enqueue-to-completion seconds per batch, rule_idx, action),
+        the outputs holding the last batch's results at their front."""
+        st = np.ascontiguousarray(starts, dtype=np.uint64)
+        ct = np.ascontiguousarray(counts, dtype=np.uint64)
+        cap = int(ct.max()) if ct.size else 1
+        dev = pk.src_ip.device
+        oi = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        oa = torch.empty(max(cap, 1), dtype=torch.uint8, device=dev)
+        opts = ClassifyOpts(MODES[mode] if isinstance(mode, str) else int(mode), int(partitions),
+                            _stream_ptr(stream), int(lookup), int(packets_per_lane), None)
+        sec = np.zeros(len(st), dtype=np.float64)
+        c = pk.c_struct()
+        _check(load_library().fw_closed_loop(self._h, ctypes.byref(c), len(st), st.ctypes.data,
+                                             ct.ctypes.data, oi.data_ptr(), oa.data_ptr(),
+                                             ctypes.byref(opts), sec.ctypes.data))
+        return sec, oi, oa
 
     def lookup_intervals(self, keys: torch.Tensor, lookup: int = 0, stream=None) -> torch.Tensor:
         out = torch.empty(keys.shape[0], dtype=torch.int32, device=keys.device)

@@ -294,3 +294,27 @@ def test_every_first_test_kind(catch_all_at):
         else:
             got = classify_np(rules, pk, **kw)
         assert_same(got, want, f"kinds {catch_all_at} {kw}")
+
+
+def test_closed_loop_probe():
+    """fw_closed_loop classifies each batch like fw_classify_ex (checked on its last batch,
+    whose results are left in the output arrays), reports a positive time per batch, and
+    rejects a batch start that breaks 16-byte alignment."""
+    import torch
+    fw = fwmod()
+    rules = gen.make_rules(300, 41)
+    pk = gen.make_packets(rules, 20_000, 41)
+    with fw.Ruleset(rules) as rs:
+        dp = fw.DevicePackets.from_host(pk)
+        for mode in ("packet_split", "rule_split", "hybrid"):
+            starts = np.array([0, 16, 4096, 8000], dtype=np.uint64)
+            counts = np.array([64, 1000, 3, 5000], dtype=np.uint64)
+            sec, idx, act = rs.closed_loop(dp, starts, counts, mode=mode, partitions=4)
+            torch.cuda.synchronize()
+            assert sec.shape == (4,) and np.all(sec > 0)
+            want = oracle.classify(rules, pk.subset(slice(8000, 13000)))
+            assert_same((idx[:5000].cpu().numpy(), act[:5000].cpu().numpy()), want,
+                        f"closed loop {mode}")
+        with pytest.raises(fw.FwError) as ei:
+            rs.closed_loop(dp, np.array([8]), np.array([10]))
+        assert ei.value.status == fw.E_ALIGN
