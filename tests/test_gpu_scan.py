@@ -306,7 +306,8 @@ def test_closed_loop_probe():
     pk = gen.make_packets(rules, 20_000, 41)
     with fw.Ruleset(rules) as rs:
         dp = fw.DevicePackets.from_host(pk)
-        for mode in ("packet_split", "rule_split", "hybrid"):
+        rs.build_learned_index(epochs1=200, epochs2=400)
+        for mode in ("packet_split", "rule_split", "hybrid", "learned"):
             starts = np.array([0, 16, 4096, 8000], dtype=np.uint64)
             counts = np.array([64, 1000, 3, 5000], dtype=np.uint64)
             sec, idx, act = rs.closed_loop(dp, starts, counts, mode=mode, partitions=4)
