@@ -1,6 +1,6 @@
 /*
  * Sequential CPU first-match oracle.  TEST INFRASTRUCTURE ONLY: the tests, the
- * smoke check and the benchmark's CPU-baseline leg use it to judge the GPU
+ * smoke check and the benchmark's CPU-baseline leg use it to check the GPU
  * path; the product never calls it.  It shares no code, header, table or
  * helper with the GPU library.
  *
@@ -12,7 +12,7 @@
  * fate ("first match"); a packet that no rule matches is denied ("default
  * deny").  Packets are processed one after the other.
  *
- * Readings where the paper is silent (each is stated again in the design doc):
+ * Readings where the paper is silent:
  *  - addresses are CIDR prefixes (base, length); length 0 is the wildcard
  *    and the bits of the base below the prefix are ignored;
  *  - ports are inclusive ranges [lo, hi]; the wildcard is [0, 65535];

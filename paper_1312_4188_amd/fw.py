@@ -141,8 +141,8 @@ def load_library():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise FileNotFoundError(
-                f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
-                "(or python paper_1312_4188_amd/build_lib.py)")
+                f"{LIB_PATH} is missing: build it with "
+                "python paper_1312_4188_amd/build_lib.py")
         lib = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             f = getattr(lib, name)
