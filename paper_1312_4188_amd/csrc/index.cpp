@@ -47,10 +47,10 @@ struct LearnedIndex {
     uint32_t pt_shape[5] = {0, 0, 0, 0, 0};
     std::vector<uint16_t> bs_bucket;
     uint16_t* d_bs_bucket = nullptr;
-    uint4* d_image[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // LDS images, see LdsLayout
+    uint4* d_image[2] = {nullptr, nullptr};   // LDS images, see LdsLayout
     PortTable* d_pt = nullptr;
     float* d_w1 = nullptr;
-    uint16_t* d_w2 = nullptr;
+    uint32_t* d_w2 = nullptr;
     ExpertMeta* d_meta = nullptr;
     unsigned long long* d_miss = nullptr;
     std::vector<uint32_t> B, off, L_idx, G_idx, err;
@@ -128,7 +128,7 @@ void init_network(float* p, uint32_t H, SplitMix& rng) {
 // hardware applies to the multiply-add for free.  A unit whose scaled values
 // would not round-trip (far outside any trained range) is left as it is; the
 // error bounds are measured with the lookup's own arithmetic either way.
-// `row` is one network in the inference layout (32-slot segments).
+// `row` is one network in 32-slot segments [w1][b1][w2].
 template <class Get, class Put>
 void fold_relu(Get get, Put put) {
     for (uint32_t i = 0; i < 32; ++i) {
@@ -277,8 +277,7 @@ void free_index_memory(LearnedIndex* ix) {
                     static_cast<void*>(ix->d_w1), static_cast<void*>(ix->d_w2),
                     static_cast<void*>(ix->d_meta), static_cast<void*>(ix->d_miss),
                     static_cast<void*>(ix->d_pt), static_cast<void*>(ix->d_bs_bucket),
-                    static_cast<void*>(ix->d_image[0][0]), static_cast<void*>(ix->d_image[0][1]),
-                    static_cast<void*>(ix->d_image[1][0]), static_cast<void*>(ix->d_image[1][1])})
+                    static_cast<void*>(ix->d_image[0]), static_cast<void*>(ix->d_image[1])})
         if (p) (void)hipFree(p);
 }
 
@@ -300,8 +299,7 @@ LookupArgs args_of(const LearnedIndex* ix, uint32_t use_net) {
     a.pt_steps_s = ix->pt_shape[1];
     a.pt_steps_d = ix->pt_shape[2];
     a.bs_bucket = ix->d_bs_bucket;
-    for (int b = 0; b < 2; ++b)
-        for (int f = 0; f < 2; ++f) a.image[b][f] = ix->d_image[b][f];
+    for (int b = 0; b < 2; ++b) a.image[b] = ix->d_image[b];
     a.bs_bits = ix->pt_shape[3];
     a.bs_steps = ix->pt_shape[4];
     a.Bs = ix->d_Bs;
@@ -471,31 +469,21 @@ void build_bucket_table(const std::vector<uint32_t>& B, std::vector<uint16_t>* t
     *steps = longest;
 }
 
-// The lookup kernel's LDS image for one layout variant, byte for byte (see
-// LdsLayout): w1 and w2 are the inference weights (scaled units), meta holds
-// the final error bounds.
+// The lookup kernel's LDS image for one placement (see LdsLayout): w1 and
+// w2 are the inference weights (w2 as stage-2 rows), meta holds the final
+// error bounds.
 std::vector<uint8_t> lds_image(const LearnedIndex* ix, const std::vector<float>& w1q,
                                const std::vector<ExpertMeta>& meta,
-                               const std::vector<uint16_t>& w2q, bool b_lds, bool f32) {
+                               const std::vector<uint32_t>& w2r, bool b_lds) {
     const uint32_t E = ix->E;
-    const LdsLayout L(E, ix->M, ix->Ms, ix->pt_shape[3], b_lds, f32);
+    const LdsLayout L(E, ix->M, ix->Ms, ix->pt_shape[3], b_lds);
     std::vector<uint8_t> img(L.bytes, 0);
     auto put = [&](size_t at, const void* src, size_t bytes) {
         if (bytes) std::memcpy(img.data() + at, src, bytes);
     };
     put(L.w1, w1q.data(), kInferStride * sizeof(float));
     for (uint32_t e = 0; e < E; ++e) put(L.meta + size_t(e) * kLdsMetaBytes, &meta[e], sizeof(ExpertMeta));
-    for (uint32_t e = 0; e < E; ++e) {
-        if (f32) {
-            for (uint32_t c = 0; c < kLdsStrideF32; ++c) {
-                const float v = from_bf16(w2q[size_t(e) * kInferStride + c]);
-                put(L.w2 + (size_t(e) * kLdsStrideF32 + c) * 4, &v, 4);
-            }
-        } else {
-            put(L.w2 + size_t(e) * kLdsStrideBf16 * 2, w2q.data() + size_t(e) * kInferStride,
-                kInferStride * 2);
-        }
-    }
+    put(L.w2, w2r.data(), w2r.size() * 4);
     put(L.pt, &ix->pt, sizeof(PortTable));
     put(L.bk, ix->bs_bucket.data(), ix->bs_bucket.size() * 2);
     if (b_lds) {
@@ -505,6 +493,23 @@ std::vector<uint8_t> lds_image(const LearnedIndex* ix, const std::vector<float>&
         put(L.soff, ix->soff.data(), ix->soff.size() * 4);
     }
     return img;
+}
+
+// Stage-2 rows (see kRowDwords) from bf16 networks in 32-slot segments
+// [w1][b1][w2][b2]: dword k = (w1[k], b1[k]), w1 in the low half; w2[k] and
+// b2 widened to fp32 (a bf16 value is the top half of its fp32 pattern).
+std::vector<uint32_t> stage2_rows(const std::vector<uint16_t>& seg, uint32_t E) {
+    std::vector<uint32_t> out(size_t(E) * kRowDwords, 0);
+    for (uint32_t e = 0; e < E; ++e) {
+        const uint16_t* r = seg.data() + size_t(e) * kInferStride;
+        uint32_t* o = out.data() + size_t(e) * kRowDwords;
+        for (uint32_t k = 0; k < 32; ++k) {
+            o[kRowPairs + k] = uint32_t(r[k]) | (uint32_t(r[32 + k]) << 16);
+            o[kRowOut + k] = uint32_t(r[64 + k]) << 16;
+        }
+        o[kRowBias] = uint32_t(r[96]) << 16;
+    }
+    return out;
 }
 
 // Destination intervals with their per-interval lists L_j (rules with a
@@ -624,8 +629,10 @@ fw_status build_index(const fw_rule* rules, const RuleRec* recs, uint32_t n_rule
                           uint64_t(ix->Ms) * 8 + 4 + ix->nS * sizeof(RuleRec) +
                           uint64_t(ix->nG ? ix->nG : 1) * sizeof(RuleRec) +
                           (uint64_t(ix->nG) + kPairPadding) * 8 + kGradCols * 4 +
-                          uint64_t(E) * kInferStride * 2 + uint64_t(E) * sizeof(ExpertMeta) + 8 +
-                          sizeof(PortTable) + (uint64_t(1) << 12) * 2;
+                          uint64_t(E) * kRowDwords * 4 + uint64_t(E) * sizeof(ExpertMeta) + 8 +
+                          sizeof(PortTable) + (uint64_t(1) << 12) * 2 +
+                          LdsLayout(E, M, ix->Ms, ix->pt_shape[3], false).bytes +
+                          LdsLayout(E, M, ix->Ms, ix->pt_shape[3], true).bytes;
     if (o.mem_budget && keep > o.mem_budget) {
         delete ix;
         return fail(FW_E_NOMEM, "learned index needs %llu bytes, budget is %llu",
@@ -647,7 +654,7 @@ fw_status build_index(const fw_rule* rules, const RuleRec* recs, uint32_t n_rule
         (e = dalloc(&ix->d_S, ix->nS, &bytes)) != hipSuccess ||
 
         (e = dalloc(&ix->d_w1, kGradCols, &bytes)) != hipSuccess ||
-        (e = dalloc(&ix->d_w2, size_t(E) * kInferStride, &bytes)) != hipSuccess ||
+        (e = dalloc(&ix->d_w2, size_t(E) * kRowDwords, &bytes)) != hipSuccess ||
         (e = dalloc(&ix->d_meta, E, &bytes)) != hipSuccess ||
         (e = dalloc(&ix->d_miss, 1, &bytes)) != hipSuccess ||
         (e = dalloc(&ix->d_pt, 1, &bytes)) != hipSuccess ||
@@ -830,7 +837,8 @@ fw_status build_index(const fw_rule* rules, const RuleRec* recs, uint32_t n_rule
         fold_relu([&](uint32_t k) { return from_bf16(row[k]); },
                   [&](uint32_t k, float v) { row[k] = to_bf16(v); });   // exact: v is bf16
     }
-    if ((e = upload(ix->d_w2, w2q, s)) != hipSuccess ||
+    const std::vector<uint32_t> w2r = stage2_rows(w2q, E);
+    if ((e = upload(ix->d_w2, w2r, s)) != hipSuccess ||
         (e = upload(ix->d_meta, meta, s)) != hipSuccess)
         return fail_train(e, "uploading stage-2 weights");
 
@@ -846,16 +854,15 @@ fw_status build_index(const fw_rule* rules, const RuleRec* recs, uint32_t n_rule
     for (uint32_t ex = 0; ex < E; ++ex) meta[ex].err = ix->err[ex];
     if ((e = upload(ix->d_meta, meta, s)) != hipSuccess || (e = hipStreamSynchronize(s)) != hipSuccess)
         return fail_train(e, "uploading error bounds");
-    // the kernel's LDS images, one per layout variant
-    for (int b = 0; b < 2 && e == hipSuccess; ++b)
-        for (int f = 0; f < 2 && e == hipSuccess; ++f) {
-            const std::vector<uint8_t> img = lds_image(ix, w1q, meta, w2q, b != 0, f != 0);
-            uint8_t* d = nullptr;
-            e = dalloc(&d, img.size(), &ix->device_bytes);
-            ix->d_image[b][f] = reinterpret_cast<uint4*>(d);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(d, img.data(), img.size(), hipMemcpyHostToDevice, s);
-        }
+    // the kernel's LDS images, one per placement of the boundary arrays
+    for (int b = 0; b < 2 && e == hipSuccess; ++b) {
+        const std::vector<uint8_t> img = lds_image(ix, w1q, meta, w2r, b != 0);
+        uint8_t* d = nullptr;
+        e = dalloc(&d, img.size(), &ix->device_bytes);
+        ix->d_image[b] = reinterpret_cast<uint4*>(d);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d, img.data(), img.size(), hipMemcpyHostToDevice, s);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail_train(e, "uploading the LDS images");
     free_scratch();

@@ -47,9 +47,18 @@ constexpr uint32_t kMaxHidden = 32;
 constexpr uint32_t kMaxExperts = 256;
 constexpr uint32_t kGradCols = 128;      // padded column count of the gradient product
 constexpr uint32_t kNoExpert = 0xFFFFFFFFu;
-// Inference layout of one network: [w1][b1][w2][b2] in 32-slot segments,
-// padded to 104 entries (a multiple of 8); hidden units past H are zero.
+// Inference layout of one stage-1 network (fp32): [w1][b1][w2][b2] in
+// 32-slot segments, padded to 104 entries (a multiple of 8); hidden units past
+// H are zero.  A stage-2 row (kRowDwords dwords) holds one expert: dword k
+// is the bf16 pair (w1[k], b1[k]) (w1 in the low half), dwords 32 + k hold
+// w2[k] and dword 64 holds b2, both as fp32 (bf16 values widened, exact); the
+// rest is zero.  Rows of all-fp32 weights would not fit the LDS budget of the
+// lookup at 10,000 rules; fp32 w2 saves the lookup one widening per unit.
 constexpr uint32_t kInferStride = 104;
+constexpr uint32_t kRowPairs = 0;     // dword of (w1[0], b1[0]) in a stage-2 row
+constexpr uint32_t kRowOut = 32;      // dword of w2[0]
+constexpr uint32_t kRowBias = 64;     // dword of b2
+constexpr uint32_t kRowDwords = 68;   // stage-2 row stride (a 16-byte multiple)
 
 // Port/protocol table of the first (up to 64) candidates that leave both
 // addresses unspecified: such a rule matches a packet exactly when both of
@@ -84,34 +93,30 @@ constexpr uint32_t kListPastEnd = 0x7FFFFFF0u;
 static_assert(kListPastEnd > kMaxListBytes + 32, "past-the-end offset must be out of range");
 
 // LDS strides of the per-expert data, chosen so that lanes reading different
-// experts spread over all LDS banks: a row of fp32 weights at 104 dwords
-// would put every expert on one of only 4 bank offsets (104 e mod 32 takes
-// 4 values), at 100 dwords on 8 (32 banks) or 16 (64 banks), each 16-byte
-// read covering 4 banks.  bf16 rows (52 dwords) and 48-byte expert records
-// (12 dwords) spread the same way.
-constexpr uint32_t kLdsStrideF32 = 100;     // >= 97 weights used per row, 16-byte multiple
-constexpr uint32_t kLdsStrideBf16 = kInferStride;
+// experts spread over all LDS banks: a row of 68 dwords puts expert e at
+// bank offset 68 e, which takes 8 values modulo 32 banks and 16 modulo 64
+// (each 16-byte read covering 4 banks), and 48-byte expert records (12
+// dwords) spread the same way.
 constexpr uint32_t kLdsMetaBytes = 48;
-static_assert(kLdsStrideF32 >= 3 * 32 + 1 && kLdsStrideF32 % 4 == 0, "fp32 row layout");
 static_assert(kLdsMetaBytes >= sizeof(ExpertMeta) && kLdsMetaBytes % 16 == 0, "record layout");
+static_assert(kRowDwords % 4 == 0 && kRowBias < kRowDwords, "stage-2 row layout");
 
 // Byte offsets of the lookup kernel's LDS image, every section 16-byte
 // aligned: stage-1 weights (kInferStride fp32), expert records
-// (kLdsMetaBytes each), expert rows (fp32 at kLdsStrideF32 or bf16 at
-// kLdsStrideBf16), the port/protocol table, the source bucket table, and,
-// with the boundary arrays in LDS (b_lds), B, Bs, off and soff.  The index
-// build writes this image once per variant; the kernel copies it whole.
+// (kLdsMetaBytes each), expert rows (kRowDwords each), the
+// port/protocol table, the source bucket table, and, with the boundary arrays
+// in LDS (b_lds), B, Bs, off and soff.  The index build writes this image
+// once per variant; the kernel copies it whole.
 struct LdsLayout {
     size_t w1 = 0, meta, w2, pt, bk, b, bs, off, soff, bytes;
     __host__ __device__ static size_t up16(size_t x) { return (x + 15) & ~size_t(15); }
     __host__ __device__ LdsLayout(uint32_t E, uint32_t M, uint32_t Ms, uint32_t bs_bits,
-                                  bool b_lds, bool w2_f32) {
+                                  bool b_lds) {
         size_t o = up16(kInferStride * sizeof(float));
         meta = o;
         o = up16(o + size_t(E) * kLdsMetaBytes);
         w2 = o;
-        o = up16(o + size_t(E) * (w2_f32 ? kLdsStrideF32 * sizeof(float)
-                                         : kLdsStrideBf16 * sizeof(uint16_t)));
+        o = up16(o + size_t(E) * kRowDwords * sizeof(uint32_t));
         pt = o;
         o = up16(o + sizeof(PortTable));
         bk = o;
@@ -135,7 +140,7 @@ struct LookupArgs {
     const uint32_t* B;        // M boundaries
     uint32_t M;
     const float* w1;          // stage 1 in the inference layout (bf16 values, widened)
-    const uint16_t* w2;       // stage 2, E experts x kInferStride bf16
+    const uint32_t* w2;       // stage-2 rows, E x kRowDwords
     const ExpertMeta* meta;   // E
     uint32_t E;
     const uint32_t* off;      // M + 1 per-interval list offsets
@@ -154,7 +159,7 @@ struct LookupArgs {
     const uint32_t* soff;     // Ms + 1 per-source-interval list offsets
     const RuleRec* S;         // per-source-interval candidate records
     uint32_t nS;              // records in S
-    const uint4* image[2][2]; // LDS image per [boundaries in LDS][fp32 expert rows]
+    const uint4* image[2];    // LDS image per placement [boundaries in LDS]
     uint32_t use_net;         // 0: full binary search only
     unsigned long long* miss; // optional window-miss counter
 };
@@ -180,6 +185,6 @@ hipError_t launch_learned(const LookupArgs& a, PacketsDev pk, size_t n, int32_t*
                           uint8_t* out_act, uint32_t dflt, const uint32_t* keys,
                           int32_t* out_interval, uint32_t packets_per_lane, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
-size_t learned_lds_bytes(const LookupArgs& a, bool b_in_lds, bool w2_f32);
+size_t learned_lds_bytes(const LookupArgs& a, bool b_in_lds);
 
 }  // namespace fw

@@ -19,7 +19,6 @@
 #include <map>
 #include <mutex>
 #include <tuple>
-#include <type_traits>
 
 #include "device_util.h"
 #include "fw_internal.h"
@@ -34,8 +33,6 @@ typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr uint32_t kChunk = 512;   // samples per MFMA work-group (32 steps of K = 16)
-
-__device__ __forceinline__ float bf16_to_f32(uint32_t b) { return __uint_as_float(b << 16); }
 
 // Round to nearest even (inputs here are finite).
 __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
@@ -190,11 +187,11 @@ __global__ void k_fill(uint32_t* p, size_t n, uint32_t v) {
 }
 
 // ------------------------------------------------------------------ inference
-// Inference layout of one network: four 32-slot segments [w1][b1][w2][b2],
-// kInferStride entries in all; hidden units past H carry zero weights and
-// add nothing.  Stage 1 is kept as fp32 (the bf16 values widened), stage 2 as
-// bf16.  Every routine below is shared by the error-bound kernel and the
-// lookup kernels, so the recorded error bounds describe exactly the lookup's
+// Stage 1 is kept as fp32 (the bf16 values widened) in four 32-slot segments
+// [w1][b1][w2][b2]; stage 2 as rows of bf16 (w1, b1) pairs and widened w2, b2
+// (see kRowDwords).  Hidden units past H carry zero weights and add nothing.
+// Every routine below is shared by the error-bound kernel and the lookup
+// kernels, so the recorded error bounds describe exactly the lookup's
 // arithmetic.
 constexpr uint32_t kSeg = 32;
 
@@ -215,41 +212,26 @@ __device__ __forceinline__ uint32_t route(const float* w1, uint32_t E, uint32_t 
     return s >= 1.0f ? (s < float(E) ? uint32_t(s) : E - 1u) : 0u;
 }
 
-// Stage 2 (bf16 weights, read 8 at a time): position estimate of x inside
-// expert e's range of positions.
-__device__ __forceinline__ int32_t position(const uint16_t* w2e, const ExpertMeta& m,
+// Stage 2: position estimate of x inside expert e's range of positions.
+// Hidden unit k widens its bf16 pair (w1, b1) with one shift and one mask
+// (exact), forms fp32 max(w1 v + b1, 0) as one clamped multiply-add, and adds
+// its fp32 w2 share with a second: four instructions per unit.
+__device__ __forceinline__ int32_t position(const uint32_t* row, const ExpertMeta& m,
                                             uint32_t x) {
     const float v = x >= m.key_lo ? fminf(float(x - m.key_lo) * m.inv_span, 1.0f) : 0.0f;
-    float y = bf16_to_f32(w2e[3 * kSeg]);
-#pragma unroll
-    for (uint32_t c = 0; c < kSeg; c += 8) {
-        const u16x8 a = *reinterpret_cast<const u16x8*>(w2e + c);
-        const u16x8 b = *reinterpret_cast<const u16x8*>(w2e + kSeg + c);
-        const u16x8 o = *reinterpret_cast<const u16x8*>(w2e + 2 * kSeg + c);
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const float z = fmaf(bf16_to_f32(a[i]), v, bf16_to_f32(b[i]));
-            y = fmaf(bf16_to_f32(o[i]), relu01(z), y);
-        }
-    }
-    const float q = fminf(fmaxf(y * m.pos_span, 0.0f), m.pos_span);  // NaN -> 0
-    return m.pos_lo + int32_t(rintf(q));
-}
-
-// The same stage-2 arithmetic on a row already widened to fp32 (the widening
-// of a bf16 value is exact, so both routines return identical positions).
-__device__ __forceinline__ int32_t position(const float* w2e, const ExpertMeta& m, uint32_t x) {
-    const float v = x >= m.key_lo ? fminf(float(x - m.key_lo) * m.inv_span, 1.0f) : 0.0f;
-    float y = w2e[3 * kSeg];
+    float y = __uint_as_float(row[kRowBias]);
 #pragma unroll
     for (uint32_t c = 0; c < kSeg; c += 4) {
-        const float4 a = *reinterpret_cast<const float4*>(w2e + c);
-        const float4 b = *reinterpret_cast<const float4*>(w2e + kSeg + c);
-        const float4 o = *reinterpret_cast<const float4*>(w2e + 2 * kSeg + c);
-        y = fmaf(o.x, relu01(fmaf(a.x, v, b.x)), y);
-        y = fmaf(o.y, relu01(fmaf(a.y, v, b.y)), y);
-        y = fmaf(o.z, relu01(fmaf(a.z, v, b.z)), y);
-        y = fmaf(o.w, relu01(fmaf(a.w, v, b.w)), y);
+        const uint4 p = *reinterpret_cast<const uint4*>(row + kRowPairs + c);
+        const float4 o = *reinterpret_cast<const float4*>(row + kRowOut + c);
+        const uint32_t pr[4] = {p.x, p.y, p.z, p.w};
+        const float op[4] = {o.x, o.y, o.z, o.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float w1 = __uint_as_float(pr[i] << 16);
+            const float b1 = __uint_as_float(pr[i] & 0xFFFF0000u);
+            y = fmaf(op[i], relu01(fmaf(w1, v, b1)), y);
+        }
     }
     const float q = fminf(fmaxf(y * m.pos_span, 0.0f), m.pos_span);  // NaN -> 0
     return m.pos_lo + int32_t(rintf(q));
@@ -282,17 +264,17 @@ __device__ __forceinline__ uint32_t bucket_walk(const uint16_t* bucket, const ui
 
 // Interval of x: the window [p - err, p + err] of the predicted position first,
 // checked by B[j] <= x < B[j+1]; a miss falls back to the full range.
-// Expert rows and records may sit at a padded stride (W2_STRIDE weights,
-// META_BYTES bytes) in LDS; see LdsLayout.
-template <uint32_t W2_STRIDE, uint32_t META_BYTES, class W2>
+// Expert records may sit at a padded stride (META_BYTES bytes) in LDS; see
+// LdsLayout.
+template <uint32_t META_BYTES>
 __device__ __forceinline__ uint32_t locate(const uint32_t* B, uint32_t M, const float* w1,
-                                           const W2* w2, const ExpertMeta* meta, uint32_t E,
+                                           const uint32_t* w2, const ExpertMeta* meta, uint32_t E,
                                            uint32_t use_net, uint32_t x, bool* miss) {
     if (use_net) {
         const uint32_t e = route(w1, E, x);
         const ExpertMeta m = *reinterpret_cast<const ExpertMeta*>(
             reinterpret_cast<const unsigned char*>(meta) + size_t(e) * META_BYTES);
-        const int32_t p = position(w2 + size_t(e) * W2_STRIDE, m, x);
+        const int32_t p = position(w2 + size_t(e) * kRowDwords, m, x);
         const int64_t lo = int64_t(p) - int64_t(m.err), hi = int64_t(p) + int64_t(m.err);
         const uint32_t l = uint32_t(lo < 0 ? 0 : (lo >= int64_t(M) ? M - 1 : lo));
         const uint32_t h = uint32_t(hi < int64_t(l) ? l : (hi >= int64_t(M) ? M - 1 : hi));
@@ -323,7 +305,7 @@ __global__ void k_err_bound(LookupArgs a, const uint32_t* __restrict__ keys,
     if (i >= n) return;
     const uint32_t x = keys[i];
     const uint32_t e = route(a.w1, a.E, x);
-    const int32_t p = position(a.w2 + size_t(e) * kInferStride, a.meta[e], x);
+    const int32_t p = position(a.w2 + size_t(e) * kRowDwords, a.meta[e], x);
     const int32_t d = p - pos[i];
     atomicMax(err + e, uint32_t(d < 0 ? -d : d));
 }
@@ -403,11 +385,10 @@ __device__ __forceinline__ uint32_t port_table_first(const PortTable& t, uint32_
 constexpr uint32_t kLearnedBlock = 1024;
 constexpr uint32_t kLearnedK = 2;     // default packets per lane in the classify kernel
 
-template <class W2>
 struct IndexView {
     const float* w1;
     const ExpertMeta* meta;
-    const W2* w2;
+    const uint32_t* w2;       // stage-2 rows, kRowDwords each
     const uint32_t* B;
     const uint32_t* Bs;
     const PortTable* pt;
@@ -416,8 +397,6 @@ struct IndexView {
     const uint32_t* soff;
 };
 
-// Stage the index into LDS; stage-2 weights stay bf16 (W2 = uint16_t) or are
-// widened to fp32 (W2 = float) on the way in.
 // Copy `words` 16-byte words from global memory to LDS.  Each thread issues
 // all of its loads of a round (four words) before its stores, and the whole
 // index image is one copy, so staging costs about one memory round trip
@@ -440,39 +419,34 @@ __device__ __forceinline__ void stage_words(uint4* __restrict__ dst, const uint4
     }
 }
 
-// Stage the index into LDS: the build wrote, for each layout variant, the
-// exact LDS image (see LdsLayout), so staging is one copy.  Stage-2 weights
-// are bf16 (W2 = uint16_t) or fp32 (W2 = float) in the image.
-template <bool B_LDS, class W2>
-__device__ __forceinline__ IndexView<W2> stage_index(const LookupArgs& a, unsigned char* smem) {
-    constexpr bool kF32 = sizeof(W2) == 4;
-    const LdsLayout L(a.E, a.M, a.Ms, a.bs_bits, B_LDS, kF32);
-    stage_words(reinterpret_cast<uint4*>(smem), a.image[B_LDS][kF32], uint32_t(L.bytes / 16u));
+// Stage the index into LDS: the build wrote, for each placement, the exact
+// LDS image (see LdsLayout), so staging is one copy.
+template <bool B_LDS>
+__device__ __forceinline__ IndexView stage_index(const LookupArgs& a, unsigned char* smem) {
+    const LdsLayout L(a.E, a.M, a.Ms, a.bs_bits, B_LDS);
+    stage_words(reinterpret_cast<uint4*>(smem), a.image[B_LDS], uint32_t(L.bytes / 16u));
     __syncthreads();
-    return IndexView<W2>{reinterpret_cast<const float*>(smem + L.w1),
-                         reinterpret_cast<const ExpertMeta*>(smem + L.meta),
-                         reinterpret_cast<const W2*>(smem + L.w2),
-                         B_LDS ? reinterpret_cast<const uint32_t*>(smem + L.b) : a.B,
-                         B_LDS ? reinterpret_cast<const uint32_t*>(smem + L.bs) : a.Bs,
-                         reinterpret_cast<const PortTable*>(smem + L.pt),
-                         reinterpret_cast<const uint16_t*>(smem + L.bk),
-                         B_LDS ? reinterpret_cast<const uint32_t*>(smem + L.off) : a.off,
-                         B_LDS ? reinterpret_cast<const uint32_t*>(smem + L.soff) : a.soff};
+    return IndexView{reinterpret_cast<const float*>(smem + L.w1),
+                     reinterpret_cast<const ExpertMeta*>(smem + L.meta),
+                     reinterpret_cast<const uint32_t*>(smem + L.w2),
+                     B_LDS ? reinterpret_cast<const uint32_t*>(smem + L.b) : a.B,
+                     B_LDS ? reinterpret_cast<const uint32_t*>(smem + L.bs) : a.Bs,
+                     reinterpret_cast<const PortTable*>(smem + L.pt),
+                     reinterpret_cast<const uint16_t*>(smem + L.bk),
+                     B_LDS ? reinterpret_cast<const uint32_t*>(smem + L.off) : a.off,
+                     B_LDS ? reinterpret_cast<const uint32_t*>(smem + L.soff) : a.soff};
 }
 
 // With one or two packets per lane, two work-groups per CU (the LDS footprint
 // allows two): eight waves per SIMD, so at most 64 VGPRs.  Four packets per
-// lane need more registers and run one work-group per CU.  W2F32: the expert
-// weights are widened to fp32 while staged (exact), so the loop reads them
-// without converting; chosen whenever the LDS budget has room.
-template <bool B_LDS, int K, bool W2F32>
+// lane need more registers and run one work-group per CU.
+template <bool B_LDS, int K>
 __global__ __launch_bounds__(kLearnedBlock, K >= 4 ? 4 : 8) void k_learned(LookupArgs a, PacketsDev pk, size_t n,
                                                            int32_t* __restrict__ out_idx,
                                                            uint8_t* __restrict__ out_act,
                                                            uint32_t dflt) {
     extern __shared__ __align__(16) unsigned char smem[];
-    using W2 = typename std::conditional<W2F32, float, uint16_t>::type;
-    const IndexView<W2> v = stage_index<B_LDS, W2>(a, smem);
+    const IndexView v = stage_index<B_LDS>(a, smem);
     const uint32_t lane = threadIdx.x & 63u;
     constexpr uint32_t kWaves = kLearnedBlock / 64;   // compile-time: keeps the loop scalar
     const size_t waves = size_t(gridDim.x) * kWaves;
@@ -487,7 +461,7 @@ __global__ __launch_bounds__(kLearnedBlock, K >= 4 ? 4 : 8) void k_learned(Looku
         for (int s = 0; s < K; ++s) {
             const bool valid = w.p0 + s < n;
             bool miss = false;
-            jj[s] = locate<W2F32 ? kLdsStrideF32 : kLdsStrideBf16, kLdsMetaBytes>(
+            jj[s] = locate<kLdsMetaBytes>(
                 v.B, a.M, v.w1, v.w2, v.meta, a.E, a.use_net, w.dst[s], &miss);
             if (a.miss) {
                 const uint64_t mm = ballot(valid && miss);
@@ -588,14 +562,13 @@ __global__ __launch_bounds__(kLearnedBlock, K >= 4 ? 4 : 8) void k_learned(Looku
 }
 
 // Interval lookup only, one key per lane.
-template <bool B_LDS, bool W2F32>
+template <bool B_LDS>
 __global__ __launch_bounds__(kLearnedBlock) void k_lookup(LookupArgs a,
                                                           const uint32_t* __restrict__ keys,
                                                           size_t n,
                                                           int32_t* __restrict__ out_interval) {
     extern __shared__ __align__(16) unsigned char smem[];
-    using W2 = typename std::conditional<W2F32, float, uint16_t>::type;
-    const IndexView<W2> v = stage_index<B_LDS, W2>(a, smem);
+    const IndexView v = stage_index<B_LDS>(a, smem);
     constexpr uint32_t kWaves = kLearnedBlock / 64;   // compile-time: keeps the loop scalar
     const size_t waves = size_t(gridDim.x) * kWaves;
     const size_t wave0 = size_t(blockIdx.x) * kWaves + wave_in_group();
@@ -603,7 +576,7 @@ __global__ __launch_bounds__(kLearnedBlock) void k_lookup(LookupArgs a,
         const size_t i = base + (threadIdx.x & 63u);
         const bool valid = i < n;
         bool miss = false;
-        const uint32_t j = locate<W2F32 ? kLdsStrideF32 : kLdsStrideBf16, kLdsMetaBytes>(
+        const uint32_t j = locate<kLdsMetaBytes>(
             v.B, a.M, v.w1, v.w2, v.meta, a.E, a.use_net, valid ? keys[i] : 0u, &miss);
         if (valid) out_interval[i] = int32_t(j);
     }
@@ -734,8 +707,8 @@ hipError_t launch_err_bound(const LookupArgs& a, const uint32_t* keys, const int
     return hipGetLastError();
 }
 
-size_t learned_lds_bytes(const LookupArgs& a, bool b_in_lds, bool w2_f32) {
-    return LdsLayout(a.E, a.M, a.Ms, a.bs_bits, b_in_lds, w2_f32).bytes;
+size_t learned_lds_bytes(const LookupArgs& a, bool b_in_lds) {
+    return LdsLayout(a.E, a.M, a.Ms, a.bs_bits, b_in_lds).bytes;
 }
 
 hipError_t launch_learned(const LookupArgs& a, PacketsDev pk, size_t n, int32_t* out_idx,
@@ -755,34 +728,26 @@ hipError_t launch_learned(const LookupArgs& a, PacketsDev pk, size_t n, int32_t*
     }
     // One or two packets per lane keep two work-groups of 16 waves per CU, so
     // the staged index must stay within 80 KiB; four per lane run one
-    // work-group per CU and may use up to 150 KiB.  In that budget the
-    // boundary arrays and list offsets come first (the binary searches probe
-    // them, every packet reads its list bounds), fp32 expert weights second.
+    // work-group per CU and may use up to 150 KiB.  The boundary arrays and
+    // list offsets go to LDS when they fit (the binary searches probe them,
+    // every packet reads its list bounds); the rest of the image always does
+    // (past about 200 experts it outgrows 80 KiB, and one work-group per CU
+    // runs).
     const uint32_t K = packets_per_lane ? packets_per_lane : kLearnedK;
     const size_t cap = std::min<size_t>(K >= 4 ? 150u * 1024u : 80u * 1024u,
                                         size_t(g_cache.max_lds));
-    bool b_lds = false, f32 = false;
-    size_t lds = 0;
-    for (int option = 0; option < 4; ++option) {
-        b_lds = option < 2;
-        f32 = option % 2 == 0;
-        lds = learned_lds_bytes(a, b_lds, f32);
-        if (lds <= cap) break;
-    }
+    const bool b_lds = learned_lds_bytes(a, true) <= cap;
+    const size_t lds = learned_lds_bytes(a, b_lds);
     if (keys) {
         const size_t tiles = (n + 63) / 64;
-#define FW_LOOKUP(BL, F) launch_persistent(k_lookup<BL, F>, lds, tiles, s, a, keys, n, out_interval)
-        if (b_lds) return f32 ? FW_LOOKUP(true, true) : FW_LOOKUP(true, false);
-        return f32 ? FW_LOOKUP(false, true) : FW_LOOKUP(false, false);
-#undef FW_LOOKUP
+        return b_lds ? launch_persistent(k_lookup<true>, lds, tiles, s, a, keys, n, out_interval)
+                     : launch_persistent(k_lookup<false>, lds, tiles, s, a, keys, n, out_interval);
     }
     const size_t tiles = (n + 64 * K - 1) / (64 * K);
-#define FW_LEARNED(BL, KK, F) \
-    launch_persistent(k_learned<BL, KK, F>, lds, tiles, s, a, pk, n, out_idx, out_act, dflt)
-#define FW_LEARNED_K(BL, F)                          \
-    (K == 1 ? FW_LEARNED(BL, 1, F) : K == 2 ? FW_LEARNED(BL, 2, F) : FW_LEARNED(BL, 4, F))
-    if (b_lds) return f32 ? FW_LEARNED_K(true, true) : FW_LEARNED_K(true, false);
-    return f32 ? FW_LEARNED_K(false, true) : FW_LEARNED_K(false, false);
+#define FW_LEARNED(BL, KK) \
+    launch_persistent(k_learned<BL, KK>, lds, tiles, s, a, pk, n, out_idx, out_act, dflt)
+#define FW_LEARNED_K(BL) (K == 1 ? FW_LEARNED(BL, 1) : K == 2 ? FW_LEARNED(BL, 2) : FW_LEARNED(BL, 4))
+    return b_lds ? FW_LEARNED_K(true) : FW_LEARNED_K(false);
 #undef FW_LEARNED_K
 #undef FW_LEARNED
 }
