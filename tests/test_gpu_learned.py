@@ -392,3 +392,47 @@ def test_source_bucket_fallback_to_binary_search():
     for ppl in (1, 2, 4):
         got, _, _ = _learned_np(rules, pk, packets_per_lane=ppl)
         assert_same(got, want, f"binary-search sources K={ppl}")
+
+
+def test_long_candidate_lists():
+    """Wide destination prefixes with specified sources: few intervals (the boundary arrays
+    fit in LDS easily), but every interval's list is long, more than 65,535 records in all.
+    Every packet against the oracle at 1, 2 and 4 packets per lane."""
+    rng = np.random.Generator(np.random.PCG64(14))
+    rules = gen.make_rules(4000, 14)
+    rules.dst_plen[:] = rng.integers(1, 9, 4000).astype(np.uint8)
+    rules.src_plen[:] = rng.integers(16, 25, 4000).astype(np.uint8)
+    pk = gen.make_packets(rules, 100_000, 14)
+    fw = fwmod()
+    with fw.Ruleset(rules) as rs:
+        st = rs.build_learned_index(**FAST)
+        n_list = int(rs.export(1)[-1])
+    say(f"long lists: {n_list} records, {st['n_boundaries']} boundaries")
+    assert n_list > 0xFFFF and st["n_boundaries"] * 4 < 16 * 1024
+    want = oracle.classify(rules, pk, threads=16)
+    for ppl in (1, 2, 4):
+        got, _, _ = _learned_np(rules, pk, packets_per_lane=ppl)
+        assert_same(got, want, f"long lists K={ppl}")
+
+
+def test_positions_identical_across_packets_per_lane():
+    """190 experts on a small ruleset, one index classified with 1, 2 and 4 packets per lane
+    (different kernels and LDS budgets).  With error bounds forced to zero every window miss
+    depends on the exact predicted position, so equal miss counts show that all of them
+    predict alike; every answer against the oracle."""
+    import torch
+    rules = gen.make_rules(200, 15, skew=True)
+    pk = gen.make_packets(rules, 60_000, 15)
+    want = oracle.classify(rules, pk)
+    fw = fwmod()
+    misses = {}
+    with fw.Ruleset(rules) as rs:
+        rs.build_learned_index(**dict(FAST, experts=190, zero_error_bounds=True))
+        dp = fw.DevicePackets.from_host(pk)
+        for ppl in (1, 2, 4):
+            say(f"row formats K={ppl}")
+            idx, act, misses[ppl] = rs.classify(dp, mode="learned", count_misses=True,
+                                                packets_per_lane=ppl)
+            torch.cuda.synchronize()
+            assert_same((idx.cpu().numpy(), act.cpu().numpy()), want, f"190 experts K={ppl}")
+    assert misses[1] == misses[2] == misses[4] > 0
