@@ -200,16 +200,37 @@ constexpr uint32_t kSeg = 32;
 // compiler folds into the producing multiply-add's clamp modifier.
 __device__ __forceinline__ float relu01(float z) { return __builtin_amdgcn_fmed3f(z, 0.0f, 1.0f); }
 
-// Stage 1: u = x / 2^32 -> expert index in [0, E).
-__device__ __forceinline__ uint32_t route(const float* w1, uint32_t E, uint32_t x) {
-    const float u = float(x) * 0x1p-32f;
-    float y = w1[3 * kSeg];
+// Stage 1: u = x / 2^32 -> expert index in [0, E), for K keys at once: the
+// weights are the same for every key, so each is read once and used K times;
+// every key sees the same sequence of operations as on its own.
+template <int K>
+__device__ __forceinline__ void route(const float* w1, uint32_t E, const uint32_t (&x)[K],
+                                      uint32_t (&e)[K]) {
+    float u[K], y[K];
 #pragma unroll
-    for (uint32_t k = 0; k < kSeg; ++k)
-        y = fmaf(w1[2 * kSeg + k], relu01(fmaf(w1[k], u, w1[kSeg + k])), y);
-    const float s = y * float(E);
-    // NaN and negatives go to expert 0, overflow to the last expert
-    return s >= 1.0f ? (s < float(E) ? uint32_t(s) : E - 1u) : 0u;
+    for (int s = 0; s < K; ++s) {
+        u[s] = float(x[s]) * 0x1p-32f;
+        y[s] = w1[3 * kSeg];
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < kSeg; ++k) {
+        const float a = w1[k], b = w1[kSeg + k], o = w1[2 * kSeg + k];
+#pragma unroll
+        for (int s = 0; s < K; ++s) y[s] = fmaf(o, relu01(fmaf(a, u[s], b)), y[s]);
+    }
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+        const float t = y[s] * float(E);
+        // NaN and negatives go to expert 0, overflow to the last expert
+        e[s] = t >= 1.0f ? (t < float(E) ? uint32_t(t) : E - 1u) : 0u;
+    }
+}
+
+__device__ __forceinline__ uint32_t route(const float* w1, uint32_t E, uint32_t x) {
+    const uint32_t k[1] = {x};
+    uint32_t e[1];
+    route<1>(w1, E, k, e);
+    return e[0];
 }
 
 // Stage 2: position estimate of x inside expert e's range of positions.
@@ -262,16 +283,15 @@ __device__ __forceinline__ uint32_t bucket_walk(const uint16_t* bucket, const ui
     return i;
 }
 
-// Interval of x: the window [p - err, p + err] of the predicted position first,
-// checked by B[j] <= x < B[j+1]; a miss falls back to the full range.
-// Expert records may sit at a padded stride (META_BYTES bytes) in LDS; see
-// LdsLayout.
+// Interval of x, routed to expert e by stage 1: the window [p - err, p + err]
+// of the predicted position first, checked by B[j] <= x < B[j+1]; a miss
+// falls back to the full range.  Expert records may sit at a padded stride
+// (META_BYTES bytes) in LDS; see LdsLayout.
 template <uint32_t META_BYTES>
-__device__ __forceinline__ uint32_t locate(const uint32_t* B, uint32_t M, const float* w1,
-                                           const uint32_t* w2, const ExpertMeta* meta, uint32_t E,
-                                           uint32_t use_net, uint32_t x, bool* miss) {
+__device__ __forceinline__ uint32_t locate(const uint32_t* B, uint32_t M, const uint32_t* w2,
+                                           const ExpertMeta* meta, uint32_t use_net, uint32_t e,
+                                           uint32_t x, bool* miss) {
     if (use_net) {
-        const uint32_t e = route(w1, E, x);
         const ExpertMeta m = *reinterpret_cast<const ExpertMeta*>(
             reinterpret_cast<const unsigned char*>(meta) + size_t(e) * META_BYTES);
         const int32_t p = position(w2 + size_t(e) * kRowDwords, m, x);
@@ -455,14 +475,17 @@ __global__ __launch_bounds__(kLearnedBlock, K >= 4 ? 4 : 8) void k_learned(Looku
         WaveScan<K> w;
         w.init(pk, base, n, dflt);
         uint32_t lbest[K], lact[K], jj[K], si[K];
-        // every packet's destination and source intervals first: the K
-        // lookups are independent, so their LDS round trips overlap
+        // every packet's destination and source intervals first: stage 1
+        // routes the K keys in one pass over its weights, and the K lookups
+        // are independent, so their LDS round trips overlap
+        uint32_t ex[K];
+        if (a.use_net) route<K>(v.w1, a.E, w.dst, ex);
 #pragma unroll
         for (int s = 0; s < K; ++s) {
             const bool valid = w.p0 + s < n;
             bool miss = false;
-            jj[s] = locate<kLdsMetaBytes>(
-                v.B, a.M, v.w1, v.w2, v.meta, a.E, a.use_net, w.dst[s], &miss);
+            jj[s] = locate<kLdsMetaBytes>(v.B, a.M, v.w2, v.meta, a.use_net,
+                                          a.use_net ? ex[s] : 0u, w.dst[s], &miss);
             if (a.miss) {
                 const uint64_t mm = ballot(valid && miss);
                 if (lane == 0 && mm) atomicAdd(a.miss, (unsigned long long)__popcll(mm));
@@ -576,8 +599,9 @@ __global__ __launch_bounds__(kLearnedBlock) void k_lookup(LookupArgs a,
         const size_t i = base + (threadIdx.x & 63u);
         const bool valid = i < n;
         bool miss = false;
-        const uint32_t j = locate<kLdsMetaBytes>(
-            v.B, a.M, v.w1, v.w2, v.meta, a.E, a.use_net, valid ? keys[i] : 0u, &miss);
+        const uint32_t x = valid ? keys[i] : 0u;
+        const uint32_t j = locate<kLdsMetaBytes>(v.B, a.M, v.w2, v.meta, a.use_net,
+                                                 a.use_net ? route(v.w1, a.E, x) : 0u, x, &miss);
         if (valid) out_interval[i] = int32_t(j);
     }
 }
