@@ -513,8 +513,10 @@ __global__ __launch_bounds__(kLearnedBlock, K >= 4 ? 4 : 8) void k_learned(Looku
         // whose source test it passes).  Each is ascending and ends at its
         // first match or at the first entry that can no longer beat the best
         // so far, so the answer is the minimum over lists.  All K packets'
-        // lists advance together, one entry each per round, so the round's
-        // 2K record loads are in flight at once.
+        // lists advance together, one entry each per round, so a round's
+        // record loads are in flight at once; a wave runs as many rounds as
+        // its longest list needs, so the short source lists drop out of the
+        // rounds once every lane is done with them.
         const __amdgpu_buffer_rsrc_t rl = list_rsrc(a.L, a.nL);
         const __amdgpu_buffer_rsrc_t rs_ = list_rsrc(a.S, a.nS);
         uint32_t lk[K], le[K], sk[K], se[K];
@@ -528,14 +530,42 @@ __global__ __launch_bounds__(kLearnedBlock, K >= 4 ? 4 : 8) void k_learned(Looku
             sk[s] = s0;
             se[s] = valid ? s1 : s0;
         }
+        // One entry of a packet's destination-interval list: the record's
+        // source, port and protocol tests (its destination test is implied by
+        // the list).  Straight-line selects, no branches, so no load is sunk
+        // into a conditional block behind another's wait.
+        auto step_dst = [&](int s, const RuleRec& q) {
+            const bool on = lk[s] < le[s];
+            const bool beats = q.idx < lbest[s];
+            const bool m = (unsigned(on) & unsigned(beats) &
+                            unsigned(in_range(w.src[s], q.src_lo, q.src_w)) &
+                            unsigned(ports_in(w.pp[s], q.port_lo, q.port_w)) &
+                            unsigned(in_range(w.pr[s], proto_lo(q.proto), proto_w(q.proto)))) != 0u;
+            lbest[s] = m ? q.idx : lbest[s];
+            lact[s] = m ? rule_action(q.proto) : lact[s];
+            lk[s] = on ? ((m | !beats) ? le[s] : lk[s] + 1u) : lk[s];
+        };
+        // One entry of its source-interval list (source test implied as well).
+        auto step_src = [&](int s, const RuleRec& q) {
+            const bool on = sk[s] < se[s];
+            const bool beats = q.idx < lbest[s];
+            const bool m = (unsigned(on) & unsigned(beats) &
+                            unsigned(ports_in(w.pp[s], q.port_lo, q.port_w)) &
+                            unsigned(in_range(w.pr[s], proto_lo(q.proto), proto_w(q.proto)))) != 0u;
+            lbest[s] = m ? q.idx : lbest[s];
+            lact[s] = m ? rule_action(q.proto) : lact[s];
+            sk[s] = on ? ((m | !beats) ? se[s] : sk[s] + 1u) : sk[s];
+        };
+        // Buffer loads: a lane whose list is exhausted passes an offset past
+        // the end of the array, so its load returns zeros without a memory
+        // access, and no branch separates the loads.
+        // Phase 1, while any lane has a source-interval entry left (those
+        // lists are short): both lists of every packet advance each round.
         for (;;) {
             bool more = false;
 #pragma unroll
-            for (int s = 0; s < K; ++s) more = more || lk[s] < le[s] || sk[s] < se[s];
+            for (int s = 0; s < K; ++s) more = more || sk[s] < se[s];
             if (ballot(more) == 0) break;
-            // Buffer loads: a lane whose list is exhausted passes an offset
-            // past the end of the array, so its load returns zeros without a
-            // memory access, and no branch separates the loads.
             RuleRec ql[K], qs[K];
 #pragma unroll
             for (int s = 0; s < K; ++s) {
@@ -543,36 +573,25 @@ __global__ __launch_bounds__(kLearnedBlock, K >= 4 ? 4 : 8) void k_learned(Looku
                 qs[s] = list_record_tail(rs_, sk[s] < se[s] ? sk[s] * uint32_t(sizeof(RuleRec))
                                                             : kPastEnd);
             }
-            // straight-line updates (selects, no branches), so no load is
-            // sunk into a conditional block behind another's wait
 #pragma unroll
             for (int s = 0; s < K; ++s) {
-                {
-                    const RuleRec& q = ql[s];
-                    const bool on = lk[s] < le[s];
-                    const bool beats = q.idx < lbest[s];
-                    const bool m = (unsigned(on) & unsigned(beats) &
-                                    unsigned(in_range(w.src[s], q.src_lo, q.src_w)) &
-                                    unsigned(ports_in(w.pp[s], q.port_lo, q.port_w)) &
-                                    unsigned(in_range(w.pr[s], proto_lo(q.proto),
-                                                      proto_w(q.proto)))) != 0u;
-                    lbest[s] = m ? q.idx : lbest[s];
-                    lact[s] = m ? rule_action(q.proto) : lact[s];
-                    lk[s] = on ? ((m | !beats) ? le[s] : lk[s] + 1u) : lk[s];
-                }
-                {
-                    const RuleRec& q = qs[s];
-                    const bool on = sk[s] < se[s];
-                    const bool beats = q.idx < lbest[s];
-                    const bool m = (unsigned(on) & unsigned(beats) &
-                                    unsigned(ports_in(w.pp[s], q.port_lo, q.port_w)) &
-                                    unsigned(in_range(w.pr[s], proto_lo(q.proto),
-                                                      proto_w(q.proto)))) != 0u;
-                    lbest[s] = m ? q.idx : lbest[s];
-                    lact[s] = m ? rule_action(q.proto) : lact[s];
-                    sk[s] = on ? ((m | !beats) ? se[s] : sk[s] + 1u) : sk[s];
-                }
+                step_dst(s, ql[s]);
+                step_src(s, qs[s]);
             }
+        }
+        // Phase 2: the rest of the destination-interval lists alone, at half
+        // the cost per round.
+        for (;;) {
+            bool more = false;
+#pragma unroll
+            for (int s = 0; s < K; ++s) more = more || lk[s] < le[s];
+            if (ballot(more) == 0) break;
+            RuleRec ql[K];
+#pragma unroll
+            for (int s = 0; s < K; ++s)
+                ql[s] = list_record(rl, lk[s] < le[s] ? lk[s] * uint32_t(sizeof(RuleRec)) : kPastEnd);
+#pragma unroll
+            for (int s = 0; s < K; ++s) step_dst(s, ql[s]);
         }
 #pragma unroll
         for (int s = 0; s < K; ++s) {
