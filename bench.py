@@ -506,7 +506,7 @@ def main():
     traffic = committed_traffic(args.workload)
     roofline = {"bound": "alu", "achieved": achieved_tops, "peak": VALU_INT32_PEAK_TOPS,
                 "unit": "Tops/s", "frac": achieved_tops / VALU_INT32_PEAK_TOPS,
-                "traffic": traffic.get("k_learned"), "kernel": "k_learned<true,2>",
+                "traffic": traffic.get("k_learned"), "kernel": "k_learned<true,2,false>",
                 "algorithmic_lane_ops": work["lane_ops"], "algorithmic_bytes": work["bytes"],
                 "hbm_gbs": work["bytes"] / (ms_learned * 1e-3) / 1e9,
                 "hbm_frac": work["bytes"] / (ms_learned * 1e-3) / 1e9 / HBM_PEAK_GBS}

@@ -459,8 +459,12 @@ __device__ __forceinline__ IndexView stage_index(const LookupArgs& a, unsigned c
 
 // With one or two packets per lane, two work-groups per CU (the LDS footprint
 // allows two): eight waves per SIMD, so at most 64 VGPRs.  Four packets per
-// lane need more registers and run one work-group per CU.
-template <bool B_LDS, int K>
+// lane need more registers and run one work-group per CU.  PLAN: the grouped
+// plan of address-wildcard candidates beyond the port table has groups to
+// scan; without any, only its catch-all tail is applied, and the kernel
+// carries none of the plan scan's scalar state (fewer scalar registers kept
+// in vector lanes).
+template <bool B_LDS, int K, bool PLAN>
 __global__ __launch_bounds__(kLearnedBlock, K >= 4 ? 4 : 8) void k_learned(LookupArgs a, PacketsDev pk, size_t n,
                                                            int32_t* __restrict__ out_idx,
                                                            uint8_t* __restrict__ out_act,
@@ -598,7 +602,10 @@ __global__ __launch_bounds__(kLearnedBlock, K >= 4 ? 4 : 8) void k_learned(Looku
             w.best[s] = lbest[s];
             w.act[s] = lact[s];
         }
-        w.scan_plan(a.G);
+        if constexpr (PLAN)
+            w.scan_plan(a.G);
+        else
+            w.seed_tail(a.G);
         w.store(out_idx, out_act, n);
     }
 }
@@ -787,10 +794,13 @@ hipError_t launch_learned(const LookupArgs& a, PacketsDev pk, size_t n, int32_t*
                      : launch_persistent(k_lookup<false>, lds, tiles, s, a, keys, n, out_interval);
     }
     const size_t tiles = (n + 64 * K - 1) / (64 * K);
-#define FW_LEARNED(BL, KK) \
-    launch_persistent(k_learned<BL, KK>, lds, tiles, s, a, pk, n, out_idx, out_act, dflt)
-#define FW_LEARNED_K(BL) (K == 1 ? FW_LEARNED(BL, 1) : K == 2 ? FW_LEARNED(BL, 2) : FW_LEARNED(BL, 4))
-    return b_lds ? FW_LEARNED_K(true) : FW_LEARNED_K(false);
+    const bool plan = a.G.n_groups != 0;
+#define FW_LEARNED(BL, KK, P) \
+    launch_persistent(k_learned<BL, KK, P>, lds, tiles, s, a, pk, n, out_idx, out_act, dflt)
+#define FW_LEARNED_K(BL, P) \
+    (K == 1 ? FW_LEARNED(BL, 1, P) : K == 2 ? FW_LEARNED(BL, 2, P) : FW_LEARNED(BL, 4, P))
+    if (b_lds) return plan ? FW_LEARNED_K(true, true) : FW_LEARNED_K(true, false);
+    return plan ? FW_LEARNED_K(false, true) : FW_LEARNED_K(false, false);
 #undef FW_LEARNED_K
 #undef FW_LEARNED
 }
