@@ -279,6 +279,7 @@ __device__ __forceinline__ uint32_t bucket_walk(const uint16_t* bucket, const ui
                                                 uint32_t M, uint32_t bits, uint32_t steps,
                                                 uint32_t x) {
     uint32_t i = bucket[x >> (32u - bits)];
+#pragma unroll 1   // serial steps (see port_table_first)
     for (uint32_t k = 0; k < steps; ++k) i += (i + 1u < M && B[i + 1u] <= x) ? 1u : 0u;
     return i;
 }
@@ -379,7 +380,11 @@ __device__ __forceinline__ uint32_t port_table_first(const PortTable& t, uint32_
                                                      uint32_t steps_d, uint32_t pp, uint32_t pr) {
     const uint32_t sp = pp >> 16, dp = pp & 0xFFFFu;
     uint32_t is = t.bucket_s[sp >> 8], id = t.bucket_d[dp >> 8];
+    // Each step depends on the one before, so unrolling gains nothing; kept
+    // rolled, the loops need no precomputed remainder masks in scalar registers.
+#pragma unroll 1
     for (uint32_t k = 0; k < steps_s; ++k) is += t.b_s[is + 1u] <= sp ? 1u : 0u;
+#pragma unroll 1
     for (uint32_t k = 0; k < steps_d; ++k) id += t.b_d[id + 1u] <= dp ? 1u : 0u;
     const uint64_t m = t.mask_s[is] & t.mask_d[id] & t.mask_p[pr & 0xFFu];
     return t.rule[m ? uint32_t(__builtin_ctzll(m)) : kPtRules];
