@@ -206,7 +206,9 @@ typedef struct fw_index_stats {
  * on the host, network training on the GPU with the library's own forward,
  * backward and Adam kernels, bf16 quantisation, and error bounds measured
  * with the inference kernel itself.  `opts` and `stats` may be NULL.
- * Synchronous.  Must not run while `rs` is used by other calls.
+ * Synchronous.  Must not run concurrently with other calls on `rs`; work
+ * they enqueued earlier may still be running: a rebuild waits for the device
+ * to finish it before it frees the previous index.
  * Errors: FW_E_INVAL (bad options), FW_E_NOMEM (over mem_budget or
  * allocation failure; `rs` stays usable in the scan modes), FW_E_DEVICE. */
 fw_status fw_build_learned_index(fw_ruleset *rs, const fw_index_opts *opts,
@@ -261,8 +263,9 @@ fw_status fw_index_export(const fw_ruleset *rs, uint32_t what, void *host, size_
  * the start of its fw_classify_ex call to the end of the stream
  * synchronisation: the library's own enqueue-to-completion latency, with no
  * binding in between.  Results go to out_rule_idx / out_action at offset 0
- * (at least max(count) entries each).  Errors: those of fw_classify_ex, and
- * FW_E_ALIGN for a start that is not a multiple of 16. */
+ * (at least max(count) entries each).  Errors: those of fw_classify_ex,
+ * FW_E_INVAL for a NULL argument or packet field, and FW_E_ALIGN for a start
+ * that is not a multiple of 16. */
 fw_status fw_closed_loop(const fw_ruleset *rs, const fw_packets *pk, uint32_t n_batches,
                          const size_t *start, const size_t *count, int32_t *out_rule_idx,
                          uint8_t *out_action, const fw_classify_opts *opts, double *seconds);

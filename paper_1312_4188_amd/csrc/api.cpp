@@ -96,7 +96,6 @@ void ruleset_view(const fw_ruleset* rs, const RuleRec** rules, const uint2** pai
     *default_action = rs->default_action;
 }
 
-// A device fault in earlier asynchronous work is sticky; report it before new work.
 // Packets per lane when the caller leaves it to the library: the most (up to
 // `most`) that still gives the launch 8,192 waves (8 per SIMD on 256 CUs), so
 // small batches spread over more waves and each wave's scan is shorter.
@@ -106,6 +105,7 @@ static uint32_t default_packets_per_lane(size_t n, uint32_t most) {
     return k;
 }
 
+// A device fault in earlier asynchronous work is sticky; report it before new work.
 static fw_status check_device_state() {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "earlier device work failed");
@@ -261,6 +261,9 @@ fw_status fw_closed_loop(const fw_ruleset* rs, const fw_packets* pk, uint32_t n_
     if (!rs || !pk) return fail(FW_E_INVAL, "ruleset or packets is NULL");
     if (n_batches == 0) return FW_OK;
     if (!start || !count || !seconds) return fail(FW_E_INVAL, "NULL argument");
+    // checked here, before the slices are offset (an offset NULL is not NULL)
+    if (!pk->src_ip || !pk->dst_ip || !pk->src_port || !pk->dst_port || !pk->proto)
+        return fail(FW_E_INVAL, "a packet field pointer is NULL");
     fw_classify_opts o{};
     if (opts) o = *opts;
     hipStream_t stream = static_cast<hipStream_t>(o.stream);
@@ -289,7 +292,15 @@ fw_status fw_build_learned_index(fw_ruleset* rs, const fw_index_opts* opts,
     const fw_status st = build_index(rs->source.data(), rs->h_rules.data(), rs->n_rules, o,
                                      stats, &built);
     if (st != FW_OK) return st;
-    destroy_index(rs->index);
+    if (rs->index) {
+        // classifications enqueued earlier may still read the old index
+        const hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) {
+            destroy_index(built);
+            return hip_fail(e, "waiting for work on the previous index");
+        }
+        destroy_index(rs->index);
+    }
     rs->index = built;
     return FW_OK;
 }

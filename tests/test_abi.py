@@ -125,3 +125,11 @@ def test_argument_errors(fw):
     assert lib.fw_classify_multi(bad, 1, None) == fw.E_INVAL       # NULL ruleset
     assert lib.fw_classify_multi(None, 0, None) == fw.OK           # nothing to do
     assert lib.fw_autotune_multi(None, 3, None, None, None) == fw.E_INVAL
+    # closed loop: NULL packet fields are caught before the slices are offset
+    # (the ruleset handle is never touched)
+    starts = (ctypes.c_size_t * 1)(16)
+    counts = (ctypes.c_size_t * 1)(64)
+    secs = (ctypes.c_double * 1)()
+    assert lib.fw_closed_loop(fake, ctypes.byref(fw.Packets()), 1, starts, counts, None, None,
+                              None, secs) == fw.E_INVAL
+    assert lib.fw_closed_loop(None, None, 1, starts, counts, None, None, None, secs) == fw.E_INVAL

@@ -436,3 +436,27 @@ def test_positions_identical_across_packets_per_lane():
             torch.cuda.synchronize()
             assert_same((idx.cpu().numpy(), act.cpu().numpy()), want, f"190 experts K={ppl}")
     assert misses[1] == misses[2] == misses[4] > 0
+
+
+def test_rebuild_waits_for_work_in_flight():
+    """A classification still running on another stream when the index is rebuilt: the
+    rebuild waits for it before freeing the old index, so its results stay exact."""
+    import torch
+    rules, pk = gen.workload("scan_1000x1M", seed=16, n_packets=2_000_000)
+    sample = np.arange(0, len(pk), 97)
+    want = oracle.classify(rules, pk.subset(sample), threads=16)
+    fw = fwmod()
+    with fw.Ruleset(rules) as rs:
+        rs.build_learned_index(**FAST)
+        dp = fw.DevicePackets.from_host(pk)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())     # the packets' upload
+        say("classify on a side stream, then rebuild the index at once")
+        idx, act = rs.classify(dp, mode="learned", stream=side)[:2]
+        rs.build_learned_index(**dict(FAST, seed=2))
+        side.synchronize()
+        assert_same((idx.cpu().numpy()[sample], act.cpu().numpy()[sample]), want,
+                    "classified while the index was rebuilt")
+        again = rs.classify(dp, mode="learned")[:2]
+        torch.cuda.synchronize()
+        assert np.array_equal(again[0].cpu().numpy(), idx.cpu().numpy())
