@@ -6,8 +6,9 @@
 // slot (stream) free and the arena can hold its packets and results; it is
 // then copied in, classified and copied out by that worker, and an event
 // marks its completion.  Several workers issue the HIP calls of different
-// requests in parallel, which is what bounds throughput for small requests.  Requests on different slots overlap on the device;
-// each is classified exactly as it would be alone.  Copies run either on the
+// requests in parallel (per-request host work is what bounds throughput for
+// small requests).  Requests on different slots overlap on the device; each
+// is classified exactly as it would be alone.  Copies run either on the
 // request's slot stream, or (pipeline mode) on one shared upload stream and
 // one shared download stream in admission order, with events ordering
 // upload -> classification (slot stream) -> download.
