@@ -154,13 +154,23 @@ def test_tiny_rulesets_every_partition_count(R):
         assert_same(classify_np(rules, pk, **kw), want, f"R={R} {kw}")
 
 
-def test_boundary_packets():
-    """Packets at every rule's lo-1, lo, hi, hi+1 in each field; /0 and /32; ports 0 and 65535."""
+@pytest.mark.parametrize("wild", [False, True])
+def test_boundary_packets(wild):
+    """Packets at every rule's lo-1, lo, hi, hi+1 in each field; /0 and /32; ports 0 and 65535.
+    Every scan mode and the learned path (whose interval, port-table and source-bucket lookups
+    all turn on these values); with `wild`, a third of the rules leave both addresses
+    unspecified, so the port/protocol table's edges are probed as well."""
     rules = gen.make_rules(64, 31)
     rules.src_plen[::7] = 32
     rules.dst_plen[::5] = 0
     rules.dport_lo[::6] = 0
     rules.dport_hi[::6] = 65535
+    if wild:
+        rules.src_plen[1::3] = 0
+        rules.dst_plen[1::3] = 0
+        catch = ((rules.src_plen == 0) & (rules.dst_plen == 0) & (rules.sport_lo == 0)
+                 & (rules.sport_hi == 65535) & (rules.dport_lo == 0) & (rules.dport_hi == 65535))
+        rules.proto_any[catch] = 0                 # no catch-all: every rule stays reachable
     rng = np.random.Generator(np.random.PCG64(31))
     from tests.boxes import rule_box
     pts = []
@@ -178,8 +188,18 @@ def test_boundary_packets():
     pk = points_to_packets(pts)
     want = oracle.classify(rules, pk)
     for kw in SCAN_MODES:
-        say(f"boundary {kw}")
+        say(f"boundary wild={wild} {kw}")
         assert_same(classify_np(rules, pk, **kw), want, f"boundary {kw}")
+    import torch
+    fw = fwmod()
+    with fw.Ruleset(rules) as rs:
+        rs.build_learned_index(epochs1=300, epochs2=600)
+        dp = fw.DevicePackets.from_host(pk)
+        for ppl in (1, 2, 4):
+            say(f"boundary wild={wild} learned K={ppl}")
+            idx, act = rs.classify(dp, mode="learned", packets_per_lane=ppl)[:2]
+            torch.cuda.synchronize()
+            assert_same((idx.cpu().numpy(), act.cpu().numpy()), want, f"boundary learned K={ppl}")
 
 
 def test_10000_rules_16M_packets_sampled():
