@@ -482,7 +482,10 @@ std::vector<uint8_t> lds_image(const LearnedIndex* ix, const std::vector<float>&
         if (bytes) std::memcpy(img.data() + at, src, bytes);
     };
     put(L.w1, w1q.data(), kInferStride * sizeof(float));
-    for (uint32_t e = 0; e < E; ++e) put(L.meta + size_t(e) * kLdsMetaBytes, &meta[e], sizeof(ExpertMeta));
+    for (uint32_t e = 0; e < E; ++e) {
+        const LdsExpert r{meta[e].pos_lo, meta[e].err};
+        put(L.meta + size_t(e) * sizeof(LdsExpert), &r, sizeof r);
+    }
     put(L.w2, w2r.data(), w2r.size() * 4);
     put(L.pt, &ix->pt, sizeof(PortTable));
     put(L.bk, ix->bs_bucket.data(), ix->bs_bucket.size() * 2);
@@ -497,8 +500,10 @@ std::vector<uint8_t> lds_image(const LearnedIndex* ix, const std::vector<float>&
 
 // Stage-2 rows (see kRowDwords) from bf16 networks in 32-slot segments
 // [w1][b1][w2][b2]: dword k = (w1[k], b1[k]), w1 in the low half; w2[k] and
-// b2 widened to fp32 (a bf16 value is the top half of its fp32 pattern).
-std::vector<uint32_t> stage2_rows(const std::vector<uint16_t>& seg, uint32_t E) {
+// b2 widened to fp32 (a bf16 value is the top half of its fp32 pattern); the
+// expert's key_lo, inv_span and pos_span beside the bias.
+std::vector<uint32_t> stage2_rows(const std::vector<uint16_t>& seg, uint32_t E,
+                                  const std::vector<ExpertMeta>& meta) {
     std::vector<uint32_t> out(size_t(E) * kRowDwords, 0);
     for (uint32_t e = 0; e < E; ++e) {
         const uint16_t* r = seg.data() + size_t(e) * kInferStride;
@@ -508,6 +513,9 @@ std::vector<uint32_t> stage2_rows(const std::vector<uint16_t>& seg, uint32_t E) 
             o[kRowOut + k] = uint32_t(r[64 + k]) << 16;
         }
         o[kRowBias] = uint32_t(r[96]) << 16;
+        o[kRowKeyLo] = meta[e].key_lo;
+        std::memcpy(&o[kRowInvSpan], &meta[e].inv_span, 4);
+        std::memcpy(&o[kRowPosSpan], &meta[e].pos_span, 4);
     }
     return out;
 }
@@ -837,7 +845,7 @@ fw_status build_index(const fw_rule* rules, const RuleRec* recs, uint32_t n_rule
         fold_relu([&](uint32_t k) { return from_bf16(row[k]); },
                   [&](uint32_t k, float v) { row[k] = to_bf16(v); });   // exact: v is bf16
     }
-    const std::vector<uint32_t> w2r = stage2_rows(w2q, E);
+    const std::vector<uint32_t> w2r = stage2_rows(w2q, E, meta);
     if ((e = upload(ix->d_w2, w2r, s)) != hipSuccess ||
         (e = upload(ix->d_meta, meta, s)) != hipSuccess)
         return fail_train(e, "uploading stage-2 weights");

@@ -51,13 +51,18 @@ constexpr uint32_t kNoExpert = 0xFFFFFFFFu;
 // 32-slot segments, padded to 104 entries (a multiple of 8); hidden units past
 // H are zero.  A stage-2 row (kRowDwords dwords) holds one expert: dword k
 // is the bf16 pair (w1[k], b1[k]) (w1 in the low half), dwords 32 + k hold
-// w2[k] and dword 64 holds b2, both as fp32 (bf16 values widened, exact); the
-// rest is zero.  Rows of all-fp32 weights would not fit the LDS budget of the
-// lookup at 10,000 rules; fp32 w2 saves the lookup one widening per unit.
+// w2[k] and dword 64 holds b2, both as fp32 (bf16 values widened, exact);
+// dwords 65..67 carry the expert's input scaling (key_lo, inv_span) and
+// pos_span, read with the bias in one 16-byte load.  Rows of all-fp32 weights
+// would not fit the LDS budget of the lookup at 10,000 rules; fp32 w2 saves
+// the lookup one widening per unit.
 constexpr uint32_t kInferStride = 104;
 constexpr uint32_t kRowPairs = 0;     // dword of (w1[0], b1[0]) in a stage-2 row
 constexpr uint32_t kRowOut = 32;      // dword of w2[0]
 constexpr uint32_t kRowBias = 64;     // dword of b2
+constexpr uint32_t kRowKeyLo = 65;    // ExpertMeta::key_lo
+constexpr uint32_t kRowInvSpan = 66;  // ExpertMeta::inv_span
+constexpr uint32_t kRowPosSpan = 67;  // ExpertMeta::pos_span
 constexpr uint32_t kRowDwords = 68;   // stage-2 row stride (a 16-byte multiple)
 
 // Port/protocol table of the first (up to 64) candidates that leave both
@@ -92,18 +97,22 @@ constexpr uint64_t kMaxListBytes = 0x7FFF0000ull;
 constexpr uint32_t kListPastEnd = 0x7FFFFFF0u;
 static_assert(kListPastEnd > kMaxListBytes + 32, "past-the-end offset must be out of range");
 
-// LDS strides of the per-expert data, chosen so that lanes reading different
+// What the lookup reads of an expert record besides its row: position
+// offset and error bound, one 8-byte load.
+struct LdsExpert {
+    int32_t pos_lo;
+    uint32_t err;
+};
+
+// LDS stride of the expert rows, chosen so that lanes reading different
 // experts spread over all LDS banks: a row of 68 dwords puts expert e at
 // bank offset 68 e, which takes 8 values modulo 32 banks and 16 modulo 64
-// (each 16-byte read covering 4 banks), and 48-byte expert records (12
-// dwords) spread the same way.
-constexpr uint32_t kLdsMetaBytes = 48;
-static_assert(kLdsMetaBytes >= sizeof(ExpertMeta) && kLdsMetaBytes % 16 == 0, "record layout");
-static_assert(kRowDwords % 4 == 0 && kRowBias < kRowDwords, "stage-2 row layout");
+// (each 16-byte read covering 4 banks); the 8-byte records take 32.
+static_assert(kRowDwords % 4 == 0 && kRowPosSpan < kRowDwords, "stage-2 row layout");
 
 // Byte offsets of the lookup kernel's LDS image, every section 16-byte
-// aligned: stage-1 weights (kInferStride fp32), expert records
-// (kLdsMetaBytes each), expert rows (kRowDwords each), the
+// aligned: stage-1 weights (kInferStride fp32), expert records (LdsExpert
+// each), expert rows (kRowDwords each), the
 // port/protocol table, the source bucket table, and, with the boundary arrays
 // in LDS (b_lds), B, Bs, off and soff.  The index build writes this image
 // once per variant; the kernel copies it whole.
@@ -114,7 +123,7 @@ struct LdsLayout {
                                   bool b_lds) {
         size_t o = up16(kInferStride * sizeof(float));
         meta = o;
-        o = up16(o + size_t(E) * kLdsMetaBytes);
+        o = up16(o + size_t(E) * sizeof(LdsExpert));
         w2 = o;
         o = up16(o + size_t(E) * kRowDwords * sizeof(uint32_t));
         pt = o;

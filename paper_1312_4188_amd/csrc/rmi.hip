@@ -233,13 +233,17 @@ __device__ __forceinline__ uint32_t route(const float* w1, uint32_t E, uint32_t 
     return e[0];
 }
 
-// Stage 2: position estimate of x inside expert e's range of positions.
-// Hidden unit k widens its bf16 pair (w1, b1) with one shift and one mask
-// (exact), forms fp32 max(w1 v + b1, 0) as one clamped multiply-add, and adds
-// its fp32 w2 share with a second: four instructions per unit.
-__device__ __forceinline__ int32_t position(const uint32_t* row, const ExpertMeta& m,
-                                            uint32_t x) {
-    const float v = x >= m.key_lo ? fminf(float(x - m.key_lo) * m.inv_span, 1.0f) : 0.0f;
+// Stage 2: position estimate of x inside expert e's range of positions (the
+// row carries the expert's input scaling and position span; pos_lo is its
+// first position).  Hidden unit k widens its bf16 pair (w1, b1) with one
+// shift and one mask (exact), forms fp32 max(w1 v + b1, 0) as one clamped
+// multiply-add, and adds its fp32 w2 share with a second: four instructions
+// per unit.
+__device__ __forceinline__ int32_t position(const uint32_t* row, int32_t pos_lo, uint32_t x) {
+    const uint32_t key_lo = row[kRowKeyLo];
+    const float inv_span = __uint_as_float(row[kRowInvSpan]);
+    const float pos_span = __uint_as_float(row[kRowPosSpan]);
+    const float v = x >= key_lo ? fminf(float(x - key_lo) * inv_span, 1.0f) : 0.0f;
     float y = __uint_as_float(row[kRowBias]);
 #pragma unroll
     for (uint32_t c = 0; c < kSeg; c += 4) {
@@ -254,8 +258,8 @@ __device__ __forceinline__ int32_t position(const uint32_t* row, const ExpertMet
             y = fmaf(op[i], relu01(fmaf(w1, v, b1)), y);
         }
     }
-    const float q = fminf(fmaxf(y * m.pos_span, 0.0f), m.pos_span);  // NaN -> 0
-    return m.pos_lo + int32_t(rintf(q));
+    const float q = fminf(fmaxf(y * pos_span, 0.0f), pos_span);  // NaN -> 0
+    return pos_lo + int32_t(rintf(q));
 }
 
 // Largest j in [lo, hi] with B[j] <= x, assuming B[lo] <= x.
@@ -286,16 +290,14 @@ __device__ __forceinline__ uint32_t bucket_walk(const uint16_t* bucket, const ui
 
 // Interval of x, routed to expert e by stage 1: the window [p - err, p + err]
 // of the predicted position first, checked by B[j] <= x < B[j+1]; a miss
-// falls back to the full range.  Expert records may sit at a padded stride
-// (META_BYTES bytes) in LDS; see LdsLayout.
-template <uint32_t META_BYTES>
+// falls back to the full range.  `meta` holds each expert's first position and
+// error bound (the rest of its record rides in its row).
 __device__ __forceinline__ uint32_t locate(const uint32_t* B, uint32_t M, const uint32_t* w2,
-                                           const ExpertMeta* meta, uint32_t use_net, uint32_t e,
+                                           const LdsExpert* meta, uint32_t use_net, uint32_t e,
                                            uint32_t x, bool* miss) {
     if (use_net) {
-        const ExpertMeta m = *reinterpret_cast<const ExpertMeta*>(
-            reinterpret_cast<const unsigned char*>(meta) + size_t(e) * META_BYTES);
-        const int32_t p = position(w2 + size_t(e) * kRowDwords, m, x);
+        const LdsExpert m = meta[e];
+        const int32_t p = position(w2 + size_t(e) * kRowDwords, m.pos_lo, x);
         const int64_t lo = int64_t(p) - int64_t(m.err), hi = int64_t(p) + int64_t(m.err);
         const uint32_t l = uint32_t(lo < 0 ? 0 : (lo >= int64_t(M) ? M - 1 : lo));
         const uint32_t h = uint32_t(hi < int64_t(l) ? l : (hi >= int64_t(M) ? M - 1 : hi));
@@ -326,7 +328,7 @@ __global__ void k_err_bound(LookupArgs a, const uint32_t* __restrict__ keys,
     if (i >= n) return;
     const uint32_t x = keys[i];
     const uint32_t e = route(a.w1, a.E, x);
-    const int32_t p = position(a.w2 + size_t(e) * kRowDwords, a.meta[e], x);
+    const int32_t p = position(a.w2 + size_t(e) * kRowDwords, a.meta[e].pos_lo, x);
     const int32_t d = p - pos[i];
     atomicMax(err + e, uint32_t(d < 0 ? -d : d));
 }
@@ -412,7 +414,7 @@ constexpr uint32_t kLearnedK = 2;     // default packets per lane in the classif
 
 struct IndexView {
     const float* w1;
-    const ExpertMeta* meta;
+    const LdsExpert* meta;
     const uint32_t* w2;       // stage-2 rows, kRowDwords each
     const uint32_t* B;
     const uint32_t* Bs;
@@ -452,7 +454,7 @@ __device__ __forceinline__ IndexView stage_index(const LookupArgs& a, unsigned c
     stage_words(reinterpret_cast<uint4*>(smem), a.image[B_LDS], uint32_t(L.bytes / 16u));
     __syncthreads();
     return IndexView{reinterpret_cast<const float*>(smem + L.w1),
-                     reinterpret_cast<const ExpertMeta*>(smem + L.meta),
+                     reinterpret_cast<const LdsExpert*>(smem + L.meta),
                      reinterpret_cast<const uint32_t*>(smem + L.w2),
                      B_LDS ? reinterpret_cast<const uint32_t*>(smem + L.b) : a.B,
                      B_LDS ? reinterpret_cast<const uint32_t*>(smem + L.bs) : a.Bs,
@@ -493,7 +495,7 @@ __global__ __launch_bounds__(kLearnedBlock, K >= 4 ? 4 : 8) void k_learned(Looku
         for (int s = 0; s < K; ++s) {
             const bool valid = w.p0 + s < n;
             bool miss = false;
-            jj[s] = locate<kLdsMetaBytes>(v.B, a.M, v.w2, v.meta, a.use_net,
+            jj[s] = locate(v.B, a.M, v.w2, v.meta, a.use_net,
                                           a.use_net ? ex[s] : 0u, w.dst[s], &miss);
             if (a.miss) {
                 const uint64_t mm = ballot(valid && miss);
@@ -631,7 +633,7 @@ __global__ __launch_bounds__(kLearnedBlock) void k_lookup(LookupArgs a,
         const bool valid = i < n;
         bool miss = false;
         const uint32_t x = valid ? keys[i] : 0u;
-        const uint32_t j = locate<kLdsMetaBytes>(v.B, a.M, v.w2, v.meta, a.use_net,
+        const uint32_t j = locate(v.B, a.M, v.w2, v.meta, a.use_net,
                                                  a.use_net ? route(v.w1, a.E, x) : 0u, x, &miss);
         if (valid) out_interval[i] = int32_t(j);
     }
