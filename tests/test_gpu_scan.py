@@ -339,3 +339,33 @@ def test_closed_loop_probe():
         with pytest.raises(fw.FwError) as ei:
             rs.closed_loop(dp, np.array([8]), np.array([10]))
         assert ei.value.status == fw.E_ALIGN
+
+
+def test_permutation_and_batch_size_invariance():
+    """Invariants of a per-packet result (the oracle's own tests pin them on the CPU): permuting
+    the packets permutes the outputs, and any 16-aligned slice of a batch, of any length,
+    classifies exactly as the same packets inside the whole batch, in every mode (the library
+    picks packets per lane and launch shapes by batch size, so this crosses those choices)."""
+    import torch
+    fw = fwmod()
+    rules, pk = gen.workload("scan_1000x1M", seed=17, n_packets=300_000)
+    rng = np.random.Generator(np.random.PCG64(17))
+    perm = rng.permutation(len(pk))
+    dp = fw.DevicePackets.from_host(pk)
+    dperm = fw.DevicePackets.from_host(pk.subset(perm))
+    cuts = [(0, 1), (16, 63), (4096, 65), (160_000, 9_999), (32, 300_000 - 32)]
+    with fw.Ruleset(rules) as rs:
+        rs.build_learned_index(epochs1=300, epochs2=600)
+        modes = SCAN_MODES[:4] + [dict(mode="hybrid", partitions=16)] + \
+            [dict(mode="learned", packets_per_lane=k) for k in (0, 1, 2, 4)]
+        for kw in modes:
+            say(f"invariance {kw}")
+            full = [t.cpu().numpy() for t in rs.classify(dp, **kw)[:2]]
+            got = [t.cpu().numpy() for t in rs.classify(dperm, **kw)[:2]]
+            torch.cuda.synchronize()
+            assert np.array_equal(got[0], full[0][perm]) and np.array_equal(got[1], full[1][perm]), \
+                f"permutation {kw}"
+            for a, m in cuts:
+                part = [t.cpu().numpy() for t in rs.classify(dp.slice(a, a + m), **kw)[:2]]
+                assert np.array_equal(part[0], full[0][a:a + m]), f"slice {a}+{m} {kw}"
+                assert np.array_equal(part[1], full[1][a:a + m]), f"slice {a}+{m} {kw}"
