@@ -169,6 +169,23 @@ def rules_to_records(rules) -> np.ndarray:
     return rec
 
 
+def _check_outputs(out_idx: torch.Tensor, out_act: torch.Tensor, n: int, dev):
+    """Result buffers: n entries each, contiguous, on the packets' device."""
+    for name, t, size in (("out_idx", out_idx, 4), ("out_act", out_act, 1)):
+        if t.device != dev or t.dim() != 1 or not t.is_contiguous() or t.shape[0] < n \
+                or t.element_size() != size:
+            raise ValueError(f"{name} must be a contiguous 1-D tensor of at least {n} "
+                             f"{size}-byte elements on {dev}")
+
+
+def _record_on(stream, tensors):
+    """Work enqueued on a side stream uses these tensors: tell torch's allocator, so that
+    memory freed by the caller is not handed out again before that work is done."""
+    if isinstance(stream, torch.cuda.Stream) and stream != torch.cuda.current_stream():
+        for t in tensors:
+            t.record_stream(stream)
+
+
 def _stream_ptr(stream) -> int | None:
     if stream is None:
         return torch.cuda.current_stream().cuda_stream
@@ -207,6 +224,23 @@ class DevicePackets:
     def c_struct(self) -> Packets:
         return Packets(self.src_ip.data_ptr(), self.dst_ip.data_ptr(), self.sport.data_ptr(),
                        self.dport.data_ptr(), self.proto.data_ptr())
+
+    def fields(self):
+        return (self.src_ip, self.dst_ip, self.sport, self.dport, self.proto)
+
+    def check(self) -> int:
+        """The kernels read len(self) entries of each field: validate that before any launch."""
+        n = len(self)
+        dev = self.src_ip.device
+        for name, t, size in zip(("src_ip", "dst_ip", "sport", "dport", "proto"), self.fields(),
+                                 (4, 4, 2, 2, 1)):
+            if t.device != dev or dev.type != "cuda":
+                raise ValueError(f"packet field {name} must be on {dev} (a CUDA device)")
+            if t.dim() != 1 or t.shape[0] != n or not t.is_contiguous():
+                raise ValueError(f"packet field {name} must be a contiguous 1-D tensor of {n}")
+            if t.element_size() != size:
+                raise ValueError(f"packet field {name} must have {size}-byte elements")
+        return n
 
 
 class Ruleset:
@@ -252,12 +286,14 @@ class Ruleset:
                  out_idx: torch.Tensor | None = None, out_act: torch.Tensor | None = None,
                  lookup: int = 0, packets_per_lane: int = 0, count_misses: bool = False):
         """Enqueue first-match classification; returns (rule_idx int32, action uint8[, misses])."""
-        n = len(pk)
+        n = pk.check()
         dev = pk.src_ip.device
         if out_idx is None:
             out_idx = torch.empty(n, dtype=torch.int32, device=dev)
         if out_act is None:
             out_act = torch.empty(n, dtype=torch.uint8, device=dev)
+        _check_outputs(out_idx, out_act, n, dev)
+        _record_on(stream, pk.fields() + (out_idx, out_act))
         misses = ctypes.c_uint64(0)
         opts = ClassifyOpts(MODES[mode] if isinstance(mode, str) else int(mode),
                             int(partitions), _stream_ptr(stream), int(lookup),
@@ -272,10 +308,11 @@ class Ruleset:
 
     def classify_plain(self, pk: DevicePackets, out_idx=None, out_act=None):
         """fw_classify: mode AUTO on the null stream."""
-        n = len(pk)
+        n = pk.check()
         dev = pk.src_ip.device
         out_idx = torch.empty(n, dtype=torch.int32, device=dev) if out_idx is None else out_idx
         out_act = torch.empty(n, dtype=torch.uint8, device=dev) if out_act is None else out_act
+        _check_outputs(out_idx, out_act, n, dev)
         c = pk.c_struct()
         _check(load_library().fw_classify(self._h, ctypes.byref(c), n, out_idx.data_ptr(),
                                           out_act.data_ptr()))
@@ -297,8 +334,11 @@ class Ruleset:
         """fw_closed_loop: batches [starts[k], starts[k] + counts[k]) one after another, each
         waited for; returns (native enqueue-to-completion seconds per batch, rule_idx, action),
         the outputs holding the last batch's results at their front."""
+        n = pk.check()
         st = np.ascontiguousarray(starts, dtype=np.uint64)
         ct = np.ascontiguousarray(counts, dtype=np.uint64)
+        if st.shape != ct.shape or (st.size and int((st + ct).max()) > n):
+            raise ValueError("every batch [start, start + count) must lie inside the packets")
         cap = int(ct.max()) if ct.size else 1
         dev = pk.src_ip.device
         oi = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
@@ -313,7 +353,11 @@ class Ruleset:
         return sec, oi, oa
 
     def lookup_intervals(self, keys: torch.Tensor, lookup: int = 0, stream=None) -> torch.Tensor:
+        if keys.device.type != "cuda" or keys.dim() != 1 or not keys.is_contiguous() \
+                or keys.element_size() != 4:
+            raise ValueError("keys must be a contiguous 1-D CUDA tensor of 32-bit values")
         out = torch.empty(keys.shape[0], dtype=torch.int32, device=keys.device)
+        _record_on(stream, (keys, out))
         _check(load_library().fw_index_lookup(self._h, keys.data_ptr(), keys.shape[0],
                                               out.data_ptr(), int(lookup), _stream_ptr(stream)))
         return out
@@ -364,14 +408,17 @@ def _chain_array(items):
     """items: list of (Ruleset, DevicePackets, out_idx tensor, out_act tensor)."""
     arr = (ChainBatch * len(items))()
     for k, (rs, pk, oi, oa) in enumerate(items):
-        arr[k] = ChainBatch(rs.handle.value, pk.c_struct(), len(pk), oi.data_ptr(),
-                            oa.data_ptr())
+        n = pk.check()
+        _check_outputs(oi, oa, n, pk.src_ip.device)
+        arr[k] = ChainBatch(rs.handle.value, pk.c_struct(), n, oi.data_ptr(), oa.data_ptr())
     return arr
 
 
 def classify_multi(items, stream=None, packets_per_lane=0, placement=0, rule_tile=0):
     """One persistent launch over many chains; items as for _chain_array (outputs preallocated)."""
     arr = _chain_array(items)
+    for _, pk, oi, oa in items:
+        _record_on(stream, pk.fields() + (oi, oa))
     opts = MultiOpts(_stream_ptr(stream), int(packets_per_lane), int(placement), int(rule_tile), 0)
     _check(load_library().fw_classify_multi(arr, len(items), ctypes.byref(opts)))
 

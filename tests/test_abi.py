@@ -133,3 +133,30 @@ def test_argument_errors(fw):
     assert lib.fw_closed_loop(fake, ctypes.byref(fw.Packets()), 1, starts, counts, None, None,
                               None, secs) == fw.E_INVAL
     assert lib.fw_closed_loop(None, None, 1, starts, counts, None, None, None, secs) == fw.E_INVAL
+
+
+def test_binding_checks_shapes_before_any_launch(fw):
+    """The binding validates what the kernels will read and write (lengths, element sizes,
+    contiguity, device) and raises before calling into the library."""
+    import torch
+    n = 32
+    good = [torch.zeros(n, dtype=d) for d in (torch.int32, torch.int32, torch.int16,
+                                                torch.int16, torch.uint8)]
+    with pytest.raises(ValueError, match="CUDA"):
+        fw.DevicePackets(*good).check()               # host tensors
+    short = list(good)
+    short[3] = torch.zeros(n - 1, dtype=torch.int16)
+    with pytest.raises(ValueError):
+        fw.DevicePackets(*short).check()
+    wide = list(good)
+    wide[4] = torch.zeros(n, dtype=torch.int32)
+    with pytest.raises(ValueError):
+        fw.DevicePackets(*wide).check()
+    dev = torch.device("cpu")
+    with pytest.raises(ValueError, match="out_idx"):
+        fw._check_outputs(torch.zeros(n - 1, dtype=torch.int32), torch.zeros(n, dtype=torch.uint8),
+                          n, dev)
+    with pytest.raises(ValueError, match="out_act"):
+        fw._check_outputs(torch.zeros(n, dtype=torch.int32), torch.zeros(n, dtype=torch.int32),
+                          n, dev)
+    fw._check_outputs(torch.zeros(n, dtype=torch.int32), torch.zeros(n, dtype=torch.uint8), n, dev)

@@ -272,6 +272,14 @@ def test_plain_entry_point_and_errors():
         assert ei.value.status == fw.E_INVAL
         # n == 0 is accepted and writes nothing
         rs.classify(dp.slice(0, 0))
+        # fields of unequal length, and outputs too short, never reach a kernel
+        with pytest.raises(ValueError):
+            rs.classify(fw.DevicePackets(dp.src_ip, dp.dst_ip, dp.sport[:-16], dp.dport,
+                                         dp.proto))
+        with pytest.raises(ValueError):
+            rs.classify(dp, out_idx=torch.empty(len(dp) - 1, dtype=torch.int32, device="cuda"))
+        with pytest.raises(ValueError):
+            rs.closed_loop(dp, [0], [len(dp) + 16])
 
 
 @pytest.mark.parametrize("catch_all_at", [None, 0, 150, 299])
