@@ -434,6 +434,10 @@ def autotune_multi(items, stream=None):
              "rule_tile": best.rule_tile}, float(ms.value))
 
 
+# element sizes of src_ip, dst_ip, sport, dport, proto, rule index and action
+_SERVER_ITEMSIZES = (4, 4, 2, 2, 1, 4, 1)
+
+
 class Server:
     """Continuous-batching server over resident rulesets (fw_server_*).
 
@@ -461,6 +465,10 @@ class Server:
             if not (isinstance(a, np.ndarray) and a.flags.c_contiguous):
                 raise TypeError("server buffers must be C-contiguous numpy arrays")
         n = int(src_ip.shape[0])
+        for a, size in zip(arrays, _SERVER_ITEMSIZES):
+            if a.ndim != 1 or a.shape[0] != n or a.itemsize != size:
+                raise ValueError(f"server buffers must be 1-D arrays of {n} entries with "
+                                 "4, 4, 2, 2, 1, 4 and 1-byte elements")
         pk = HostPackets(*(a.ctypes.data for a in arrays[:5]))
         t = ctypes.c_uint64(0)
         _check(load_library().fw_server_submit(self._h, int(chain), ctypes.byref(pk), n,
@@ -484,7 +492,18 @@ class Server:
         ch = np.ascontiguousarray(chain, dtype=np.uint32)
         off = np.ascontiguousarray(offset, dtype=np.uint64)
         cnt = np.ascontiguousarray(n, dtype=np.uint64)
-        pk = HostPackets(*(np.asarray(a).ctypes.data for a in pool))
+        pool = [np.ascontiguousarray(a) for a in pool]   # kept alive through the call
+        total = int(pool[0].shape[0])
+        for a, size in zip(list(pool) + [out_idx, out_act], _SERVER_ITEMSIZES):
+            if a.ndim != 1 or a.shape[0] != total or a.itemsize != size:
+                raise ValueError(f"pool and result arrays must be 1-D with {total} entries and "
+                                 "4, 4, 2, 2, 1, 4 and 1-byte elements")
+        if not (out_idx.flags.c_contiguous and out_act.flags.c_contiguous):
+            raise TypeError("result arrays must be C-contiguous")
+        if not (len(arr) == len(ch) == len(off) == len(cnt)) or \
+                (len(off) and int((off + cnt).max()) > total):
+            raise ValueError("every request [offset, offset + n) must lie inside the pool")
+        pk = HostPackets(*(a.ctypes.data for a in pool))
         times = np.zeros((len(arr), 3), dtype=np.float64)
         _check(load_library().fw_server_replay(self._h, len(arr), arr.ctypes.data, ch.ctypes.data,
                                                off.ctypes.data, cnt.ctypes.data, ctypes.byref(pk),

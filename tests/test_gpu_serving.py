@@ -111,4 +111,15 @@ def test_empty_request_and_bad_chain():
             sv.submit(3, e, e, np.empty(0, np.uint16), np.empty(0, np.uint16),
                       np.empty(0, np.uint8), np.empty(0, np.int32), np.empty(0, np.uint8))
         assert ei.value.status == fw.E_INVAL
+        # buffers of unequal length or the wrong element size never reach the library
+        a = np.zeros(64, np.uint32)
+        with pytest.raises(ValueError):
+            sv.submit(0, a, a, np.zeros(63, np.uint16), np.zeros(64, np.uint16),
+                      np.zeros(64, np.uint8), np.zeros(64, np.int32), np.zeros(64, np.uint8))
+        with pytest.raises(ValueError):
+            sv.submit(0, a, a, np.zeros(64, np.uint16), np.zeros(64, np.uint16),
+                      np.zeros(64, np.uint8), np.zeros(64, np.int64), np.zeros(64, np.uint8))
+        pool = [a, a, np.zeros(64, np.uint16), np.zeros(64, np.uint16), np.zeros(64, np.uint8)]
+        with pytest.raises(ValueError):   # a request past the end of the pool
+            sv.replay([0.0], [0], [32], [64], pool, np.zeros(64, np.int32), np.zeros(64, np.uint8))
     rs[0].close()
