@@ -60,15 +60,26 @@ __device__ __forceinline__ bool full_match(const RuleRec& q, uint32_t src, uint3
             unsigned(in_range(pr, proto_lo(q.proto), proto_w(q.proto)))) != 0u;
 }
 
+// The lanes whose rule matches a packet, as a wave mask: one ballot per field
+// test (each compare already yields a lane mask), ANDed in scalar registers,
+// so the vector work is the tests alone.
+__device__ __forceinline__ uint64_t full_match_mask(const RuleRec& q, uint32_t src, uint32_t dst,
+                                                    uint32_t pp, uint32_t pr) {
+    return ballot(in_range(dst, q.dst_lo, q.dst_w)) & ballot(in_range(src, q.src_lo, q.src_w)) &
+           ballot(ports_in(pp, q.port_lo, q.port_w)) &
+           ballot(in_range(pr, proto_lo(q.proto), proto_w(q.proto)));
+}
+
 // Function-parallel scan (paper Section IV-B): every firewall node holds a
 // part of the policy and sees every packet.  A node here is a wave holding
 // partition p, the rules [p*S, min(R, (p+1)*S)); its 64 lanes take 64 of them
 // at a time into registers, and kRsPackets packets at a time are broadcast to
 // all lanes through scalar registers, so each vector test checks one packet
 // against 64 rules.  A packet is finished in this partition at the first
-// 64-rule chunk where any lane matches; the partition's first match is the
-// wave minimum (DPP) of the lanes' matches, and the partitions meet through
-// atomicMin on the 32-bit index (0xFFFFFFFF = none).
+// 64-rule chunk where any lane matches; the rules sit in lane order, so the
+// lowest lane of the match ballot is the partition's first match (a
+// wave-uniform value, no per-lane bookkeeping), and the partitions meet
+// through atomicMin on the 32-bit index (0xFFFFFFFF = none).
 constexpr uint32_t kRsPackets = 8;
 
 __global__ __launch_bounds__(kScanBlock) void k_rule_split(const RuleRec* __restrict__ rules,
@@ -102,27 +113,29 @@ __global__ __launch_bounds__(kScanBlock) void k_rule_split(const RuleRec* __rest
         if (p0 + g >= n) done |= 1u << g;
     }
     const uint32_t all = (1u << kRsPackets) - 1u;
-    uint32_t best[kRsPackets];
+    uint32_t first[kRsPackets];   // wave-uniform: this partition's first match per packet
 #pragma unroll
-    for (uint32_t g = 0; g < kRsPackets; ++g) best[g] = kNoMatch;
+    for (uint32_t g = 0; g < kRsPackets; ++g) first[g] = kNoMatch;
 
     for (uint32_t k = begin; k < end && done != all; k += 64u) {
         const uint32_t r = k + lane;
         const bool ok = r < end;
         const RuleRec q = rules[ok ? r : begin];
+        const uint64_t in_part = ballot(ok);
 #pragma unroll
         for (uint32_t g = 0; g < kRsPackets; ++g) {
             if ((done >> g) & 1u) continue;  // wave-uniform
-            const bool m = (unsigned(ok) & unsigned(full_match(q, src[g], dst[g], pp[g], pr[g]))) != 0u;
-            if (m) best[g] = r;              // at most one chunk per packet matches
-            if (ballot(m) != 0) done |= 1u << g;
+            const uint64_t mb = full_match_mask(q, src[g], dst[g], pp[g], pr[g]) & in_part;
+            if (mb != 0) {                   // at most one chunk per packet matches
+                first[g] = k + uint32_t(__builtin_ctzll(mb));
+                done |= 1u << g;
+            }
         }
     }
+    if (lane == 0) {
 #pragma unroll
-    for (uint32_t g = 0; g < kRsPackets; ++g) {
-        if (p0 + g >= n) break;
-        const uint32_t m = wave_min(best[g]);
-        if (lane == 0 && m != kNoMatch) atomicMin(idx + p0 + g, m);
+        for (uint32_t g = 0; g < kRsPackets; ++g)
+            if (first[g] != kNoMatch) atomicMin(idx + p0 + g, first[g]);
     }
 }
 
