@@ -112,10 +112,11 @@ typedef struct fw_classify_opts {
     void *stream;           /* hipStream_t to enqueue on; NULL = null stream */
     uint32_t lookup;        /* learned mode: 0 = network + error window (default),
                                1 = full binary search with the network skipped */
-    uint32_t packets_per_lane; /* packet split and learned mode: 1, 2 or 4; 0 = library
-                                  default: the most (up to 4 for packet split, 2 for learned)
-                                  that still gives the launch 8,192 waves, so small batches
-                                  use fewer per lane */
+    uint32_t packets_per_lane; /* packet split, learned and hybrid mode: 1, 2 or 4 (rule
+                                  split ignores it); 0 = library default: the most (up to 4
+                                  for packet split, 2 for learned) that still gives the
+                                  launch 8,192 waves, so small batches use fewer per lane;
+                                  hybrid: 4 from 2,097,152 packets up, else 1 */
     uint64_t *window_misses;   /* learned mode, optional HOST pointer: when given the call
                                   waits for its work and stores how many packets' error
                                   window missed (they fell back to a full search) */

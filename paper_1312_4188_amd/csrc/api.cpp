@@ -105,6 +105,13 @@ static uint32_t default_packets_per_lane(size_t n, uint32_t most) {
     return k;
 }
 
+// Hybrid default: four packets per lane once a batch fills 8,192 waves with
+// them (measured fastest on large batches; two measured slower than one), one
+// below that, where the batch's latency matters more.
+static uint32_t hybrid_packets_per_lane(size_t n) {
+    return n >= size_t(8192) * 64u * 4u ? 4u : 1u;
+}
+
 // A device fault in earlier asynchronous work is sticky; report it before new work.
 static fw_status check_device_state() {
     const hipError_t e = hipGetLastError();
@@ -234,7 +241,10 @@ fw_status fw_classify_ex(const fw_ruleset* rs, const fw_packets* pk, size_t n,
             break;
         case FW_MODE_HYBRID:
             e = launch_hybrid(rs->d_pairs, rs->d_rules, reachable, P, pd, n, out_rule_idx,
-                              out_action, rs->default_action, stream);
+                              out_action, rs->default_action,
+                              o.packets_per_lane ? int(o.packets_per_lane)
+                                                 : int(hybrid_packets_per_lane(n)),
+                              stream);
             break;
         case FW_MODE_LEARNED:
             return classify_learned(rs->index, rs->default_action, pd, n, out_rule_idx,

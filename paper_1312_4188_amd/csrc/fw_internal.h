@@ -84,6 +84,6 @@ hipError_t launch_rule_split(const RuleRec* rules, uint32_t n_rules, uint32_t pa
 hipError_t launch_hybrid(const uint2* pairs, const RuleRec* rules, uint32_t n_rules,
                          uint32_t partitions,
                          PacketsDev pk, size_t n, int32_t* out_idx, uint8_t* out_act,
-                         uint8_t default_action, hipStream_t stream);
+                         uint8_t default_action, int packets_per_lane, hipStream_t stream);
 
 }  // namespace fw

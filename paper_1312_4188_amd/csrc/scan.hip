@@ -155,27 +155,31 @@ __global__ void k_apply_action(const RuleRec* __restrict__ rules, const int32_t*
 }
 
 // ------------------------------------------------------------------ hybrid
-// One work-group per 64 packets (paper Section IV-C: a block per packet, its
-// threads splitting the rules; here a lane per packet and a wave per rule
+// One work-group per 64 K packets (paper Section IV-C: a block per packet, its
+// threads splitting the rules; here K packets per lane and a wave per rule
 // partition).  Wave w scans partition w with the packet-split wave scan, in
 // chunks of kHybridChunk rules; after each chunk its lanes' first matches go
-// into LDS through atomicMin, and lanes that another wave has already beaten
+// into LDS through atomicMin, and packets that another wave has already beaten
 // (an LDS minimum below the next rule index) drop out.
 constexpr uint32_t kHybridChunk = 64;
 
+template <int K>
 __global__ __launch_bounds__(1024) void k_hybrid(const uint2* __restrict__ pairs,
                                                  const RuleRec* __restrict__ rules,
                                                  uint32_t n_rules, uint32_t S, PacketsDev pk,
                                                  size_t n, int32_t* __restrict__ out_idx,
                                                  uint8_t* __restrict__ out_act, uint32_t dflt) {
-    __shared__ uint32_t smin[64];
+    __shared__ uint32_t smin[64 * K];   // packet first + K * lane + s at K * lane + s
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t w = wave_in_group();
-    const size_t first = size_t(blockIdx.x) * 64u;
-    if (w == 0) smin[lane] = kNoMatch;
+    const size_t first = size_t(blockIdx.x) * 64u * K;
+    if (w == 0) {
+#pragma unroll
+        for (int s = 0; s < K; ++s) smin[K * lane + s] = kNoMatch;
+    }
     __syncthreads();
 
-    WaveScan<1> ws;
+    WaveScan<K> ws;
     ws.init(pk, first, n, dflt);
     const uint64_t r0 = uint64_t(w) * S;
     const uint32_t begin = uint32_t(r0 < n_rules ? r0 : n_rules);
@@ -183,17 +187,27 @@ __global__ __launch_bounds__(1024) void k_hybrid(const uint2* __restrict__ pairs
     for (uint32_t c = begin; c < end && ws.any_live(); c += kHybridChunk) {
         const uint32_t cnt = min(kHybridChunk, end - c);
         ws.template scan<FirstField::Dst>(pairs + c, rules + c, cnt, c);
-        if (ws.best[0] != kNoMatch) atomicMin(&smin[lane], ws.best[0]);
-        const uint32_t cur = *reinterpret_cast<volatile uint32_t*>(&smin[lane]);
-        ws.live[0] &= ballot(cur > c + cnt);
-        ws.live_any = ws.live[0];
+        uint64_t live_any = 0;
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            if (ws.best[s] != kNoMatch) atomicMin(&smin[K * lane + s], ws.best[s]);
+            const uint32_t cur = *reinterpret_cast<volatile uint32_t*>(&smin[K * lane + s]);
+            ws.live[s] &= ballot(cur > c + cnt);
+            live_any |= ws.live[s];
+        }
+        ws.live_any = live_any;
     }
     __syncthreads();
-    const size_t i = first + lane;
-    if (w == 0 && i < n) {
-        const uint32_t b = smin[lane];
-        out_idx[i] = int32_t(b);
-        out_act[i] = uint8_t(b == kNoMatch ? dflt : rule_action(rules[b].proto));
+    if (w == 0) {
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            const size_t i = first + K * lane + s;
+            if (i < n) {
+                const uint32_t b = smin[K * lane + s];
+                out_idx[i] = int32_t(b);
+                out_act[i] = uint8_t(b == kNoMatch ? dflt : rule_action(rules[b].proto));
+            }
+        }
     }
 }
 
@@ -299,14 +313,24 @@ hipError_t launch_rule_split(const RuleRec* rules, uint32_t n_rules, uint32_t P,
 hipError_t launch_hybrid(const uint2* pairs, const RuleRec* rules, uint32_t n_rules, uint32_t P,
                          PacketsDev pk,
                          size_t n, int32_t* out_idx, uint8_t* out_act, uint8_t default_action,
-                         hipStream_t stream) {
+                         int packets_per_lane, hipStream_t stream) {
     if (n == 0) return hipSuccess;
     const uint32_t S = n_rules == 0 ? 1u : ceil_div(n_rules, P);
-    // a work-group of 64*P lanes per 64 packets
-    return in_chunks(n, chunk_packets(double(P)), [&](size_t o, size_t c) {
-        hipLaunchKernelGGL(k_hybrid, dim3(ceil_div(c, 64)), dim3(64 * P), 0, stream, pairs,
-                           rules, n_rules, S, advance(pk, o), c, out_idx + o, out_act + o,
-                           uint32_t(default_action));
+    const uint32_t K = uint32_t(packets_per_lane);
+    // a work-group of 64*P lanes per 64*K packets
+    return in_chunks(n, chunk_packets(double(P) / K), [&](size_t o, size_t c) {
+        const dim3 grid(ceil_div(c, 64u * K)), block(64 * P);
+        const PacketsDev q = advance(pk, o);
+        const uint32_t d = uint32_t(default_action);
+        if (K == 4)
+            hipLaunchKernelGGL(k_hybrid<4>, grid, block, 0, stream, pairs, rules, n_rules, S, q,
+                               c, out_idx + o, out_act + o, d);
+        else if (K == 2)
+            hipLaunchKernelGGL(k_hybrid<2>, grid, block, 0, stream, pairs, rules, n_rules, S, q,
+                               c, out_idx + o, out_act + o, d);
+        else
+            hipLaunchKernelGGL(k_hybrid<1>, grid, block, 0, stream, pairs, rules, n_rules, S, q,
+                               c, out_idx + o, out_act + o, d);
         return hipGetLastError();
     });
 }

@@ -26,6 +26,8 @@ SCAN_MODES = [
     dict(mode="rule_split", partitions=100),
     dict(mode="hybrid", partitions=4),
     dict(mode="hybrid", partitions=16),
+    dict(mode="hybrid", partitions=4, packets_per_lane=2),
+    dict(mode="hybrid", partitions=16, packets_per_lane=4),
 ]
 
 
@@ -105,8 +107,8 @@ def test_rule_split_short_partitions_share_waves():
 
 
 def test_hybrid_launch_chunks():
-    """Hybrid with 16 partitions takes 16 work-items per packet, so one launch covers
-    268,435,392 packets; a batch just above that runs in two launches.  The batch tiles
+    """Hybrid with 16 partitions and one packet per lane takes 16 work-items per packet, so one
+    launch covers 268,435,392 packets; a batch just above that runs in two launches.  The batch tiles
     1,048,576 distinct packets, so every output is checked against the oracle's answer for
     its tile position."""
     import torch
@@ -122,7 +124,7 @@ def test_hybrid_launch_chunks():
                                                           small.proto)))
     say(f"hybrid P=16 over {n} packets (two launches)")
     with fw.Ruleset(rules) as rs:
-        idx, act = rs.classify(dp, mode="hybrid", partitions=16)
+        idx, act = rs.classify(dp, mode="hybrid", partitions=16, packets_per_lane=1)
         torch.cuda.synchronize()
     wi = torch.from_numpy(want_idx).cuda().repeat(reps)[:n]
     wa = torch.from_numpy(want_act).cuda().repeat(reps)[:n]
