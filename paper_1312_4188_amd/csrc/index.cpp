@@ -498,10 +498,31 @@ std::vector<uint8_t> lds_image(const LearnedIndex* ix, const std::vector<float>&
     return img;
 }
 
+// Pair dword of a stage-2 hidden unit: w1's bf16 bits in the low half, and a
+// high half chosen so that the whole dword read as fp32, which the lookup
+// takes as the unit's bias, is the nearest such value to b1.  The low bits add
+// less than one bf16 step to the magnitude of the high half's value, so the
+// candidates are b1's own pattern and the one a step toward zero; the bias
+// applied is then within half a bf16 step of b1.
+uint32_t pair_dword(uint16_t w1, uint16_t b1) {
+    const float want = from_bf16(b1);
+    auto as_float = [](uint32_t u) {
+        float f;
+        std::memcpy(&f, &u, 4);
+        return f;
+    };
+    uint32_t best = (uint32_t(b1) << 16) | w1;
+    if ((b1 & 0x7FFFu) != 0) {   // a step toward zero exists (b1 is not a zero)
+        const uint32_t alt = (uint32_t(b1 - 1u) << 16) | w1;
+        if (std::fabs(as_float(alt) - want) < std::fabs(as_float(best) - want)) best = alt;
+    }
+    return best;
+}
+
 // Stage-2 rows (see kRowDwords) from bf16 networks in 32-slot segments
-// [w1][b1][w2][b2]: dword k = (w1[k], b1[k]), w1 in the low half; w2[k] and
-// b2 widened to fp32 (a bf16 value is the top half of its fp32 pattern); the
-// expert's key_lo, inv_span and pos_span beside the bias.
+// [w1][b1][w2][b2]: dword k = pair_dword(w1[k], b1[k]); w2[k] and b2 widened
+// to fp32 (a bf16 value is the top half of its fp32 pattern); the expert's
+// key_lo, inv_span and pos_span beside the bias.
 std::vector<uint32_t> stage2_rows(const std::vector<uint16_t>& seg, uint32_t E,
                                   const std::vector<ExpertMeta>& meta) {
     std::vector<uint32_t> out(size_t(E) * kRowDwords, 0);
@@ -509,7 +530,7 @@ std::vector<uint32_t> stage2_rows(const std::vector<uint16_t>& seg, uint32_t E,
         const uint16_t* r = seg.data() + size_t(e) * kInferStride;
         uint32_t* o = out.data() + size_t(e) * kRowDwords;
         for (uint32_t k = 0; k < 32; ++k) {
-            o[kRowPairs + k] = uint32_t(r[k]) | (uint32_t(r[32 + k]) << 16);
+            o[kRowPairs + k] = pair_dword(r[k], r[32 + k]);
             o[kRowOut + k] = uint32_t(r[64 + k]) << 16;
         }
         o[kRowBias] = uint32_t(r[96]) << 16;

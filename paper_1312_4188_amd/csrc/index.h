@@ -50,14 +50,15 @@ constexpr uint32_t kNoExpert = 0xFFFFFFFFu;
 // Inference layout of one stage-1 network (fp32): [w1][b1][w2][b2] in
 // 32-slot segments, padded to 104 entries (a multiple of 8); hidden units past
 // H are zero.  A stage-2 row (kRowDwords dwords) holds one expert: dword k
-// is the bf16 pair (w1[k], b1[k]) (w1 in the low half), dwords 32 + k hold
+// pairs w1[k] (bf16, low half) with b1[k] (the whole dword read as fp32, its
+// high half b1's bf16 pattern or the one next to it), dwords 32 + k hold
 // w2[k] and dword 64 holds b2, both as fp32 (bf16 values widened, exact);
 // dwords 65..67 carry the expert's input scaling (key_lo, inv_span) and
 // pos_span, read with the bias in one 16-byte load.  Rows of all-fp32 weights
 // would not fit the LDS budget of the lookup at 10,000 rules; fp32 w2 saves
 // the lookup one widening per unit.
 constexpr uint32_t kInferStride = 104;
-constexpr uint32_t kRowPairs = 0;     // dword of (w1[0], b1[0]) in a stage-2 row
+constexpr uint32_t kRowPairs = 0;     // pair dword of hidden unit 0 in a stage-2 row
 constexpr uint32_t kRowOut = 32;      // dword of w2[0]
 constexpr uint32_t kRowBias = 64;     // dword of b2
 constexpr uint32_t kRowKeyLo = 65;    // ExpertMeta::key_lo

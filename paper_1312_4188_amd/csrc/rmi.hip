@@ -188,7 +188,7 @@ __global__ void k_fill(uint32_t* p, size_t n, uint32_t v) {
 
 // ------------------------------------------------------------------ inference
 // Stage 1 is kept as fp32 (the bf16 values widened) in four 32-slot segments
-// [w1][b1][w2][b2]; stage 2 as rows of bf16 (w1, b1) pairs and widened w2, b2
+// [w1][b1][w2][b2]; stage 2 as rows of (w1, b1) pair dwords and widened w2, b2
 // (see kRowDwords).  Hidden units past H carry zero weights and add nothing.
 // Every routine below is shared by the error-bound kernel and the lookup
 // kernels, so the recorded error bounds describe exactly the lookup's
@@ -235,10 +235,11 @@ __device__ __forceinline__ uint32_t route(const float* w1, uint32_t E, uint32_t 
 
 // Stage 2: position estimate of x inside expert e's range of positions (the
 // row carries the expert's input scaling and position span; pos_lo is its
-// first position).  Hidden unit k widens its bf16 pair (w1, b1) with one
-// shift and one mask (exact), forms fp32 max(w1 v + b1, 0) as one clamped
-// multiply-add, and adds its fp32 w2 share with a second: four instructions
-// per unit.
+// first position).  Hidden unit k takes w1 from the low half of its pair
+// dword with one shift (exact) and its bias as the whole dword read as fp32
+// (the index build picks the high half for it), forms fp32 max(w1 v + b1, 0)
+// as one clamped multiply-add, and adds its fp32 w2 share with a second:
+// three instructions per unit.
 __device__ __forceinline__ int32_t position(const uint32_t* row, int32_t pos_lo, uint32_t x) {
     const uint32_t key_lo = row[kRowKeyLo];
     const float inv_span = __uint_as_float(row[kRowInvSpan]);
@@ -254,7 +255,7 @@ __device__ __forceinline__ int32_t position(const uint32_t* row, int32_t pos_lo,
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const float w1 = __uint_as_float(pr[i] << 16);
-            const float b1 = __uint_as_float(pr[i] & 0xFFFF0000u);
+            const float b1 = __uint_as_float(pr[i]);
             y = fmaf(op[i], relu01(fmaf(w1, v, b1)), y);
         }
     }
