@@ -529,48 +529,54 @@ __global__ __launch_bounds__(kLearnedBlock, K >= 4 ? 4 : 8) void k_learned(Looku
         // record loads are in flight at once; a wave runs as many rounds as
         // its longest list needs, so the short source lists drop out of the
         // rounds once every lane is done with them.
+        // The list cursors are byte offsets of the next record, or kPastEnd
+        // (beyond every list end) once the list is done, so the cursor is the
+        // load offset itself and the test "entries left" is cursor < end.
         const __amdgpu_buffer_rsrc_t rl = list_rsrc(a.L, a.nL);
         const __amdgpu_buffer_rsrc_t rs_ = list_rsrc(a.S, a.nS);
+        constexpr uint32_t kRec = uint32_t(sizeof(RuleRec));
         uint32_t lk[K], le[K], sk[K], se[K];
 #pragma unroll
         for (int s = 0; s < K; ++s) {   // plain loads, all issued before the first use
             const uint32_t l0 = v.off[jj[s]], l1 = v.off[jj[s] + 1u];
             const uint32_t s0 = v.soff[si[s]], s1 = v.soff[si[s] + 1u];
             const bool valid = w.p0 + s < n;
-            lk[s] = l0;
-            le[s] = valid ? l1 : l0;
-            sk[s] = s0;
-            se[s] = valid ? s1 : s0;
+            lk[s] = valid && l0 < l1 ? l0 * kRec : kPastEnd;
+            le[s] = l1 * kRec;
+            sk[s] = valid && s0 < s1 ? s0 * kRec : kPastEnd;
+            se[s] = s1 * kRec;
         }
         // One entry of a packet's destination-interval list: the record's
         // source, port and protocol tests (its destination test is implied by
-        // the list).  Straight-line selects, no branches, so no load is sunk
-        // into a conditional block behind another's wait.
+        // the list).  The list advances while its entries still beat the best
+        // so far and do not match; otherwise it stops.  Straight-line selects,
+        // no branches, so no load is sunk into a conditional block behind
+        // another's wait.
         auto step_dst = [&](int s, const RuleRec& q) {
-            const bool on = lk[s] < le[s];
-            const bool beats = q.idx < lbest[s];
-            const bool m = (unsigned(on) & unsigned(beats) &
-                            unsigned(in_range(w.src[s], q.src_lo, q.src_w)) &
+            const bool live = (unsigned(lk[s] < le[s]) & unsigned(q.idx < lbest[s])) != 0u;
+            const bool t = (unsigned(in_range(w.src[s], q.src_lo, q.src_w)) &
                             unsigned(ports_in(w.pp[s], q.port_lo, q.port_w)) &
                             unsigned(in_range(w.pr[s], proto_lo(q.proto), proto_w(q.proto)))) != 0u;
+            const bool m = live && t;
             lbest[s] = m ? q.idx : lbest[s];
             lact[s] = m ? rule_action(q.proto) : lact[s];
-            lk[s] = on ? ((m | !beats) ? le[s] : lk[s] + 1u) : lk[s];
+            const uint32_t next = lk[s] + kRec;
+            lk[s] = live && !t && next < le[s] ? next : kPastEnd;
         };
         // One entry of its source-interval list (source test implied as well).
         auto step_src = [&](int s, const RuleRec& q) {
-            const bool on = sk[s] < se[s];
-            const bool beats = q.idx < lbest[s];
-            const bool m = (unsigned(on) & unsigned(beats) &
-                            unsigned(ports_in(w.pp[s], q.port_lo, q.port_w)) &
+            const bool live = (unsigned(sk[s] < se[s]) & unsigned(q.idx < lbest[s])) != 0u;
+            const bool t = (unsigned(ports_in(w.pp[s], q.port_lo, q.port_w)) &
                             unsigned(in_range(w.pr[s], proto_lo(q.proto), proto_w(q.proto)))) != 0u;
+            const bool m = live && t;
             lbest[s] = m ? q.idx : lbest[s];
             lact[s] = m ? rule_action(q.proto) : lact[s];
-            sk[s] = on ? ((m | !beats) ? se[s] : sk[s] + 1u) : sk[s];
+            const uint32_t next = sk[s] + kRec;
+            sk[s] = live && !t && next < se[s] ? next : kPastEnd;
         };
-        // Buffer loads: a lane whose list is exhausted passes an offset past
-        // the end of the array, so its load returns zeros without a memory
-        // access, and no branch separates the loads.
+        // Buffer loads: a finished list loads at kPastEnd, out of the
+        // buffer's range, so the load returns zeros without a memory access,
+        // and no branch separates the loads.
         // Phase 1, while any lane has a source-interval entry left (those
         // lists are short): both lists of every packet advance each round.
         for (;;) {
@@ -581,9 +587,8 @@ __global__ __launch_bounds__(kLearnedBlock, K >= 4 ? 4 : 8) void k_learned(Looku
             RuleRec ql[K], qs[K];
 #pragma unroll
             for (int s = 0; s < K; ++s) {
-                ql[s] = list_record(rl, lk[s] < le[s] ? lk[s] * uint32_t(sizeof(RuleRec)) : kPastEnd);
-                qs[s] = list_record_tail(rs_, sk[s] < se[s] ? sk[s] * uint32_t(sizeof(RuleRec))
-                                                            : kPastEnd);
+                ql[s] = list_record(rl, lk[s]);
+                qs[s] = list_record_tail(rs_, sk[s]);
             }
 #pragma unroll
             for (int s = 0; s < K; ++s) {
@@ -600,8 +605,7 @@ __global__ __launch_bounds__(kLearnedBlock, K >= 4 ? 4 : 8) void k_learned(Looku
             if (ballot(more) == 0) break;
             RuleRec ql[K];
 #pragma unroll
-            for (int s = 0; s < K; ++s)
-                ql[s] = list_record(rl, lk[s] < le[s] ? lk[s] * uint32_t(sizeof(RuleRec)) : kPastEnd);
+            for (int s = 0; s < K; ++s) ql[s] = list_record(rl, lk[s]);
 #pragma unroll
             for (int s = 0; s < K; ++s) step_dst(s, ql[s]);
         }
