@@ -92,24 +92,26 @@ def test_learned_classify_matches_oracle(wl, seed):
             assert miss == 0
 
 
-def test_learned_10000_rules_sampled():
-    """10,000 skewed rules x 16,777,216 packets; the full batch runs, a sample is checked."""
+@pytest.mark.parametrize("seed", [1, 2, 3, 4, 5])
+def test_learned_10000_rules_sampled(seed):
+    """10,000 skewed rules x 16,777,216 packets, seeds 1-5; the full batch runs, a sample is
+    checked against the oracle and the whole batch against the packet-split scan."""
     import torch
     fw = fwmod()
-    rules, pk = gen.workload("learned_10000x16M", seed=1)
+    rules, pk = gen.workload("learned_10000x16M", seed=seed)
     rng = np.random.Generator(np.random.PCG64(9))
     sample = np.sort(rng.choice(len(pk), 40_000, replace=False))
     want = oracle.classify(rules, pk.subset(sample), threads=16)
     dp = fw.DevicePackets.from_host(pk)
     with fw.Ruleset(rules) as rs:
-        say("learned 10000x16M build")
+        say(f"learned 10000x16M seed={seed} build")
         st = rs.build_learned_index()
         say(f"  stats {st}")
         for lookup in (0, 1):
             idx, act, miss = rs.classify(dp, mode="learned", lookup=lookup, count_misses=True)
             torch.cuda.synchronize()
             got = (idx.cpu().numpy()[sample], act.cpu().numpy()[sample])
-            assert_same(got, want, f"learned 10000x16M lookup {lookup}")
+            assert_same(got, want, f"learned 10000x16M seed {seed} lookup {lookup}")
             say(f"  lookup {lookup}: window misses {miss} of {len(pk)}")
         # the scan agrees on the whole batch
         si, sa = rs.classify(dp, mode="packet_split")

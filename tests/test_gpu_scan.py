@@ -56,12 +56,13 @@ def test_small_config_all_modes(seed, kw):
 @pytest.mark.parametrize("kw", [dict(mode="packet_split"), dict(mode="rule_split", partitions=16),
                                 dict(mode="rule_split", partitions=1000),
                                 dict(mode="hybrid", partitions=8)], ids=_id)
-def test_1000_rules_full_batch(kw):
-    """1,000 rules x 1,048,576 packets, every packet against the oracle."""
-    say(f"scan_1000x1M {kw}")
-    rules, pk = gen.workload("scan_1000x1M", seed=1)
+@pytest.mark.parametrize("seed", [1, 2, 3, 4, 5])
+def test_1000_rules_full_batch(seed, kw):
+    """1,000 rules x 1,048,576 packets, seeds 1-5, every packet against the oracle."""
+    say(f"scan_1000x1M seed={seed} {kw}")
+    rules, pk = gen.workload("scan_1000x1M", seed=seed)
     want = oracle.classify(rules, pk, threads=16)
-    assert_same(classify_np(rules, pk, **kw), want, f"1000x1M {kw}")
+    assert_same(classify_np(rules, pk, **kw), want, f"1000x1M seed {seed} {kw}")
 
 
 def test_rule_split_launch_chunks():
@@ -204,22 +205,25 @@ def test_boundary_packets(wild):
             assert_same((idx.cpu().numpy(), act.cpu().numpy()), want, f"boundary learned K={ppl}")
 
 
-def test_10000_rules_16M_packets_sampled():
-    """10,000 skewed rules x 16,777,216 packets, packet split and rule split; a sample vs the oracle."""
+@pytest.mark.parametrize("seed", [1, 2, 3, 4, 5])
+def test_10000_rules_16M_packets_sampled(seed):
+    """10,000 skewed rules x 16,777,216 packets, seeds 1-5: packet split, rule split and hybrid;
+    a sample vs the oracle."""
     import torch
     fw = fwmod()
-    rules, pk = gen.workload("learned_10000x16M", seed=1)
+    rules, pk = gen.workload("learned_10000x16M", seed=seed)
     rng = np.random.Generator(np.random.PCG64(5))
     sample = np.sort(rng.choice(len(pk), 40_000, replace=False))
     want = oracle.classify(rules, pk.subset(sample), threads=16)
     dp = fw.DevicePackets.from_host(pk)
     with fw.Ruleset(rules) as rs:
-        for kw in (dict(mode="packet_split"), dict(mode="rule_split", partitions=16)):
-            say(f"10000x16M {kw}")
+        for kw in (dict(mode="packet_split"), dict(mode="rule_split", partitions=16),
+                   dict(mode="hybrid", partitions=16)):
+            say(f"10000x16M seed={seed} {kw}")
             idx, act = rs.classify(dp, **kw)
             torch.cuda.synchronize()
             got = (idx.cpu().numpy()[sample], act.cpu().numpy()[sample])
-            assert_same(got, want, f"10000x16M {kw}")
+            assert_same(got, want, f"10000x16M seed {seed} {kw}")
             # every index is -1 or a real rule, and actions agree with the rule table
             ia = idx.cpu().numpy()
             assert ia.min() >= -1 and ia.max() < len(rules)
