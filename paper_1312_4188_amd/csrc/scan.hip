@@ -80,6 +80,13 @@ __device__ __forceinline__ uint64_t full_match_mask(const RuleRec& q, uint32_t s
 // lowest lane of the match ballot is the partition's first match (a
 // wave-uniform value, no per-lane bookkeeping), and the partitions meet
 // through atomicMin on the 32-bit index (0xFFFFFFFF = none).
+// Waves are numbered partition-major (all packet groups of partition 0, then
+// of partition 1, ...), so on a large batch a wave of partition p starts after
+// the lower partitions of its packets have finished.  It reads their merged
+// index first and skips every packet already matched below its own first rule
+// (the pruning across partitions): the index only decreases, so any value
+// read bounds the final one from above, and a packet whose value lies below
+// the partition start cannot take a rule of it.
 constexpr uint32_t kRsPackets = 8;
 
 __global__ __launch_bounds__(kScanBlock) void k_rule_split(const RuleRec* __restrict__ rules,
@@ -88,29 +95,35 @@ __global__ __launch_bounds__(kScanBlock) void k_rule_split(const RuleRec* __rest
                                                           uint32_t* __restrict__ idx) {
     const uint32_t lane = threadIdx.x & 63u;
     const size_t wave = size_t(blockIdx.x) * (kScanBlock / 64) + wave_in_group();
-    const uint32_t part = uint32_t(wave % P);
-    const size_t p0 = (wave / P) * kRsPackets;
-    if (p0 >= n) return;  // wave-uniform
+    const size_t groups = (n + kRsPackets - 1) / kRsPackets;
+    const size_t part_sz = wave / groups;
+    if (part_sz >= P) return;  // wave-uniform: past the last partition
+    const uint32_t part = uint32_t(part_sz);
+    const size_t p0 = (wave % groups) * kRsPackets;
     const uint64_t b64 = uint64_t(part) * S;
     const uint32_t begin = uint32_t(b64 < n_rules ? b64 : n_rules);
     const uint32_t end = uint32_t(b64 + S < n_rules ? b64 + S : n_rules);
     if (begin >= end) return;  // empty partition
 
-    // the packets, one per lane, then broadcast one at a time
+    // the packets, one per lane, then broadcast one at a time; with them the
+    // index merged so far (a device-scope load, past the compute unit's cache)
     const size_t mine = p0 + (lane < kRsPackets ? lane : 0u);
     const bool have = lane < kRsPackets && mine < n;
     const uint32_t v_src = have ? pk.src[mine] : 0u, v_dst = have ? pk.dst[mine] : 0u;
     const uint32_t v_pp = have ? ((uint32_t(pk.sport[mine]) << 16) | pk.dport[mine]) : 0u;
     const uint32_t v_pr = have ? uint32_t(pk.proto[mine]) : 0u;
+    const uint32_t v_cur = have ? __hip_atomic_load(idx + mine, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT)
+                                : 0u;
     uint32_t src[kRsPackets], dst[kRsPackets], pp[kRsPackets], pr[kRsPackets];
-    uint32_t done = 0;
+    // done: packets past the batch end, and packets already matched below begin
+    uint32_t done = uint32_t(ballot(!have || v_cur < begin)) & ((1u << kRsPackets) - 1u);
 #pragma unroll
     for (uint32_t g = 0; g < kRsPackets; ++g) {
         src[g] = __builtin_amdgcn_readlane(int(v_src), int(g));
         dst[g] = __builtin_amdgcn_readlane(int(v_dst), int(g));
         pp[g] = __builtin_amdgcn_readlane(int(v_pp), int(g));
         pr[g] = __builtin_amdgcn_readlane(int(v_pr), int(g));
-        if (p0 + g >= n) done |= 1u << g;
     }
     const uint32_t all = (1u << kRsPackets) - 1u;
     uint32_t first[kRsPackets];   // wave-uniform: this partition's first match per packet
@@ -297,7 +310,7 @@ hipError_t launch_rule_split(const RuleRec* rules, uint32_t n_rules, uint32_t P,
         const uint32_t S0 = ceil_div(n_rules, P);
         const uint32_t S = S0 >= 64u ? S0 : S0 * ceil_div(64u, S0);
         P = ceil_div(n_rules, S);
-        // P waves of 64 lanes per kRsPackets packets
+        // P waves of 64 lanes per kRsPackets packets, numbered partition-major
         e = in_chunks(n, chunk_packets(64.0 * P / kRsPackets), [&](size_t o, size_t c) {
             const uint64_t waves = uint64_t(P) * ((c + kRsPackets - 1) / kRsPackets);
             const uint64_t blocks = (waves + (kScanBlock / 64) - 1) / (kScanBlock / 64);
