@@ -35,8 +35,6 @@ __device__ __forceinline__ uint32_t proto_lo(uint32_t p) { return p & 0xFFu; }
 __device__ __forceinline__ uint32_t proto_w(uint32_t p) { return (p >> 8) & 0xFFu; }
 __device__ __forceinline__ uint32_t rule_action(uint32_t p) { return (p >> 16) & 1u; }
 
-__device__ __forceinline__ uint32_t umin(uint32_t a, uint32_t b) { return a < b ? a : b; }
-
 // Source, port and protocol tests (the destination test is implied by a candidate list).
 __device__ __forceinline__ bool match_no_dst(const RuleRec& q, uint32_t src, uint32_t pp,
                                              uint32_t pr) {

@@ -37,29 +37,6 @@ __global__ __launch_bounds__(kScanBlock) void k_packet_split(ScanPlan plan, Pack
 }
 
 // ------------------------------------------------------------------ rule split
-// Minimum over the 64 lanes of a wave, with DPP lane permutations (quad
-// swaps, half-row and row mirrors), one swizzle across the two rows of each
-// 32-lane half and a readlane pair across the halves; every lane receives it.
-// Must be called with the whole wave active.
-__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
-    v = umin(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0xB1, 0xF, 0xF, false)));   // quad_perm [1,0,3,2]
-    v = umin(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x4E, 0xF, 0xF, false)));   // quad_perm [2,3,0,1]
-    v = umin(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x141, 0xF, 0xF, false)));  // row_half_mirror
-    v = umin(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x140, 0xF, 0xF, false)));  // row_mirror
-    v = umin(v, uint32_t(__builtin_amdgcn_ds_swizzle(int(v), 0x401F)));                     // lane ^ 16
-    return umin(uint32_t(__builtin_amdgcn_readlane(int(v), 0)),
-                uint32_t(__builtin_amdgcn_readlane(int(v), 32)));
-}
-
-// All five tests without short-circuit branches: each compare yields a lane
-// mask and the masks are combined, so the lanes never diverge.
-__device__ __forceinline__ bool full_match(const RuleRec& q, uint32_t src, uint32_t dst,
-                                           uint32_t pp, uint32_t pr) {
-    return (unsigned(in_range(dst, q.dst_lo, q.dst_w)) & unsigned(in_range(src, q.src_lo, q.src_w)) &
-            unsigned(ports_in(pp, q.port_lo, q.port_w)) &
-            unsigned(in_range(pr, proto_lo(q.proto), proto_w(q.proto)))) != 0u;
-}
-
 // The lanes whose rule matches a packet, as a wave mask: one ballot per field
 // test (each compare already yields a lane mask), ANDed in scalar registers,
 // so the vector work is the tests alone.
