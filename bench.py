@@ -369,8 +369,21 @@ def multichain_leg(seed: int, steps: int, log_fn):
     return out
 
 
-def cpu_baseline(rules, pk, n_sample: int):
-    """The CPU oracle, as it stands, on a bounded sample of the same batch."""
+def host_cpu_model() -> str:
+    """The host's CPU model name, as the kernel reports it."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(rules, pk, n_sample: int, n_single: int = 1_048_576):
+    """The CPU oracle, as it stands, on a bounded sample of the same batch: with up to 16
+    worker threads (the headline figure), and on one core over a smaller sample."""
     import oracle
     threads = max(1, min(16, os.cpu_count() or 1))
     n_sample = min(n_sample, len(pk))
@@ -378,9 +391,16 @@ def cpu_baseline(rules, pk, n_sample: int):
     t0, c0 = time.perf_counter(), time.process_time()
     oracle.classify(rules, sub, threads=threads)
     dt, cpu = time.perf_counter() - t0, time.process_time() - c0
+    n_single = min(n_single, len(pk))
+    t1 = time.perf_counter()
+    oracle.classify(rules, pk.subset(slice(0, n_single)), threads=1)
+    dt1 = time.perf_counter() - t1
     return {"value": n_sample / dt / 1e6, "unit": "Mpps", "cores": threads, "kind": "oracle",
             "sample": f"first {n_sample} packets of the timed batch, {threads} threads, "
-                      f"{dt:.2f} s wall, {cpu:.1f} s CPU"}
+                      f"{dt:.2f} s wall, {cpu:.1f} s CPU",
+            "single_core": {"value": n_single / dt1 / 1e6, "unit": "Mpps",
+                            "sample": f"first {n_single} packets, 1 thread, {dt1:.2f} s"},
+            "host": {"cpu": host_cpu_model(), "logical_cpus": os.cpu_count()}}
 
 
 def main():
