@@ -13,10 +13,10 @@
  *    rule list (the paper's data-parallel firewall, Section IV-A: each node
  *    holds a duplicate of the policy, each packet goes to one node);
  *  - rule split: the rule list is cut into P contiguous partitions, one wave
- *    per partition and group of 8 packets holds 64 of its rules in its lanes,
- *    and the partial first matches are merged by a minimum over rule indices,
- *    within the wave by a cross-lane reduction and across partitions by an
- *    atomic minimum (the paper's function-parallel firewall, Section IV-B,
+ *    per partition and group of 16 packets (8 for batches under 2,097,152
+ *    packets) holds 64 of its rules in its lanes, and the partial first matches are merged by a minimum over rule
+ *    indices, within the wave as the lowest matching lane and across
+ *    partitions by an atomic minimum (the paper's function-parallel firewall, Section IV-B,
  *    where each node holds a part of the policy; the paper merges on the CPU,
  *    here the merge runs on the GPU);
  *  - learned index: a small network trained on the rule list's destination

@@ -50,7 +50,7 @@ __device__ __forceinline__ uint64_t full_match_mask(const RuleRec& q, uint32_t s
 // Function-parallel scan (paper Section IV-B): every firewall node holds a
 // part of the policy and sees every packet.  A node here is a wave holding
 // partition p, the rules [p*S, min(R, (p+1)*S)); its 64 lanes take 64 of them
-// at a time into registers, and kRsPackets packets at a time are broadcast to
+// at a time into registers, and G packets at a time are broadcast to
 // all lanes through scalar registers, so each vector test checks one packet
 // against 64 rules.  A packet is finished in this partition at the first
 // 64-rule chunk where any lane matches; the rules sit in lane order, so the
@@ -64,19 +64,25 @@ __device__ __forceinline__ uint64_t full_match_mask(const RuleRec& q, uint32_t s
 // (the pruning across partitions): the index only decreases, so any value
 // read bounds the final one from above, and a packet whose value lies below
 // the partition start cannot take a rule of it.
-constexpr uint32_t kRsPackets = 8;
+// Packets per wave, G: their fields sit in scalar registers (four each), so
+// G = 16 uses about 100 of them; the done mask is a 32-bit word.  Large
+// batches take 16 (half the waves, and with the pruning most of them end at
+// once); smaller ones 8, so that a small batch still spreads over many waves.
+constexpr uint32_t kRsLargeBatch = 2097152;
 
+template <uint32_t G>
 __global__ __launch_bounds__(kScanBlock) void k_rule_split(const RuleRec* __restrict__ rules,
                                                           uint32_t n_rules, uint32_t P,
                                                           uint32_t S, PacketsDev pk, size_t n,
                                                           uint32_t* __restrict__ idx) {
+    static_assert(G < 32, "packet masks are 32-bit words");
     const uint32_t lane = threadIdx.x & 63u;
     const size_t wave = size_t(blockIdx.x) * (kScanBlock / 64) + wave_in_group();
-    const size_t groups = (n + kRsPackets - 1) / kRsPackets;
+    const size_t groups = (n + G - 1) / G;
     const size_t part_sz = wave / groups;
     if (part_sz >= P) return;  // wave-uniform: past the last partition
     const uint32_t part = uint32_t(part_sz);
-    const size_t p0 = (wave % groups) * kRsPackets;
+    const size_t p0 = (wave % groups) * G;
     const uint64_t b64 = uint64_t(part) * S;
     const uint32_t begin = uint32_t(b64 < n_rules ? b64 : n_rules);
     const uint32_t end = uint32_t(b64 + S < n_rules ? b64 + S : n_rules);
@@ -84,28 +90,28 @@ __global__ __launch_bounds__(kScanBlock) void k_rule_split(const RuleRec* __rest
 
     // the packets, one per lane, then broadcast one at a time; with them the
     // index merged so far (a device-scope load, past the compute unit's cache)
-    const size_t mine = p0 + (lane < kRsPackets ? lane : 0u);
-    const bool have = lane < kRsPackets && mine < n;
+    const size_t mine = p0 + (lane < G ? lane : 0u);
+    const bool have = lane < G && mine < n;
     const uint32_t v_src = have ? pk.src[mine] : 0u, v_dst = have ? pk.dst[mine] : 0u;
     const uint32_t v_pp = have ? ((uint32_t(pk.sport[mine]) << 16) | pk.dport[mine]) : 0u;
     const uint32_t v_pr = have ? uint32_t(pk.proto[mine]) : 0u;
     const uint32_t v_cur = have ? __hip_atomic_load(idx + mine, __ATOMIC_RELAXED,
                                                     __HIP_MEMORY_SCOPE_AGENT)
                                 : 0u;
-    uint32_t src[kRsPackets], dst[kRsPackets], pp[kRsPackets], pr[kRsPackets];
+    uint32_t src[G], dst[G], pp[G], pr[G];
     // done: packets past the batch end, and packets already matched below begin
-    uint32_t done = uint32_t(ballot(!have || v_cur < begin)) & ((1u << kRsPackets) - 1u);
+    uint32_t done = uint32_t(ballot(!have || v_cur < begin)) & ((1u << G) - 1u);
 #pragma unroll
-    for (uint32_t g = 0; g < kRsPackets; ++g) {
+    for (uint32_t g = 0; g < G; ++g) {
         src[g] = __builtin_amdgcn_readlane(int(v_src), int(g));
         dst[g] = __builtin_amdgcn_readlane(int(v_dst), int(g));
         pp[g] = __builtin_amdgcn_readlane(int(v_pp), int(g));
         pr[g] = __builtin_amdgcn_readlane(int(v_pr), int(g));
     }
-    const uint32_t all = (1u << kRsPackets) - 1u;
-    uint32_t first[kRsPackets];   // wave-uniform: this partition's first match per packet
+    const uint32_t all = (1u << G) - 1u;
+    uint32_t first[G];   // wave-uniform: this partition's first match per packet
 #pragma unroll
-    for (uint32_t g = 0; g < kRsPackets; ++g) first[g] = kNoMatch;
+    for (uint32_t g = 0; g < G; ++g) first[g] = kNoMatch;
 
     for (uint32_t k = begin; k < end && done != all; k += 64u) {
         const uint32_t r = k + lane;
@@ -113,7 +119,7 @@ __global__ __launch_bounds__(kScanBlock) void k_rule_split(const RuleRec* __rest
         const RuleRec q = rules[ok ? r : begin];
         const uint64_t in_part = ballot(ok);
 #pragma unroll
-        for (uint32_t g = 0; g < kRsPackets; ++g) {
+        for (uint32_t g = 0; g < G; ++g) {
             if ((done >> g) & 1u) continue;  // wave-uniform
             const uint64_t mb = full_match_mask(q, src[g], dst[g], pp[g], pr[g]) & in_part;
             if (mb != 0) {                   // at most one chunk per packet matches
@@ -124,7 +130,7 @@ __global__ __launch_bounds__(kScanBlock) void k_rule_split(const RuleRec* __rest
     }
     if (lane == 0) {
 #pragma unroll
-        for (uint32_t g = 0; g < kRsPackets; ++g)
+        for (uint32_t g = 0; g < G; ++g)
             if (first[g] != kNoMatch) atomicMin(idx + p0 + g, first[g]);
     }
 }
@@ -287,12 +293,17 @@ hipError_t launch_rule_split(const RuleRec* rules, uint32_t n_rules, uint32_t P,
         const uint32_t S0 = ceil_div(n_rules, P);
         const uint32_t S = S0 >= 64u ? S0 : S0 * ceil_div(64u, S0);
         P = ceil_div(n_rules, S);
-        // P waves of 64 lanes per kRsPackets packets, numbered partition-major
-        e = in_chunks(n, chunk_packets(64.0 * P / kRsPackets), [&](size_t o, size_t c) {
-            const uint64_t waves = uint64_t(P) * ((c + kRsPackets - 1) / kRsPackets);
+        // P waves of 64 lanes per G packets, numbered partition-major
+        const uint32_t G = n >= kRsLargeBatch ? 16u : 8u;
+        e = in_chunks(n, chunk_packets(64.0 * P / G), [&](size_t o, size_t c) {
+            const uint64_t waves = uint64_t(P) * ((c + G - 1) / G);
             const uint64_t blocks = (waves + (kScanBlock / 64) - 1) / (kScanBlock / 64);
-            hipLaunchKernelGGL(k_rule_split, dim3(uint32_t(blocks)), dim3(kScanBlock), 0, stream,
-                               rules, n_rules, P, S, advance(pk, o), c, idx + o);
+            if (G == 16)
+                hipLaunchKernelGGL(k_rule_split<16>, dim3(uint32_t(blocks)), dim3(kScanBlock), 0,
+                                   stream, rules, n_rules, P, S, advance(pk, o), c, idx + o);
+            else
+                hipLaunchKernelGGL(k_rule_split<8>, dim3(uint32_t(blocks)), dim3(kScanBlock), 0,
+                                   stream, rules, n_rules, P, S, advance(pk, o), c, idx + o);
             return hipGetLastError();
         });
         if (e != hipSuccess) return e;

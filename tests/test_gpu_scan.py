@@ -67,8 +67,9 @@ def test_1000_rules_full_batch(seed, kw):
 
 def test_rule_split_launch_chunks():
     """Rule split over 10,000 rules with no catch-all, asked for 156 partitions: 65 rules each,
-    so 154 non-empty partitions and 64 * 154 / 8 = 1,232 work-items per packet; one launch
-    holds fewer than 2^32, so 3,500,000 packets go in two launches (the first covers 3,486,144).
+    so 154 non-empty partitions and 64 * 154 / 16 = 616 work-items per packet (a wave per
+    partition and 16 packets); one launch holds fewer than 2^32, so 7,200,000 packets go in two
+    launches (the first covers 6,972,288).
     Packets around the launch edge and a random sample against the oracle; the whole batch
     against the packet-split scan."""
     import torch
@@ -78,9 +79,9 @@ def test_rule_split_launch_chunks():
              & (rules.sport_hi == 65535) & (rules.dport_lo == 0) & (rules.dport_hi == 65535)
              & (rules.proto_any != 0))
     rules.proto_any[catch] = 0                  # no catch-all: every rule stays reachable
-    n = 3_500_000
+    n = 7_200_000
     pk = gen.make_packets(rules, n, 31)
-    edge = 3_486_144                            # the first launch's last packet + 1
+    edge = 6_972_288                            # the first launch's last packet + 1
     rng = np.random.Generator(np.random.PCG64(31))
     sample = np.unique(np.concatenate([np.arange(edge - 1000, edge + 1000),
                                        rng.integers(0, n, 20_000)]))
