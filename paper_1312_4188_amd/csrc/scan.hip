@@ -175,7 +175,7 @@ __global__ __launch_bounds__(1024) void k_hybrid(const uint2* __restrict__ pairs
     }
     __syncthreads();
 
-    WaveScan<K> ws;
+    WaveScan<K, false> ws;   // its two work-groups per CU need the scalar registers
     ws.init(pk, first, n, dflt);
     const uint64_t r0 = uint64_t(w) * S;
     const uint32_t begin = uint32_t(r0 < n_rules ? r0 : n_rules);

@@ -117,7 +117,11 @@ __device__ __forceinline__ T vector_load(const T* p) {
     return out;
 }
 
-template <int K>
+// BATCH: with one packet per lane, a block's eight first tests are taken at
+// once before its single branch (shorter dependence chains: a small batch,
+// whose few waves cannot hide them, finishes sooner).  It costs 16 scalar
+// registers, so a kernel short of them turns it off.
+template <int K, bool BATCH = K == 1>
 struct WaveScan {
     uint32_t src[K], dst[K], pp[K], pr[K];
     uint64_t valid[K];
@@ -237,9 +241,32 @@ struct WaveScan {
                 uint2 nxt[kPairBlock];
 #pragma unroll
                 for (uint32_t u = 0; u < kPairBlock; ++u) nxt[u] = first[r + kPairBlock + u];
+                if constexpr (K == 1 && BATCH) {
+                    // the block's eight first tests at once (they do not depend
+                    // on which lanes are live), then one branch; a block with a
+                    // passing lane goes rule by rule in order, as step() does
+                    uint64_t c8[kPairBlock];
+                    uint64_t any = 0;
 #pragma unroll
-                for (uint32_t u = 0; u < kPairBlock; ++u)
-                    step<F, OWN_INDEX, SEEDED>(cur[u], rules, r + u, base);
+                    for (uint32_t u = 0; u < kPairBlock; ++u) {
+                        c8[u] = ballot(first_test<F>(0, cur[u]));
+                        any |= c8[u];
+                    }
+                    if (__builtin_expect((any & live_any) != 0, 0)) {
+#pragma unroll
+                        for (uint32_t u = 0; u < kPairBlock; ++u) {
+                            if ((c8[u] & live_any) != 0) {
+                                const RuleRec q = rules[r + u];
+                                const uint64_t cu[1] = {c8[u]};
+                                finish<F, SEEDED>(cu, q, OWN_INDEX ? q.idx : base + r + u);
+                            }
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (uint32_t u = 0; u < kPairBlock; ++u)
+                        step<F, OWN_INDEX, SEEDED>(cur[u], rules, r + u, base);
+                }
                 if (live_any == 0) return false;
 #pragma unroll
                 for (uint32_t u = 0; u < kPairBlock; ++u) cur[u] = nxt[u];
