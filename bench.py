@@ -35,6 +35,9 @@ VALU_INT32_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # Algorithmic cost of one rule check: the destination test every check makes
 # (one subtract, one unsigned compare); deeper field tests are not counted.
 OPS_PER_CHECK = 2
+# The survey's pricing of a learned-path candidate check: every field test, the select of the
+# answer and the list step, about 7 lane-ops; reported beside the lower bound above.
+OPS_PER_CHECK_FULL = 7
 BYTES_PER_PACKET = 13 + 5          # 5-tuple in (4+4+2+2+1), index + action out (4+1)
 RECORD_BYTES = 32                  # one compiled rule record
 
@@ -70,6 +73,25 @@ def committed_traffic(workload: str):
     return {k.split(".")[0]: float(v) for k, v in vals.items() if k.endswith(".traffic_bytes")}
 
 
+def committed_valu_counters(workload: str):
+    """Executed VALU lane-ops per launch (SQ_INSTS_VALU x 64) from the committed counter summary,
+    or {} when it is for another workload or the kernels changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"valu_counters_{workload}.txt")
+    if not os.path.exists(path):
+        return {}
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#") or ":" not in line:
+                continue
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return {}
+    return {k.rsplit(".", 1)[0]: 64.0 * float(v) for k, v in vals.items()
+            if k.endswith(".SQ_INSTS_VALU")}
+
+
 def _list_checks(B, off, L, keys, ans):
     """Per packet: entries of its interval's list up to and including its answer."""
     M = len(B)
@@ -79,7 +101,7 @@ def _list_checks(B, off, L, keys, ans):
     return np.searchsorted(key, j * (1 << 41) + ans, side="right") - off[j]
 
 
-def learned_work(rs, pk, idx, hidden: int = 32):
+def learned_work(rs, pk, idx, hidden: int = 32, network: bool = True):
     """Exact algorithmic work of the learned path for every packet of the batch.
 
     Candidate checks of packet p: the entries of its destination interval's
@@ -91,7 +113,9 @@ def learned_work(rs, pk, idx, hidden: int = 32):
     hidden unit a multiply-add, a max and a multiply-add, in each stage); 2 per
     binary-search probe of the mean error window and 2 per probe of the
     source-interval lookup (bucket-table read plus its walk steps, or a
-    binary search when the index has no bucket table); for the port/protocol table of the first 64 address-wildcard
+    binary search when the index has no bucket table); without the network (``network`` false),
+    no 6H and the probes of the full binary search over B instead of the window; for the
+    port/protocol table of the first 64 address-wildcard
     rules, 2 per table read (the two high-byte tables, the walk steps, three
     masks, the rule entry) and 3 for combining the masks (two ANDs, one bit
     scan).  Bytes: the packet in, the result out, and a 32-byte record
@@ -108,9 +132,12 @@ def learned_work(rs, pk, idx, hidden: int = 32):
     n_g = np.searchsorted(rest, ans, side="right")
     checks = int(n_l.sum() + n_s.sum() + n_g.sum())
     src_probes = (1 + bs_steps) if bs_bits else math.ceil(math.log2(max(len(Bs), 1))) + 1
-    probes = math.ceil(math.log2(2.0 * float(err.mean()) + 1.0)) + 1 + src_probes
+    if network:
+        probes = math.ceil(math.log2(2.0 * float(err.mean()) + 1.0)) + 1 + src_probes
+    else:            # the full binary search over B instead of the network and its window
+        probes = math.ceil(math.log2(max(len(B), 1))) + 1 + src_probes
     table_ops = (2 * (2 + steps_s + steps_d + 4) + 3) if pt_count else 0
-    ops = 2 * checks + len(pk) * (6 * hidden + 2 * probes + table_ops)
+    ops = 2 * checks + len(pk) * ((6 * hidden if network else 0) + 2 * probes + table_ops)
     gathered = int(n_l.sum() + n_s.sum())
     nbytes = len(pk) * BYTES_PER_PACKET + gathered * RECORD_BYTES
     return {"candidate_checks": checks, "list_checks": gathered, "lane_ops": ops,
@@ -169,6 +196,28 @@ def closed_loop_latency(rs, dp, mode_kw, seed: int, n_batches: int, stream):
             "python_p50_us": pct(lat, 50), "python_p99_us": pct(lat, 99)}
 
 
+def serving_oracle(chains, chain, offset, sizes, pool):
+    """The CPU oracle's answer for every request of a serving trace, at the request's offset
+    in the pool (requests of one chain classified together)."""
+    import oracle
+    from synth import gen
+    total = int(pool[0].shape[0])
+    want_i = np.full(total, -7, dtype=np.int32)
+    want_a = np.zeros(total, dtype=np.uint8)
+    u = lambda a, dt: a.view(dt)
+    for c in range(len(chains)):
+        ks = np.nonzero(chain == c)[0]
+        if ks.size == 0:
+            continue
+        pos = np.concatenate([np.arange(int(offset[k]), int(offset[k] + sizes[k])) for k in ks])
+        pk = gen.Packets(u(pool[0], np.uint32)[pos], u(pool[1], np.uint32)[pos],
+                         u(pool[2], np.uint16)[pos], u(pool[3], np.uint16)[pos], pool[4][pos])
+        i, a = oracle.classify(chains[c], pk, threads=max(1, min(16, os.cpu_count() or 1)))
+        want_i[pos] = i
+        want_a[pos] = a
+    return want_i, want_a
+
+
 def serving_leg(seed: int, n_req: int, loads, log_fn):
     """Open-loop serving: 3 resident chains, Poisson arrivals of log-uniform batches.
 
@@ -212,6 +261,7 @@ def serving_leg(seed: int, n_req: int, loads, log_fn):
         pool[4][o:e] = pk.proto
     ti, out_i = pinned(total, torch.int32)
     ta, out_a = pinned(total, torch.uint8)
+    want_i, want_a = serving_oracle(chains, chain, offset, sizes, pool)
     out = {"chains": build, "requests": n_req, "packets": total, "modes": {}}
     mean_batch = total / n_req
     for mode, slots, pipe, workers in (("auto", 8, False, 4), ("auto", 8, False, 1),
@@ -238,6 +288,10 @@ def serving_leg(seed: int, n_req: int, loads, log_fn):
                        f"{' pipeline' if pipe else ''} load {frac:.0%}: "
                        f"p50 {res['loads'][-1]['p50_us']:.0f} us "
                        f"p99 {res['loads'][-1]['p99_us']:.0f} us")
+            # the last replay wrote every request's results: each one against the oracle
+            res["bit_exact"] = bool(np.array_equal(out_i, want_i) and
+                                    np.array_equal(out_a, want_a))
+            log_fn(f"  serving {mode}: every request bit-exact vs the oracle: {res['bit_exact']}")
             res["slots"], res["pipeline"], res["workers"] = slots, pipe, workers
             key = (("learned" if mode == "auto" else mode) + ("" if slots == 8 else f"_{slots}slots")
                    + ("" if workers == 4 else f"_{workers}worker"))
@@ -328,6 +382,7 @@ def multichain_leg(seed: int, steps: int, log_fn):
     """64 independent chains (32..8,192 rules, 4,096..1,048,576 packets, log-uniform) in one
     persistent launch, autotuned, against one packet-split launch per chain."""
     import torch
+    import oracle
     from synth import gen
     from paper_1312_4188_amd import fw
     work = gen.multichain_workload(seed=seed)
@@ -364,6 +419,12 @@ def multichain_leg(seed: int, steps: int, log_fn):
     torch.cuda.synchronize()
     out["same_as_per_chain"] = bool(all(torch.equal(a, it[2]) and torch.equal(b, it[3])
                                         for (a, b), it in zip(ref, items)))
+    # the tuned launch's results, chain by chain, against the oracle
+    threads = max(1, min(16, os.cpu_count() or 1))
+    out["bit_exact"] = bool(all(
+        np.array_equal(a.cpu().numpy(), w[0]) and np.array_equal(b.cpu().numpy(), w[1])
+        for (a, b), w in zip(ref, (oracle.classify(r, p, threads=threads) for r, p in work))))
+    log_fn(f"  multichain: every chain bit-exact vs the oracle: {out['bit_exact']}")
     for rs in rss:
         rs.close()
     return out
@@ -383,13 +444,15 @@ def host_cpu_model() -> str:
 
 def cpu_baseline(rules, pk, n_sample: int, n_single: int = 1_048_576):
     """The CPU oracle, as it stands, on a bounded sample of the same batch: with up to 16
-    worker threads (the headline figure), and on one core over a smaller sample."""
+    worker threads (the headline figure), and on one core over a smaller sample.  Returns the
+    report and the oracle's (rule index, action) for the first n_sample packets, which the
+    caller compares with the GPU's output."""
     import oracle
     threads = max(1, min(16, os.cpu_count() or 1))
     n_sample = min(n_sample, len(pk))
     sub = pk.subset(slice(0, n_sample))
     t0, c0 = time.perf_counter(), time.process_time()
-    oracle.classify(rules, sub, threads=threads)
+    want = oracle.classify(rules, sub, threads=threads)
     dt, cpu = time.perf_counter() - t0, time.process_time() - c0
     n_single = min(n_single, len(pk))
     t1 = time.perf_counter()
@@ -400,7 +463,7 @@ def cpu_baseline(rules, pk, n_sample: int, n_single: int = 1_048_576):
                       f"{dt:.2f} s wall, {cpu:.1f} s CPU",
             "single_core": {"value": n_single / dt1 / 1e6, "unit": "Mpps",
                             "sample": f"first {n_single} packets, 1 thread, {dt1:.2f} s"},
-            "host": {"cpu": host_cpu_model(), "logical_cpus": os.cpu_count()}}
+            "host": {"cpu": host_cpu_model(), "logical_cpus": os.cpu_count()}}, want
 
 
 def main():
@@ -467,6 +530,7 @@ def main():
         modes = {k: modes[k] for k in keep}
     results = {}
     ref = None
+    ref_act = None
     for name, (ruleset, kw) in modes.items():
         log(f"timing {name}")
         ms, wall = time_steps(lambda: ruleset.classify(dp, stream=stream, out_idx=out_i,
@@ -477,6 +541,7 @@ def main():
         if ref is None:
             ref = (idx.copy(), act.copy())
         agree = bool(np.array_equal(idx, ref[0]) and np.array_equal(act, ref[1]))
+        del idx, act
         results[name] = {"ms": ms, "mpps": n / ms / 1e3, "same_as_learned": agree,
                          "wall_s": wall}
         if kw["mode"] == "learned":
@@ -484,7 +549,7 @@ def main():
                                           count_misses=True, **kw)
             results[name]["window_misses"] = miss
         log(f"  {name}: {ms:.3f} ms/step, {n / ms / 1e3:.1f} Mpps")
-    ref = ref[0]
+    ref, ref_act = ref
 
     # what the trained network gains: window width, interval lookup alone, end to end
     gain = {}
@@ -520,27 +585,49 @@ def main():
 
     head = next(iter(modes))
     ms = results[head]["ms"]
-    work = learned_work(rs, pk, ref)
-    ms_learned = results.get("learned", {}).get("ms", float("nan"))   # the roofline's kernel
-    achieved_tops = work["lane_ops"] / (ms_learned * 1e-3) / 1e12
     traffic = committed_traffic(args.workload)
-    roofline = {"bound": "alu", "achieved": achieved_tops, "peak": VALU_INT32_PEAK_TOPS,
-                "unit": "Tops/s", "frac": achieved_tops / VALU_INT32_PEAK_TOPS,
-                "traffic": traffic.get("k_learned"), "kernel": "k_learned<true,2,false>",
-                "algorithmic_lane_ops": work["lane_ops"], "algorithmic_bytes": work["bytes"],
-                "hbm_gbs": work["bytes"] / (ms_learned * 1e-3) / 1e9,
-                "hbm_frac": work["bytes"] / (ms_learned * 1e-3) / 1e9 / HBM_PEAK_GBS}
-    if "learned" not in results:      # a run without the learned mode has no learned roofline
-        roofline = None
+    counters = committed_valu_counters(args.workload)
+
+    def alu_roofline(kernel, mode, work, profile_key):
+        """VALU roofline of one timed mode: algorithmic lane-ops per step over its time; HBM
+        from the committed counter traffic when it is current, else 18 B per packet."""
+        t = results[mode]["ms"] * 1e-3
+        tr = traffic.get(profile_key)
+        hbm = tr if tr is not None else n * BYTES_PER_PACKET
+        r = {"bound": "alu", "achieved": work["lane_ops"] / t / 1e12,
+             "peak": VALU_INT32_PEAK_TOPS, "unit": "Tops/s",
+             "frac": work["lane_ops"] / t / 1e12 / VALU_INT32_PEAK_TOPS,
+             "traffic": tr, "kernel": kernel, "algorithmic_lane_ops": work["lane_ops"],
+             "ops_per_check": OPS_PER_CHECK,
+             "algorithmic_hbm_bytes": n * BYTES_PER_PACKET,
+             "hbm_gbs": hbm / t / 1e9, "hbm_frac": hbm / t / 1e9 / HBM_PEAK_GBS,
+             "hbm_source": "rocprofv3 FETCH_SIZE + WRITE_SIZE" if tr is not None
+                           else "algorithmic, 18 B per packet"}
+        if "candidate_checks" in work:
+            # survey pricing of a candidate check: ~7 lane-ops (all field tests, select, step)
+            ops7 = work["lane_ops"] + (OPS_PER_CHECK_FULL - OPS_PER_CHECK) * work["candidate_checks"]
+            r["frac_at_7_ops_per_check"] = ops7 / t / 1e12 / VALU_INT32_PEAK_TOPS
+            # records gathered from the per-lane lists: served by L2 and LDS, not HBM
+            r["gather_bytes"] = work["list_checks"] * RECORD_BYTES
+            r["gather_gbs"] = r["gather_bytes"] / t / 1e9
+        ex = counters.get(profile_key)
+        if ex:
+            r["executed_lane_ops"] = ex
+            r["useful_over_executed"] = work["lane_ops"] / ex
+        return r
+
+    roofline = roofline_bs = None
+    if "learned" in results:
+        work = learned_work(rs, pk, ref)
+        roofline = alu_roofline("k_learned<true,2,false>", "learned", work, "k_learned")
+    if "learned_binary_search" in results:
+        work_bs = learned_work(rs, pk, ref, network=False)
+        roofline_bs = alu_roofline("k_learned<true,2,false> (lookup=1)", "learned_binary_search",
+                                   work_bs, "k_learned_binary_search")
     scan_roofline = None
     if "packet_split" in results:
-        scan_ms = results["packet_split"]["ms"]
-        scan_ops = checks * OPS_PER_CHECK
-        scan_roofline = {"bound": "alu", "kernel": "k_packet_split<4>",
-                         "traffic": traffic.get("k_packet_split"),
-                         "achieved": scan_ops / (scan_ms * 1e-3) / 1e12,
-                         "frac": scan_ops / (scan_ms * 1e-3) / 1e12 / VALU_INT32_PEAK_TOPS,
-                         "hbm_gbs": n * BYTES_PER_PACKET / (scan_ms * 1e-3) / 1e9}
+        scan_roofline = alu_roofline("k_packet_split<4>", "packet_split",
+                                     {"lane_ops": checks * OPS_PER_CHECK}, "k_packet_split")
     if args.copy_calibration:
         log("copy calibration: 256 MiB device-to-device")
         a = torch.empty(64 << 20, dtype=torch.int32, device="cuda")
@@ -572,9 +659,18 @@ def main():
         multichain = multichain_leg(args.seed, max(3, args.steps // 2), log)
 
     cpu = None
+    oracle_exact, checked = None, 0
     if not args.no_cpu:
-        log("cpu baseline")
-        cpu = cpu_baseline(rules, pk, min(args.cpu_sample, n))
+        log("cpu baseline (the oracle over the timed batch)")
+        cpu, (want_i, want_a) = cpu_baseline(rules, pk, min(args.cpu_sample, n))
+        checked = int(want_i.shape[0])
+        # the timed output (every mode agreed with the first one) against the oracle
+        oracle_exact = bool(np.array_equal(ref[:checked], want_i) and
+                            np.array_equal(ref_act[:checked], want_a))
+        for r in results.values():
+            r["bit_exact"] = bool(r["same_as_learned"] and oracle_exact)
+        log(f"  timed output vs the oracle over {checked} packets: bit-exact {oracle_exact}")
+        del want_i, want_a
 
     line = {
         "metric": "Mpps (bit-exact first-match) at 10k rules: learned-index vs scan; p99 latency",
@@ -584,6 +680,7 @@ def main():
         "data": "synthetic (seeded generators)",
         "config": {"workload": args.workload, "rules": R, "packets": n, "seed": args.seed,
                    "path": head, "k_star": k_star},
+        "bit_exact": oracle_exact, "bit_exact_packets": checked,
         "scan_mpps": results["packet_split"]["mpps"] if "packet_split" in results else None,
         "speedup_vs_scan": (results["packet_split"]["ms"] / ms
                             if "packet_split" in results else None),
@@ -592,13 +689,25 @@ def main():
         "modes": results, "latency": latency,
         "scan_rule_checks": checks, "learned_candidate_checks": work["candidate_checks"],
         "index": index_stats, "index_untrained": untrained_stats, "network_gain": gain,
-        "roofline": roofline, "scan_roofline": scan_roofline, "serving": serving,
+        "roofline": roofline, "roofline_binary_search": roofline_bs,
+        "scan_roofline": scan_roofline, "serving": serving,
         "multichain": multichain, "ingest": ingest, "scan_configs": scan_configs,
         "cpu_baseline": cpu,
     }
     rs.close()
     rs_un.close()
+    for name, lat in latency.items():
+        log(f"closed-loop latency {name}: p50 {lat['p50_us']:.1f} us, p99 {lat['p99_us']:.1f} us")
+    if serving:
+        for name, m in serving["modes"].items():
+            top = m["loads"][-1] if m["loads"] else {}
+            log(f"serving {name}: peak {m['peak_mpps']:.0f} Mpps, bit-exact {m.get('bit_exact')}, "
+                f"p99 at {top.get('offered_frac', 0):.0%} load {top.get('p99_us', float('nan')):.0f} us")
+    log(f"headline {head}: {line['value']:.0f} Mpps, bit-exact vs oracle {oracle_exact} "
+        f"({checked} packets)")
     print(json.dumps(line), flush=True)
+    if oracle_exact is False:
+        sys.exit("the timed output differs from the oracle")
 
 
 if __name__ == "__main__":
