@@ -117,13 +117,24 @@ typedef struct fw_classify_opts {
                                   for packet split, 2 for learned) that still gives the
                                   launch 8,192 waves, so small batches use fewer per lane;
                                   hybrid: 4 from 2,097,152 packets up, else 1 */
-    uint64_t *window_misses;   /* learned mode, optional HOST pointer: when given the call
-                                  waits for its work and stores how many packets' error
-                                  window missed (they fell back to a full search) */
+    uint64_t *window_misses;   /* learned mode, optional HOST pointer: the call's statistics.
+                                  When given, the call counts in memory of its own how many
+                                  packets' error window missed (they fell back to a full
+                                  search), waits for its work (the call is then synchronous)
+                                  and stores the count; NULL keeps the call asynchronous.
+                                  The other modes store 0. */
 } fw_classify_opts;
 
 /*
- * Compile `n_rules` rules into a device-resident ruleset.  The rules are
+ * Compile `n_rules` rules into a device-resident ruleset (paper Section I: the
+ * list's order is its priority, the first match decides, and packets no rule
+ * matches take the default action, deny in the paper; Section IV: each rule
+ * is a 5-tuple plus an action, an unspecified field matching every value).
+ * Rule i keeps index i.  Every field becomes an unsigned range [lo, lo + w]
+ * (a prefix of length L keeps the top L bits of its base), packed into a
+ * 32-byte device record; the list is also grouped by each rule's most
+ * selective field and cut after its first rule that matches every packet
+ * (rules past it can never be a first match).  The rules are
  * copied; the caller may free `rules` on return.  `default_action` (FW_DROP
  * or FW_ACCEPT) applies to packets no rule matches.  n_rules may be 0 (every
  * packet then takes the default) and at most 16,777,216.

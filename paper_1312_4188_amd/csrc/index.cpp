@@ -52,7 +52,6 @@ struct LearnedIndex {
     float* d_w1 = nullptr;
     uint32_t* d_w2 = nullptr;
     ExpertMeta* d_meta = nullptr;
-    unsigned long long* d_miss = nullptr;
     std::vector<uint32_t> B, off, L_idx, G_idx, err;
     std::vector<float> weights;   // stage 1 then experts, bf16 values widened to float
     uint64_t device_bytes = 0;
@@ -275,8 +274,7 @@ void free_index_memory(LearnedIndex* ix) {
                     static_cast<void*>(ix->d_L), static_cast<void*>(ix->d_Bs),
                     static_cast<void*>(ix->d_soff), static_cast<void*>(ix->d_S),
                     static_cast<void*>(ix->d_w1), static_cast<void*>(ix->d_w2),
-                    static_cast<void*>(ix->d_meta), static_cast<void*>(ix->d_miss),
-                    static_cast<void*>(ix->d_pt), static_cast<void*>(ix->d_bs_bucket),
+                    static_cast<void*>(ix->d_meta), static_cast<void*>(ix->d_pt), static_cast<void*>(ix->d_bs_bucket),
                     static_cast<void*>(ix->d_image[0]), static_cast<void*>(ix->d_image[1])})
         if (p) (void)hipFree(p);
 }
@@ -685,7 +683,6 @@ fw_status build_index(const fw_rule* rules, const RuleRec* recs, uint32_t n_rule
         (e = dalloc(&ix->d_w1, kGradCols, &bytes)) != hipSuccess ||
         (e = dalloc(&ix->d_w2, size_t(E) * kRowDwords, &bytes)) != hipSuccess ||
         (e = dalloc(&ix->d_meta, E, &bytes)) != hipSuccess ||
-        (e = dalloc(&ix->d_miss, 1, &bytes)) != hipSuccess ||
         (e = dalloc(&ix->d_pt, 1, &bytes)) != hipSuccess ||
         (e = dalloc(&ix->d_bs_bucket, ix->bs_bucket.size(), &bytes)) != hipSuccess)
         return bail(e, "allocating the learned index");
@@ -930,17 +927,30 @@ fw_status classify_learned(const LearnedIndex* ix, uint8_t default_action, Packe
     if (lookup > 1) return fail(FW_E_INVAL, "lookup must be 0 or 1");
     LookupArgs a = args_of(ix, lookup == 0 ? 1u : 0u);
     hipError_t e = hipSuccess;
+    // The miss count of this call only: a counter allocated on the stream for
+    // it, so calls on other streams never share one.
+    unsigned long long* cnt = nullptr;
     if (window_misses) {
-        e = launch_fill_u32(reinterpret_cast<uint32_t*>(ix->d_miss), 2, 0u, stream);
-        if (e != hipSuccess) return hip_fail(e, "clearing the miss counter");
-        a.miss = ix->d_miss;
+        e = hipMallocAsync(reinterpret_cast<void**>(&cnt), 2 * sizeof(unsigned long long), stream);
+        if (e == hipSuccess)
+            e = launch_fill_u32(reinterpret_cast<uint32_t*>(cnt), 2, 0u, stream);
+        if (e != hipSuccess) {
+            if (cnt) (void)hipFreeAsync(cnt, stream);
+            return hip_fail(e, "setting up the miss counter");
+        }
+        a.miss = cnt;
     }
     e = launch_learned(a, pk, n, out_idx, out_act, default_action, nullptr, nullptr,
                        packets_per_lane, stream);
-    if (e != hipSuccess) return hip_fail(e, "learned lookup launch");
+    if (e != hipSuccess) {
+        if (cnt) (void)hipFreeAsync(cnt, stream);
+        return hip_fail(e, "learned lookup launch");
+    }
     if (window_misses) {
         unsigned long long v = 0;
-        e = hipMemcpyAsync(&v, ix->d_miss, sizeof v, hipMemcpyDeviceToHost, stream);
+        e = hipMemcpyAsync(&v, cnt, sizeof v, hipMemcpyDeviceToHost, stream);
+        const hipError_t e2 = hipFreeAsync(cnt, stream);
+        if (e == hipSuccess) e = e2;
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
         if (e != hipSuccess) return hip_fail(e, "reading the miss counter");
         *window_misses = v;

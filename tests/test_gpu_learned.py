@@ -93,15 +93,14 @@ def test_learned_classify_matches_oracle(wl, seed):
 
 
 @pytest.mark.parametrize("seed", [1, 2, 3, 4, 5])
-def test_learned_10000_rules_sampled(seed):
-    """10,000 skewed rules x 16,777,216 packets, seeds 1-5; the full batch runs, a sample is
-    checked against the oracle and the whole batch against the packet-split scan."""
+def test_learned_10000_rules_whole_batch(seed):
+    """10,000 skewed rules x 16,777,216 packets, seeds 1-5: every packet of the batch against
+    the oracle, through the learned index (network + window, and the full binary search) and
+    the packet-split scan."""
     import torch
     fw = fwmod()
     rules, pk = gen.workload("learned_10000x16M", seed=seed)
-    rng = np.random.Generator(np.random.PCG64(9))
-    sample = np.sort(rng.choice(len(pk), 40_000, replace=False))
-    want = oracle.classify(rules, pk.subset(sample), threads=16)
+    want = oracle.classify(rules, pk, threads=16)
     dp = fw.DevicePackets.from_host(pk)
     with fw.Ruleset(rules) as rs:
         say(f"learned 10000x16M seed={seed} build")
@@ -110,14 +109,49 @@ def test_learned_10000_rules_sampled(seed):
         for lookup in (0, 1):
             idx, act, miss = rs.classify(dp, mode="learned", lookup=lookup, count_misses=True)
             torch.cuda.synchronize()
-            got = (idx.cpu().numpy()[sample], act.cpu().numpy()[sample])
-            assert_same(got, want, f"learned 10000x16M seed {seed} lookup {lookup}")
+            assert_same((idx.cpu().numpy(), act.cpu().numpy()), want,
+                        f"learned 10000x16M seed {seed} lookup {lookup}")
             say(f"  lookup {lookup}: window misses {miss} of {len(pk)}")
-        # the scan agrees on the whole batch
         si, sa = rs.classify(dp, mode="packet_split")
         torch.cuda.synchronize()
-        assert np.array_equal(si.cpu().numpy(), idx.cpu().numpy())
-        assert np.array_equal(sa.cpu().numpy(), act.cpu().numpy())
+        assert_same((si.cpu().numpy(), sa.cpu().numpy()), want,
+                    f"packet split 10000x16M seed {seed}")
+
+
+@pytest.mark.parametrize("seed,all_dst", [(1, False), (2, False), (1, True)])
+def test_learned_50000_rule_chain(seed, all_dst):
+    """The largest resident serving chain (50,000 skewed rules) through its learned index and
+    the scans, every packet of a 4,194,304-packet batch against the oracle, at the library's
+    default and at 1 and 4 packets per lane.  As generated, the chain reaches a rule matching
+    every packet early, so its index is small; with every rule's destination specified
+    (all_dst) there is none, and the boundary array (about 75,000 entries) is searched in
+    global memory."""
+    import torch
+    fw = fwmod()
+    rules = gen.serving_chains(seed)[2]
+    assert len(rules) == 50_000
+    if all_dst:
+        rules.dst_plen[rules.dst_plen == 0] = 16
+    pk = gen.make_packets(rules, 4_194_304, seed)
+    want = oracle.classify(rules, pk, threads=16)
+    dp = fw.DevicePackets.from_host(pk)
+    with fw.Ruleset(rules) as rs:
+        say(f"learned 50000-rule chain seed={seed} all_dst={all_dst} build")
+        st = rs.build_learned_index(seed=seed)
+        say(f"  stats {st}")
+        if all_dst:
+            assert st["n_boundaries"] * 4 > 80 * 1024
+        for kw in (dict(), dict(packets_per_lane=1), dict(packets_per_lane=4),
+                   dict(lookup=1)):
+            say(f"  learned {kw}")
+            idx, act = rs.classify(dp, mode="learned", **kw)[:2]
+            torch.cuda.synchronize()
+            assert_same((idx.cpu().numpy(), act.cpu().numpy()), want, f"learned 50k {kw}")
+        for mode in ("packet_split", "hybrid"):
+            say(f"  {mode}")
+            si, sa = rs.classify(dp, mode=mode)[:2]
+            torch.cuda.synchronize()
+            assert_same((si.cpu().numpy(), sa.cpu().numpy()), want, f"{mode} 50k")
 
 
 @pytest.mark.parametrize("n", [1, 63, 65, 1000, 4097])

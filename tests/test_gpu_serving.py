@@ -123,3 +123,29 @@ def test_empty_request_and_bad_chain():
         with pytest.raises(ValueError):   # a request past the end of the pool
             sv.replay([0.0], [0], [32], [64], pool, np.zeros(64, np.int32), np.zeros(64, np.uint8))
     rs[0].close()
+
+
+def test_serving_chains_of_2k_10k_50k_rules():
+    """The serving chains of 2,000, 10,000 and 50,000 skewed rules, each with its learned
+    index: 40 requests of log-uniform size (64..65,536 packets) give, request by request,
+    the same results in the mix (four slots) as alone (one slot), and the oracle's."""
+    fw = fwmod()
+    chains = gen.serving_chains(1)
+    rs = [fw.Ruleset(c) for c in chains]
+    for r in rs:
+        r.build_learned_index(seed=1)
+    reqs = _requests(chains, 40, 11, max_batch=65_536)
+    say("serving: 40 requests over the 2k/10k/50k-rule chains, 4 slots")
+    with fw.Server(rs, slots=4) as sv:
+        mix, _ = _run(sv, reqs)
+    say("serving: the same requests one at a time")
+    with fw.Server(rs, slots=1) as sv:
+        alone = [_run(sv, [r])[0][0] for r in reqs]
+    for k, ((c, pk), m, a) in enumerate(zip(reqs, mix, alone)):
+        want = oracle.classify(chains[c], pk, threads=16)
+        np.testing.assert_array_equal(m[0], a[0], err_msg=f"request {k} idx mix vs alone")
+        np.testing.assert_array_equal(m[1], a[1], err_msg=f"request {k} action mix vs alone")
+        np.testing.assert_array_equal(m[0], want[0], err_msg=f"request {k} vs oracle")
+        np.testing.assert_array_equal(m[1], want[1], err_msg=f"request {k} action vs oracle")
+    for r in rs:
+        r.close()
