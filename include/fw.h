@@ -336,6 +336,23 @@ typedef struct fw_multi_opts {
 fw_status fw_classify_multi(const fw_chain_batch *batches, uint32_t n_chains,
                             const fw_multi_opts *opts);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * launch as fw_classify_multi with the same options and results, but its
+ * chain descriptor table and work-queue counter live in a static device array
+ * the library holds on each GPU it runs on (about 97 KiB, kept until the
+ * process ends) instead of memory allocated for the call.  It calls no
+ * hipMalloc, hipFree or other device-allocating routine; the array's address
+ * is looked up once per device on the first call there.  Every call on one
+ * GPU shares that array: calls that overlap on a GPU (on different streams,
+ * or from different threads before the earlier launch has finished) race and
+ * may give wrong results, so the caller orders them (one stream, or events).
+ * The counter is cleared by a kernel at the start of each call.
+ * Errors: those of fw_classify_multi, and FW_E_INVAL for more than 1,024
+ * chains. */
+fw_status fw_classify_multi_noalloc(const fw_chain_batch *batches, uint32_t n_chains,
+                                    const fw_multi_opts *opts);
+
 /* Time every packets-per-lane x placement configuration on these batches
  * (each run really classifies them), remember the fastest for this batch
  * shape (rule and packet counts of every chain) so later calls with tuned

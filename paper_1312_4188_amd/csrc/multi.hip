@@ -52,6 +52,37 @@ struct ChainDesc {
 static_assert(sizeof(ChainDesc) == 96, "descriptor layout");
 
 constexpr uint32_t kDescPerChunk = 32;   // 3 KiB of kernel arguments per upload launch
+
+// Scratch of fw_classify_multi_noalloc: the descriptor table of up to
+// kNoAllocMaxChains chains, then the work-queue counter, in one static device
+// array (each GPU the library runs on holds its own copy for the life of the
+// process).  Host code never passes the array's name to a kernel: it takes
+// the array's device address from hipGetSymbolAddress, once per device.
+constexpr uint32_t kNoAllocMaxChains = 1024;
+constexpr size_t kScratchTable = sizeof(ChainDesc) * kNoAllocMaxChains;
+__device__ __align__(256) unsigned char scratch[kScratchTable + 256];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch array (looked up on first use).
+hipError_t scratch_address(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
 struct DescChunk {
     ChainDesc d[kDescPerChunk];
 };
@@ -185,7 +216,12 @@ hipError_t persistent_grid(Kern kern, uint32_t items, uint32_t* grid) {
     return hipSuccess;
 }
 
-hipError_t run(const fw_chain_batch* b, uint32_t n_chains, Config cfg, hipStream_t s) {
+// One persistent launch over the batches.  The descriptor table and the work
+// counter live in `scratch` when given (at least kScratchTable + 256 bytes,
+// the table at its start and the counter at kScratchTable), else in memory
+// allocated on the stream for this call and freed after it.
+hipError_t run(const fw_chain_batch* b, uint32_t n_chains, Config cfg, hipStream_t s,
+               void* scratch_mem = nullptr) {
     // order by estimated cost, largest first; skip empty batches
     std::vector<uint32_t> order;
     for (uint32_t c = 0; c < n_chains; ++c)
@@ -218,9 +254,11 @@ hipError_t run(const fw_chain_batch* b, uint32_t n_chains, Config cfg, hipStream
     }
     if (items >= 0xFFFFFFFFull) return hipErrorInvalidValue;
     const uint32_t nc = uint32_t(desc.size());
-    void* mem = nullptr;
-    const size_t table_bytes = sizeof(ChainDesc) * nc;
-    hipError_t e = hipMallocAsync(&mem, table_bytes + 256, s);
+    void* mem = scratch_mem;
+    const size_t table_bytes = scratch_mem ? kScratchTable : sizeof(ChainDesc) * nc;
+    if (scratch_mem && nc > kNoAllocMaxChains) return hipErrorInvalidValue;
+    hipError_t e = hipSuccess;
+    if (!scratch_mem) e = hipMallocAsync(&mem, table_bytes + 256, s);
     if (e != hipSuccess) return e;
     ChainDesc* table = static_cast<ChainDesc*>(mem);
     uint32_t* counter = reinterpret_cast<uint32_t*>(static_cast<char*>(mem) + table_bytes);
@@ -260,6 +298,7 @@ hipError_t run(const fw_chain_batch* b, uint32_t n_chains, Config cfg, hipStream
         else FW_MULTI((k_multi_lds<4, 1024>));
     }
 #undef FW_MULTI
+    if (scratch_mem) return e;
     const hipError_t e2 = hipFreeAsync(mem, s);
     return e != hipSuccess ? e : e2;
 }
@@ -329,6 +368,26 @@ fw_status fw_classify_multi(const fw_chain_batch* batches, uint32_t n_chains,
     if (st != FW_OK) return st;
     const hipError_t e = run(batches, n_chains, cfg, static_cast<hipStream_t>(o.stream));
     if (e != hipSuccess) return hip_fail(e, "multi-chain launch");
+    return FW_OK;
+}
+
+fw_status fw_classify_multi_noalloc(const fw_chain_batch* batches, uint32_t n_chains,
+                                    const fw_multi_opts* opts) {
+    fw_multi_opts o{};
+    if (opts) o = *opts;
+    if (n_chains > kNoAllocMaxChains)
+        return fail(FW_E_INVAL, "fw_classify_multi_noalloc takes at most %u chains (got %u)",
+                    kNoAllocMaxChains, n_chains);
+    fw_status st = check_batches(batches, n_chains);
+    if (st != FW_OK) return st;
+    Config cfg;
+    st = resolve(batches, n_chains, o, &cfg);
+    if (st != FW_OK) return st;
+    void* mem = nullptr;
+    hipError_t e = scratch_address(&mem);
+    if (e != hipSuccess) return hip_fail(e, "looking up the scratch array");
+    e = run(batches, n_chains, cfg, static_cast<hipStream_t>(o.stream), mem);
+    if (e != hipSuccess) return hip_fail(e, "multi-chain launch (no allocation)");
     return FW_OK;
 }
 

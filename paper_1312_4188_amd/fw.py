@@ -110,6 +110,8 @@ SIGNATURES = {
                                         ctypes.c_float, ctypes.c_float, ctypes.c_float]),
     "fw_classify_multi": (ctypes.c_int, [ctypes.POINTER(ChainBatch), _U32,
                                          ctypes.POINTER(MultiOpts)]),
+    "fw_classify_multi_noalloc": (ctypes.c_int, [ctypes.POINTER(ChainBatch), _U32,
+                                                 ctypes.POINTER(MultiOpts)]),
     "fw_autotune_multi": (ctypes.c_int, [ctypes.POINTER(ChainBatch), _U32, _VP,
                                          ctypes.POINTER(MultiOpts),
                                          ctypes.POINTER(ctypes.c_float)]),
@@ -414,13 +416,18 @@ def _chain_array(items):
     return arr
 
 
-def classify_multi(items, stream=None, packets_per_lane=0, placement=0, rule_tile=0):
-    """One persistent launch over many chains; items as for _chain_array (outputs preallocated)."""
+def classify_multi(items, stream=None, packets_per_lane=0, placement=0, rule_tile=0,
+                   no_alloc=False):
+    """One persistent launch over many chains; items as for _chain_array (outputs preallocated).
+    ``no_alloc`` calls fw_classify_multi_noalloc (descriptors in the library's static device
+    array instead of memory allocated for the call)."""
     arr = _chain_array(items)
     for _, pk, oi, oa in items:
         _record_on(stream, pk.fields() + (oi, oa))
     opts = MultiOpts(_stream_ptr(stream), int(packets_per_lane), int(placement), int(rule_tile), 0)
-    _check(load_library().fw_classify_multi(arr, len(items), ctypes.byref(opts)))
+    lib = load_library()
+    fn = lib.fw_classify_multi_noalloc if no_alloc else lib.fw_classify_multi
+    _check(fn(arr, len(items), ctypes.byref(opts)))
 
 
 def autotune_multi(items, stream=None):

@@ -123,6 +123,10 @@ def test_argument_errors(fw):
     assert lib.fw_server_replay(None, 0, None, None, None, None, None, None, None, None) == fw.E_INVAL
     bad = (fw.ChainBatch * 1)()
     assert lib.fw_classify_multi(bad, 1, None) == fw.E_INVAL       # NULL ruleset
+    assert lib.fw_classify_multi_noalloc(bad, 1, None) == fw.E_INVAL
+    many = (fw.ChainBatch * 1025)()
+    assert lib.fw_classify_multi_noalloc(many, 1025, None) == fw.E_INVAL   # over the array
+    assert "1024" in lib.fw_last_error().decode()
     assert lib.fw_classify_multi(None, 0, None) == fw.OK           # nothing to do
     assert lib.fw_autotune_multi(None, 3, None, None, None) == fw.E_INVAL
     # closed loop: NULL packet fields are caught before the slices are offset
