@@ -262,17 +262,24 @@ def serving_leg(seed: int, n_req: int, loads, log_fn):
     ti, out_i = pinned(total, torch.int32)
     ta, out_a = pinned(total, torch.uint8)
     want_i, want_a = serving_oracle(chains, chain, offset, sizes, pool)
-    out = {"chains": build, "requests": n_req, "packets": total, "modes": {}}
+    out = {"chains": build, "requests": n_req, "packets": total, "modes": {},
+           "host": {"logical_cpus": os.cpu_count(),
+                    "usable_cpus": len(os.sched_getaffinity(0))
+                    if hasattr(os, "sched_getaffinity") else None}}
     mean_batch = total / n_req
-    for mode, slots, pipe, workers in (("auto", 8, False, 4), ("auto", 8, False, 1),
-                                       ("auto", 4, False, 4), ("auto", 4, True, 4),
-                                       ("packet_split", 8, False, 4)):
-        with fw.Server(rsets, slots=slots, mode=mode, pipeline=pipe, workers=workers) as sv:
+    for name, mode, slots, ingest in (("learned_copy", "auto", 4, "copy"),
+                                      ("learned_mapped", "auto", 4, "mapped"),
+                                      ("learned_copy_1slot", "auto", 1, "copy"),
+                                      ("packet_split_copy", "packet_split", 4, "copy"),
+                                      ("packet_split_mapped", "packet_split", 4, "mapped")):
+        with fw.Server(rsets, slots=slots, mode=mode, ingest=ingest) as sv:
             zero = np.zeros(n_req)
             sv.replay(zero[:32], chain[:32], offset[:32], sizes[:32], pool, out_i, out_a)
             t = sv.replay(zero, chain, offset, sizes, pool, out_i, out_a)
             peak = total / (t[:, 2].max() - t[:, 0].min()) / 1e6
-            res = {"peak_mpps": peak, "loads": []}
+            res = {"peak_mpps": peak, "loads": [], "slots": slots, "ingest": ingest,
+                   "mode": mode}
+            log_fn(f"  serving {name}: saturated {peak:.0f} Mpps")
             for frac in loads:
                 rate = frac * peak * 1e6 / mean_batch          # requests per second
                 rng = np.random.Generator(np.random.PCG64(seed + int(frac * 1000)))
@@ -284,28 +291,26 @@ def serving_leg(seed: int, n_req: int, loads, log_fn):
                                      "achieved_mpps": total / span / 1e6,
                                      "p50_us": float(np.percentile(lat, 50)),
                                      "p99_us": float(np.percentile(lat, 99))})
-                log_fn(f"  serving {mode} {slots} slots {workers} workers"
-                       f"{' pipeline' if pipe else ''} load {frac:.0%}: "
+                log_fn(f"  serving {name} load {frac:.0%}: "
                        f"p50 {res['loads'][-1]['p50_us']:.0f} us "
                        f"p99 {res['loads'][-1]['p99_us']:.0f} us")
             # the last replay wrote every request's results: each one against the oracle
             res["bit_exact"] = bool(np.array_equal(out_i, want_i) and
                                     np.array_equal(out_a, want_a))
-            log_fn(f"  serving {mode}: every request bit-exact vs the oracle: {res['bit_exact']}")
-            res["slots"], res["pipeline"], res["workers"] = slots, pipe, workers
-            key = (("learned" if mode == "auto" else mode) + ("" if slots == 8 else f"_{slots}slots")
-                   + ("" if workers == 4 else f"_{workers}worker"))
-            out["modes"][key + ("_pipeline" if pipe else "")] = res
+            log_fn(f"  serving {name}: every request bit-exact vs the oracle: {res['bit_exact']}")
+            out["modes"][name] = res
     for rs in rsets:
         rs.close()
     return out
 
 
 def ingest_leg(rs, pk, ref_idx, chunk: int, log_fn):
-    """The whole batch from pinned host memory through the serving runtime: copied in,
-    classified and copied out in chunks of `chunk` packets.  With 8 slots one chunk's copies
-    overlap other chunks' classification; 1 slot runs them back to back.  PCIe-inclusive
-    rate, reported beside the headline (which starts from HBM-resident packets)."""
+    """The whole batch from pinned host memory through the serving runtime: submitted in
+    chunks of `chunk` packets at once, copied in, classified and copied out (copy ingest), or
+    read and written in place by the kernel (mapped ingest).  One chunk per group lets the
+    slots overlap one chunk's copies with another's classification; the default lets a slot
+    take as many chunks as its share of the budget holds.  PCIe-inclusive rate, reported
+    beside the headline (which starts from HBM-resident packets)."""
     import torch
     from paper_1312_4188_amd import fw
     n = len(pk)
@@ -326,18 +331,22 @@ def ingest_leg(rs, pk, ref_idx, chunk: int, log_fn):
     chain = np.zeros(len(sizes), dtype=np.uint32)
     zero = np.zeros(len(sizes))
     out = {"packets": n, "chunk": chunk, "bytes_per_packet": BYTES_PER_PACKET}
-    for slots, pipe in ((1, False), (2, False), (4, False), (8, False), (2, True), (4, True)):
-        with fw.Server([rs], slots=slots, mem_budget=1 << 30, pipeline=pipe, workers=1) as sv:
+    for slots, ingest, group in ((1, "copy", 1), (2, "copy", 1), (4, "copy", 1),
+                                 (4, "copy", 0), (1, "mapped", 1), (4, "mapped", 1),
+                                 (4, "mapped", 0)):
+        with fw.Server([rs], slots=slots, mem_budget=1 << 30, ingest=ingest,
+                       max_group=group) as sv:
             sv.replay(zero[:2], chain[:2], offset[:2], sizes[:2], pool, out_i, out_a)  # warm
             out_i[:] = -2
             t = sv.replay(zero, chain, offset, sizes, pool, out_i, out_a)
             span = float(t[:, 2].max() - t[:, 0].min())
-            name = f"slots_{slots}" + ("_pipeline" if pipe else "")
+            name = f"{ingest}_slots_{slots}" + ("_chunk_per_group" if group == 1 else "")
             out[name] = {"s": span, "mpps": n / span / 1e6,
                          "pcie_gbs": n * BYTES_PER_PACKET / span / 1e9,
                          "same_as_device": bool(np.array_equal(out_i, ref_idx))}
             log_fn(f"  ingest {name}: {n / span / 1e6:.0f} Mpps "
-                   f"({n * BYTES_PER_PACKET / span / 1e9:.1f} GB/s over PCIe)")
+                   f"({n * BYTES_PER_PACKET / span / 1e9:.1f} GB/s over PCIe), "
+                   f"same as device-resident: {out[name]['same_as_device']}")
     return out
 
 
@@ -380,7 +389,10 @@ def scan_configs_leg(seed: int, steps: int, log_fn):
 
 def multichain_leg(seed: int, steps: int, log_fn):
     """64 independent chains (32..8,192 rules, 4,096..1,048,576 packets, log-uniform) in one
-    persistent launch, autotuned, against one packet-split launch per chain."""
+    persistent launch, autotuned, against one packet-split launch per chain; then the same
+    chains with a learned index each (the default placement routes them through the learned
+    lookup), autotuned again.  Every configuration's time, the tuned launch's run-to-run
+    spread, and every chain against the oracle in both phases."""
     import torch
     import oracle
     from synth import gen
@@ -397,36 +409,125 @@ def multichain_leg(seed: int, steps: int, log_fn):
     total = sum(len(it[1]) for it in items)
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
-    best, tuned_ms = fw.autotune_multi(items)
-    log_fn(f"  multichain autotuned {best} ({tuned_ms:.3f} ms)")
+    threads = max(1, min(16, os.cpu_count() or 1))
+    want = [oracle.classify(r, p, threads=threads) for r, p in work]
+    out = {"chains": len(items), "packets": total,
+           "rules_total": int(sum(len(r) for r, _ in work))}
+
+    call = fw.MultiBatch(items)        # marshalled once: the timed calls are the library's
+
+    def phase(name, configs):
+        best, tuned_ms = fw.autotune_multi(items)
+        log_fn(f"  multichain {name}: autotuned {best} ({tuned_ms:.3f} ms)")
+        res = {"tuned": best, "autotune_best_ms": tuned_ms, "configs": {}}
+        for cname, kw in configs.items():
+            ms, _ = time_steps(lambda: call.run(stream=stream, **kw), steps, 2, stream)
+            res["configs"][cname] = {"ms": ms, "mpps": total / ms / 1e3}
+        reps = sorted([res["configs"]["tuned"]["ms"]] +
+                      [time_steps(lambda: call.run(stream=stream), steps, 1, stream)[0]
+                       for _ in range(5)])
+        res["tuned_ms_spread"] = {"min": reps[0], "median": reps[len(reps) // 2],
+                                  "max": reps[-1], "runs": len(reps)}
+        log_fn(f"  multichain {name} tuned: {reps[0]:.3f} / {reps[len(reps) // 2]:.3f} / "
+               f"{reps[-1]:.3f} ms (min / median / max of {len(reps)} runs)")
+        torch.cuda.synchronize()
+        res["bit_exact"] = bool(all(
+            np.array_equal(it[2].cpu().numpy(), w[0]) and np.array_equal(it[3].cpu().numpy(), w[1])
+            for it, w in zip(items, want)))
+        log_fn(f"  multichain {name}: every chain bit-exact vs the oracle: {res['bit_exact']}")
+        return res
+
     configs = {"tuned": {}}
     for K in (1, 2, 4):
+        configs[f"plan_k{K}"] = dict(packets_per_lane=K, placement=4)
         configs[f"scalar_k{K}"] = dict(packets_per_lane=K, placement=1)
         configs[f"vector_k{K}"] = dict(packets_per_lane=K, placement=3)
         configs[f"lds1024_k{K}"] = dict(packets_per_lane=K, placement=2, rule_tile=1024)
-    out = {"chains": len(items), "packets": total,
-           "rules_total": int(sum(len(r) for r, _ in work)), "tuned": best, "configs": {}}
-    for name, kw in configs.items():
-        ms, _ = time_steps(lambda: fw.classify_multi(items, stream=stream, **kw), steps, 2, stream)
-        out["configs"][name] = {"ms": ms, "mpps": total / ms / 1e3}
-    ref = [(it[2].clone(), it[3].clone()) for it in items]
+    out["scan"] = phase("scan", configs)
 
     def per_chain():
         for rs, dp, oi, oa in items:
             rs.classify(dp, mode="packet_split", stream=stream, out_idx=oi, out_act=oa)
     ms, _ = time_steps(per_chain, steps, 2, stream)
-    out["configs"]["one_launch_per_chain"] = {"ms": ms, "mpps": total / ms / 1e3}
-    torch.cuda.synchronize()
-    out["same_as_per_chain"] = bool(all(torch.equal(a, it[2]) and torch.equal(b, it[3])
-                                        for (a, b), it in zip(ref, items)))
-    # the tuned launch's results, chain by chain, against the oracle
-    threads = max(1, min(16, os.cpu_count() or 1))
-    out["bit_exact"] = bool(all(
-        np.array_equal(a.cpu().numpy(), w[0]) and np.array_equal(b.cpu().numpy(), w[1])
-        for (a, b), w in zip(ref, (oracle.classify(r, p, threads=threads) for r, p in work))))
-    log_fn(f"  multichain: every chain bit-exact vs the oracle: {out['bit_exact']}")
+    out["scan"]["configs"]["one_launch_per_chain"] = {"ms": ms, "mpps": total / ms / 1e3}
+
+    t0 = time.perf_counter()
+    for k, rs in enumerate(rss):
+        rs.build_learned_index(seed=seed + k)
+    out["index_build_s"] = time.perf_counter() - t0
+    out["learned"] = phase("learned", {"tuned": {}, **{f"plan_k{K}": dict(packets_per_lane=K,
+                                                                          placement=4)
+                                                       for K in (1, 2, 4)}})
+
+    def per_chain_learned():
+        for rs, dp, oi, oa in items:
+            rs.classify(dp, mode="learned", stream=stream, out_idx=oi, out_act=oa)
+    ms, _ = time_steps(per_chain_learned, steps, 2, stream)
+    out["learned"]["configs"]["one_launch_per_chain"] = {"ms": ms, "mpps": total / ms / 1e3}
     for rs in rss:
         rs.close()
+    return out
+
+
+def network_gain_leg(seed: int, steps: int, n_packets: int, log_fn):
+    """What the trained network gains (trained / untrained network / no network / plain scan)
+    on indexes of other sizes than the headline's: the 50,000-rule serving chain as generated
+    (it reaches a rule matching every packet early, so its index is small) and the same
+    chain with every rule's destination specified (no such rule: the boundary array, tens
+    of thousands of entries, is searched in global memory).  Per variant: mean window,
+    interval lookup ns per key, end-to-end Mpps; every variant's output equals the plain
+    scan's on the whole batch and the oracle's on a 200,000-packet sample."""
+    import torch
+    import oracle
+    from synth import gen
+    from paper_1312_4188_amd import fw
+    out = {}
+    stream = torch.cuda.current_stream()
+    for name, all_dst in (("50000_rules_as_generated", False),
+                          ("50000_rules_every_destination", True)):
+        rules = gen.serving_chains(seed)[2]
+        if all_dst:
+            rules.dst_plen[rules.dst_plen == 0] = 16
+        pk = gen.make_packets(rules, n_packets, seed)
+        n = len(pk)
+        rng = np.random.Generator(np.random.PCG64(seed + 5))
+        sample = np.sort(rng.choice(n, min(n, 200_000), replace=False))
+        want = oracle.classify(rules, pk.subset(sample), threads=max(1, min(16, os.cpu_count() or 1)))
+        dp = fw.DevicePackets.from_host(pk)
+        oi = torch.empty(n, dtype=torch.int32, device="cuda")
+        oa = torch.empty(n, dtype=torch.uint8, device="cuda")
+        res = {"rules": len(rules), "packets": n}
+        with fw.Ruleset(rules) as rs, fw.Ruleset(rules) as rs_un:
+            st = rs.build_learned_index(seed=seed)
+            st_un = rs_un.build_learned_index(seed=seed, train=False)
+            M = st["n_boundaries"]
+            res["boundaries"] = M
+            res["boundaries_in_lds"] = M * 4 <= 80 * 1024
+            ms_scan, _ = time_steps(lambda: rs.classify(dp, mode="packet_split", stream=stream,
+                                                        out_idx=oi, out_act=oa), steps, 2, stream)
+            ref = (oi.cpu().numpy(), oa.cpu().numpy())
+            exact = bool(np.array_equal(ref[0][sample], want[0]) and
+                         np.array_equal(ref[1][sample], want[1]))
+            res["scan"] = {"mpps": n / ms_scan / 1e3, "bit_exact": exact}
+            for vname, ruleset, lookup, stats in (("trained", rs, 0, st),
+                                                  ("untrained", rs_un, 0, st_un),
+                                                  ("no_network", rs, 1, st)):
+                ms, _ = time_steps(lambda: ruleset.classify(dp, mode="learned", lookup=lookup,
+                                                            stream=stream, out_idx=oi, out_act=oa),
+                                   steps, 2, stream)
+                same = bool(np.array_equal(oi.cpu().numpy(), ref[0]) and
+                            np.array_equal(oa.cpu().numpy(), ref[1]))
+                ms_l, _ = time_steps(lambda: ruleset.lookup_intervals(dp.dst_ip, lookup=lookup,
+                                                                      stream=stream),
+                                     steps, 2, stream)
+                res[vname] = {"mean_window": (2 * stats["err_mean"] + 1) if lookup == 0 else M,
+                              "lookup_ns_per_packet": ms_l * 1e6 / n, "mpps": n / ms / 1e3,
+                              "bit_exact": bool(same and exact)}
+                log_fn(f"  gain {name} {vname}: window {res[vname]['mean_window']:.1f}, "
+                       f"lookup {ms_l * 1e6 / n:.4f} ns/key, {n / ms / 1e3:.0f} Mpps, "
+                       f"exact {res[vname]['bit_exact']}")
+            log_fn(f"  gain {name} scan: {n / ms_scan / 1e3:.0f} Mpps (|B| = {M})")
+        out[name] = res
     return out
 
 
@@ -481,6 +582,8 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=600,
                     help="requests per offered load in the serving leg (0 = skip it)")
     ap.add_argument("--no-multichain", action="store_true", help="skip the 64-chain leg")
+    ap.add_argument("--no-gain", action="store_true",
+                    help="skip the network-gain leg on the 50,000-rule indexes")
     ap.add_argument("--no-scan-configs", action="store_true",
                     help="skip the 100x10k and 1000x1M plain-scan leg")
     ap.add_argument("--no-ingest", action="store_true",
@@ -512,6 +615,7 @@ def main():
     t0 = time.perf_counter()
     index_stats = rs.build_learned_index(seed=args.seed)
     index_stats["build_s"] = time.perf_counter() - t0
+    rs_plain = fw.Ruleset(rules)          # no index: mode AUTO picks a scan form by batch size
     rs_un = fw.Ruleset(rules)
     log("building the learned index (untrained network)")
     untrained_stats = rs_un.build_learned_index(seed=args.seed, train=False)
@@ -524,7 +628,8 @@ def main():
              "packet_split_k1": (rs, dict(mode="packet_split", packets_per_lane=1)),
              "packet_split_k2": (rs, dict(mode="packet_split", packets_per_lane=2)),
              "rule_split_p16": (rs, dict(mode="rule_split", partitions=16)),
-             "hybrid_p16": (rs, dict(mode="hybrid", partitions=16))}
+             "hybrid_p16": (rs, dict(mode="hybrid", partitions=16)),
+             "auto_no_index": (rs_plain, dict(mode="auto"))}
     if args.modes:
         keep = args.modes.split(",")
         modes = {k: modes[k] for k in keep}
@@ -576,7 +681,8 @@ def main():
     k_star = int(np.argmax(full)) if full.any() else None   # first catch-all rule
 
     latency = {}
-    for name in [m for m in ("learned", "packet_split", "rule_split_p16", "hybrid_p16")
+    for name in [m for m in ("learned", "packet_split", "rule_split_p16", "hybrid_p16",
+                             "auto_no_index")
                  if m in modes and args.latency_batches > 0]:
         ruleset, kw = modes[name]
         log(f"latency {name}")
@@ -658,6 +764,11 @@ def main():
         log("multi-chain leg")
         multichain = multichain_leg(args.seed, max(3, args.steps // 2), log)
 
+    gain_configs = None
+    if not args.no_gain:
+        log("network gain on the 50,000-rule indexes")
+        gain_configs = network_gain_leg(args.seed, max(3, args.steps // 2), 4_194_304, log)
+
     cpu = None
     oracle_exact, checked = None, 0
     if not args.no_cpu:
@@ -689,6 +800,7 @@ def main():
         "modes": results, "latency": latency,
         "scan_rule_checks": checks, "learned_candidate_checks": work["candidate_checks"],
         "index": index_stats, "index_untrained": untrained_stats, "network_gain": gain,
+        "network_gain_other_indexes": gain_configs,
         "roofline": roofline, "roofline_binary_search": roofline_bs,
         "scan_roofline": scan_roofline, "serving": serving,
         "multichain": multichain, "ingest": ingest, "scan_configs": scan_configs,
@@ -696,13 +808,15 @@ def main():
     }
     rs.close()
     rs_un.close()
+    rs_plain.close()
     for name, lat in latency.items():
         log(f"closed-loop latency {name}: p50 {lat['p50_us']:.1f} us, p99 {lat['p99_us']:.1f} us")
     if serving:
         for name, m in serving["modes"].items():
-            top = m["loads"][-1] if m["loads"] else {}
+            by = {ld["offered_frac"]: ld for ld in m["loads"]}
+            p = lambda f: by.get(f, {}).get("p99_us", float("nan"))
             log(f"serving {name}: peak {m['peak_mpps']:.0f} Mpps, bit-exact {m.get('bit_exact')}, "
-                f"p99 at {top.get('offered_frac', 0):.0%} load {top.get('p99_us', float('nan')):.0f} us")
+                f"p99 at 70% / 100% / 120% load {p(0.7):.0f} / {p(1.0):.0f} / {p(1.2):.0f} us")
     log(f"headline {head}: {line['value']:.0f} Mpps, bit-exact vs oracle {oracle_exact} "
         f"({checked} packets)")
     print(json.dumps(line), flush=True)

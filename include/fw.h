@@ -66,7 +66,12 @@ typedef enum fw_status {
 typedef enum fw_action { FW_DROP = 0, FW_ACCEPT = 1 } fw_action;
 
 typedef enum fw_mode {
-    FW_MODE_AUTO = 0,          /* learned index when built, else packet split */
+    FW_MODE_AUTO = 0,          /* learned index when built; else by batch size: packet
+                                  split from 262,144 packets, below that rule split over 64
+                                  partitions for batches up to 4,096 packets with at least
+                                  2,048 reachable rules, else the hybrid over 16 partitions
+                                  (the split forms wait for a fraction of the rule list per
+                                  packet, which is what a small batch's latency needs) */
     FW_MODE_PACKET_SPLIT = 1,  /* data-parallel scan (paper Section IV-A) */
     FW_MODE_RULE_SPLIT = 2,    /* function-parallel scan (paper Section IV-B) */
     FW_MODE_LEARNED = 3,       /* learned destination index + candidate scan */
@@ -116,7 +121,7 @@ typedef struct fw_classify_opts {
                                   split ignores it); 0 = library default: the most (up to 4
                                   for packet split, 2 for learned) that still gives the
                                   launch 8,192 waves, so small batches use fewer per lane;
-                                  hybrid: 4 from 2,097,152 packets up, else 1 */
+                                  hybrid: 1 while n * partitions / 64 <= 8,192, else 4 */
     uint64_t *window_misses;   /* learned mode, optional HOST pointer: the call's statistics.
                                   When given, the call counts in memory of its own how many
                                   packets' error window missed (they fell back to a full
@@ -322,10 +327,16 @@ typedef struct fw_chain_batch {
 
 typedef struct fw_multi_opts {
     void *stream;              /* hipStream_t; NULL = null stream */
-    uint32_t packets_per_lane; /* 1, 2 or 4; 0 = tuned choice for this batch shape, else 4 */
-    uint32_t placement;        /* 0 = tuned (else scalar), 1 = rules through the scalar
-                                  cache, 2 = rules staged in LDS tiles, 3 = rules read
-                                  by vector loads (every lane the same address) */
+    uint32_t packets_per_lane; /* 1, 2 or 4; 0 = tuned choice for this batch shape, else 2 */
+    uint32_t placement;        /* 0 = tuned (else 4); 4 = each chain as fw_classify_ex
+                                  classifies a large batch in mode AUTO: through its learned
+                                  index when one is built, else the packet-split scan of its
+                                  rules grouped by first test and cut at the first rule that
+                                  matches every packet.  The plain rule list in rule order
+                                  (the paper's Section IV-A placement study): 1 = rules
+                                  through the scalar cache, 2 = rules staged in LDS tiles,
+                                  3 = rules read by vector loads (every lane the same
+                                  address) */
     uint32_t rule_tile;        /* LDS tile in rules: 256 or 1024; 0 = tuned or 1024 */
     uint32_t _reserved;
 } fw_multi_opts;
@@ -340,7 +351,7 @@ fw_status fw_classify_multi(const fw_chain_batch *batches, uint32_t n_chains,
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * launch as fw_classify_multi with the same options and results, but its
  * chain descriptor table and work-queue counter live in a static device array
- * the library holds on each GPU it runs on (about 97 KiB, kept until the
+ * the library holds on each GPU it runs on (about 80 KiB, kept until the
  * process ends) instead of memory allocated for the call.  It calls no
  * hipMalloc, hipFree or other device-allocating routine; the array's address
  * is looked up once per device on the first call there.  Every call on one
@@ -364,32 +375,40 @@ fw_status fw_autotune_multi(const fw_chain_batch *batches, uint32_t n_chains, vo
 /* ------------------------------------------------------------------ serving
  * Not in the paper (its Section V names asynchronous launches as future
  * work).  A server keeps rulesets resident and classifies packet batches that
- * arrive over time with continuous batching: up to `slots` requests are in
- * flight at once, each on its own HIP stream, and a request is admitted as
- * soon as a slot is free and its device memory fits in the server's budget;
- * queued requests are admitted in arrival order.  Each request's result is the
- * same as classifying it alone. */
+ * arrive over time with continuous batching.  Each of `slots` host threads
+ * owns a HIP stream; a free slot admits, in arrival order, every queued
+ * request that fits its share of the memory budget (up to max_group
+ * requests) as one group, and classifies the whole group with one
+ * multi-chain launch (one entry per request: the chain's learned index where
+ * one is built, else the packet-split scan of its grouped rule list).  Each
+ * request's result is the same as classifying it alone. */
 
 typedef struct fw_server fw_server;
 
 typedef struct fw_server_opts {
-    uint32_t slots;         /* requests in flight at once, 1..64; 0 = 8 */
-    uint32_t mode;          /* fw_mode used for every request (AUTO picks per chain) */
-    uint32_t partitions;    /* for rule split / hybrid; 0 = 16 */
-    uint32_t pipeline;      /* 0: each request copies in and out on its own slot's stream;
-                               1: all copies in go through one shared stream and all copies
-                               out through another, in admission order, chained to the
-                               slots' classification by events (copies never compete with
-                               each other, and still overlap other requests' compute) */
-    uint64_t mem_budget;    /* device bytes for in-flight packets and results; 0 = 256 MiB */
-    uint32_t workers;       /* host threads that issue requests, 1..16, each owning an equal
-                               share of the slots and admitting from the one arrival-order
-                               queue; 0 = 4; never more than `slots` */
-    uint32_t _reserved;
+    uint32_t slots;         /* groups in flight at once, each with its own host thread and HIP
+                               stream, 1..16; 0 = 4 (the hardware queues a process gets) */
+    uint32_t mode;          /* FW_MODE_AUTO (learned index where built, else the grouped scan),
+                               FW_MODE_PACKET_SPLIT (indexes ignored) or FW_MODE_LEARNED (every
+                               chain must have an index: FW_E_NOINDEX otherwise) */
+    uint32_t max_group;     /* requests coalesced into one launch, 1..1024; 0 = 1024 */
+    uint32_t ingest;        /* 0 = copies: a group's requests under 4,096 packets are packed
+                               into page-locked staging and moved by one copy per field, the
+                               larger ones copied straight from and to their own buffers
+                               (any host memory works; page-locked memory copies fastest);
+                               1 = mapped: every buffer given to the server is page-locked
+                               host memory mapped into the device's address space (from
+                               hipHostMalloc, as torch's pinned memory is) and 16-byte aligned;
+                               the kernel reads the packets and writes the results in place */
+    uint64_t mem_budget;    /* bytes of packets and results in flight (18 per packet, each
+                               request rounded up to 16 packets, each array to 256 bytes);
+                               with copies it is also the device memory and the page-locked
+                               staging the server holds; 0 = 256 MiB */
+    uint32_t _reserved[2];
 } fw_server_opts;
 
-/* A batch of packet headers in HOST memory (structure of arrays).  Page-locked
- * memory (hipHostMalloc) gives asynchronous copies; pageable memory works. */
+/* A batch of packet headers in HOST memory (structure of arrays): any host
+ * memory with copy ingest, page-locked mapped memory with mapped ingest. */
 typedef struct fw_host_packets {
     const uint32_t *src_ip;
     const uint32_t *dst_ip;
@@ -403,17 +422,19 @@ typedef struct fw_request_times {
     double submit, admit, done;
 } fw_request_times;
 
-/* Start a server over `n_chains` loaded rulesets (they must outlive it; a
- * learned index built before the server starts is used by mode AUTO/LEARNED).
- * Errors: FW_E_INVAL (no chains, NULL chain, bad options), FW_E_NOMEM,
- * FW_E_DEVICE. */
+/* Start a server over `n_chains` loaded rulesets (they must outlive it; mode
+ * AUTO uses the learned index a chain has when a group is launched).
+ * Errors: FW_E_INVAL (no chains, NULL chain, bad options, a mode other than
+ * AUTO, PACKET_SPLIT or LEARNED), FW_E_NOINDEX (mode LEARNED and a chain
+ * without an index), FW_E_NOMEM, FW_E_DEVICE. */
 fw_status fw_server_create(fw_ruleset *const *chains, uint32_t n_chains,
                            const fw_server_opts *opts, fw_server **out);
 
 /* Queue `n` packets (host memory) for chain `chain`; results go to the HOST
  * arrays out_rule_idx / out_action.  All buffers must stay valid until
  * fw_server_wait returns for *ticket.  FW_E_NOMEM if the request alone
- * exceeds the memory budget (it could never be admitted). */
+ * exceeds the memory budget (it could never be admitted); FW_E_ALIGN with
+ * mapped ingest for a buffer that is not 16-byte aligned. */
 fw_status fw_server_submit(fw_server *sv, uint32_t chain, const fw_host_packets *pk, size_t n,
                            int32_t *out_rule_idx, uint8_t *out_action, uint64_t *ticket);
 

@@ -24,6 +24,8 @@ struct fw_ruleset {
     std::vector<fw::RuleRec> h_rules;        // host copy of the compiled records
     std::vector<fw_rule> source;             // the rules as given
     fw::LearnedIndex* index = nullptr;       // null until built
+    fw::ChainView h_view{};                  // what the multi-chain kernels read ...
+    fw::ChainView* d_view = nullptr;         // ... and its device copy
 };
 
 namespace fw {
@@ -88,12 +90,16 @@ PacketsDev to_dev(const fw_packets* pk) {
     return PacketsDev{pk->src_ip, pk->dst_ip, pk->src_port, pk->dst_port, pk->proto};
 }
 
-void ruleset_view(const fw_ruleset* rs, const RuleRec** rules, const uint2** pairs,
-                  uint32_t* n_rules, uint8_t* default_action) {
-    *rules = rs->d_rules;
-    *pairs = rs->d_pairs;
-    *n_rules = rs->n_rules;
-    *default_action = rs->default_action;
+const ChainView* ruleset_chain_view(const fw_ruleset* rs, const ChainView** host) {
+    if (host) *host = &rs->h_view;
+    return rs->d_view;
+}
+
+// Write the ruleset's ChainView to its device copy.  Callers make sure no
+// kernel is reading it (at load nothing can; an index build waits for the
+// device first).
+static hipError_t upload_view(fw_ruleset* rs) {
+    return hipMemcpy(rs->d_view, &rs->h_view, sizeof(ChainView), hipMemcpyHostToDevice);
 }
 
 // Packets per lane when the caller leaves it to the library: the most (up to
@@ -105,11 +111,35 @@ static uint32_t default_packets_per_lane(size_t n, uint32_t most) {
     return k;
 }
 
-// Hybrid default: four packets per lane once a batch fills 8,192 waves with
-// them (measured fastest on large batches; two measured slower than one), one
-// below that, where the batch's latency matters more.
-static uint32_t hybrid_packets_per_lane(size_t n) {
-    return n >= size_t(8192) * 64u * 4u ? 4u : 1u;
+// Hybrid default: one packet per lane while the batch's waves (P per 64
+// packets) fit the GPU at once, about 8,192 of them; four above that, where
+// fewer, longer waves finish sooner (measured at 10,000 and 1,000 rules: at
+// 65,536 packets and 16 partitions four per lane take 52 us against 61 us for
+// one, at 16,384 packets one takes 29 us against 51 us).
+static uint32_t hybrid_packets_per_lane(size_t n, uint32_t partitions) {
+    return double(n) * partitions / 64.0 <= 8192.0 ? 1u : 4u;
+}
+
+// Mode AUTO without a learned index, by batch size (closed-loop latencies
+// measured on one MI355X, 64 to 1,048,576 packets at 1,000 and 10,000 rules):
+// packet split from 262,144 packets, where the batch fills the GPU and its
+// total work is the least; below that the split forms, whose waves share the
+// rule list, so a packet waits for a fraction of the reachable rules instead
+// of all of them: rule split over 64 partitions for batches up to 4,096
+// packets when at least 2,048 rules are reachable (20-28 us at 10,000 rules
+// against 28-29 us for the hybrid and 88-89 us for packet split), the hybrid
+// over 16 partitions otherwise (at 65,536 packets 52 us against 90 us).
+struct AutoChoice {
+    uint32_t mode, partitions;
+};
+constexpr size_t kAutoScanFrom = 262144;
+constexpr size_t kAutoRuleSplitUpTo = 4096;
+constexpr uint32_t kAutoRuleSplitRules = 2048;
+static AutoChoice auto_scan_mode(size_t n, uint32_t reachable) {
+    if (n >= kAutoScanFrom) return {FW_MODE_PACKET_SPLIT, 0u};
+    if (n <= kAutoRuleSplitUpTo && reachable >= kAutoRuleSplitRules)
+        return {FW_MODE_RULE_SPLIT, 64u};
+    return {FW_MODE_HYBRID, 16u};
 }
 
 // A device fault in earlier asynchronous work is sticky; report it before new work.
@@ -166,7 +196,18 @@ fw_status fw_load_ruleset(const fw_rule* rules, uint32_t n_rules, uint8_t defaul
         e = hipMemcpy(rs->d_pairs, pairs.data(), sizeof(uint2) * pairs.size(),
                       hipMemcpyHostToDevice);
     if (e == hipSuccess) e = make_plan(rs->h_rules.data(), n_rules, &rs->plan);
+    if (e == hipSuccess) {
+        ChainView& v = rs->h_view;
+        v.rules = rs->d_rules;
+        v.pairs = rs->d_pairs;
+        v.n_rules = n_rules;
+        v.dflt = default_action;
+        v.plan = rs->plan.plan;
+        e = hipMalloc(&rs->d_view, sizeof(ChainView));
+    }
+    if (e == hipSuccess) e = upload_view(rs);
     if (e != hipSuccess) {
+        if (rs->d_view) (void)hipFree(rs->d_view);
         if (rs->d_rules) (void)hipFree(rs->d_rules);
         if (rs->d_pairs) (void)hipFree(rs->d_pairs);
         free_plan(&rs->plan);
@@ -183,7 +224,8 @@ fw_status fw_free_ruleset(fw_ruleset* rs) {
     destroy_index(rs->index);
     rs->index = nullptr;
     free_plan(&rs->plan);
-    for (void* p : {static_cast<void*>(rs->d_rules), static_cast<void*>(rs->d_pairs)}) {
+    for (void* p : {static_cast<void*>(rs->d_rules), static_cast<void*>(rs->d_pairs),
+                    static_cast<void*>(rs->d_view)}) {
         if (!p) continue;
         const hipError_t e2 = hipFree(p);
         if (e == hipSuccess) e = e2;
@@ -221,11 +263,19 @@ fw_status fw_classify_ex(const fw_ruleset* rs, const fw_packets* pk, size_t n,
     hipStream_t stream = static_cast<hipStream_t>(o.stream);
     const PacketsDev pd = to_dev(pk);
     uint32_t mode = o.mode;
-    if (mode == FW_MODE_AUTO) mode = rs->index ? FW_MODE_LEARNED : FW_MODE_PACKET_SPLIT;
     // the split forms partition the rules up to and including the first catch-all: later
     // rules can never be a first match
     const uint32_t reachable =
         rs->plan.plan.tail_idx == kNoMatch ? rs->n_rules : rs->plan.plan.tail_idx + 1u;
+    if (mode == FW_MODE_AUTO) {
+        if (rs->index) {
+            mode = FW_MODE_LEARNED;
+        } else {
+            const AutoChoice c = auto_scan_mode(n, reachable);
+            mode = c.mode;
+            if (c.partitions) P = c.partitions;
+        }
+    }
     hipError_t e = hipSuccess;
     switch (mode) {
         case FW_MODE_PACKET_SPLIT:
@@ -243,7 +293,7 @@ fw_status fw_classify_ex(const fw_ruleset* rs, const fw_packets* pk, size_t n,
             e = launch_hybrid(rs->d_pairs, rs->d_rules, reachable, P, pd, n, out_rule_idx,
                               out_action, rs->default_action,
                               o.packets_per_lane ? int(o.packets_per_lane)
-                                                 : int(hybrid_packets_per_lane(n)),
+                                                 : int(hybrid_packets_per_lane(n, P)),
                               stream);
             break;
         case FW_MODE_LEARNED:
@@ -302,15 +352,24 @@ fw_status fw_build_learned_index(fw_ruleset* rs, const fw_index_opts* opts,
     const fw_status st = build_index(rs->source.data(), rs->h_rules.data(), rs->n_rules, o,
                                      stats, &built);
     if (st != FW_OK) return st;
-    if (rs->index) {
-        // classifications enqueued earlier may still read the old index
-        const hipError_t e = hipDeviceSynchronize();
-        if (e != hipSuccess) {
-            destroy_index(built);
-            return hip_fail(e, "waiting for work on the previous index");
-        }
-        destroy_index(rs->index);
+    // classifications enqueued earlier may still read the old index or the ruleset's view
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        destroy_index(built);
+        return hip_fail(e, "waiting for work on the previous index");
     }
+    ChainView v = rs->h_view;
+    index_chain_view(built, &v);
+    const ChainView old_view = rs->h_view;
+    rs->h_view = v;
+    e = upload_view(rs);
+    if (e != hipSuccess) {
+        rs->h_view = old_view;
+        (void)upload_view(rs);
+        destroy_index(built);
+        return hip_fail(e, "publishing the learned index");
+    }
+    if (rs->index) destroy_index(rs->index);
     rs->index = built;
     return FW_OK;
 }

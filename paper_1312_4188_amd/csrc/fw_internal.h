@@ -6,30 +6,9 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "host_types.h"
+
 namespace fw {
-
-// Extra first-test pairs allocated past the end of every pair array, so a
-// scan can fetch the block after the last one without a bounds test.
-constexpr uint32_t kPairPadding = 8;
-
-// A compiled rule as the kernels read it: 32 bytes, every field a range test
-// (v - lo) <= w in unsigned arithmetic, so a prefix (base, len) becomes
-// lo = base with the low 32-len bits cleared and w = 2^(32-len) - 1.
-//   port_lo = sport_lo << 16 | dport_lo,  port_w = sport_w << 16 | dport_w
-//   proto   = proto_lo | proto_w << 8 | action << 16   (any protocol: lo 0, w 255)
-//   idx     = the rule's position in the original list
-struct alignas(32) RuleRec {
-    uint32_t src_lo, src_w;
-    uint32_t dst_lo, dst_w;
-    uint32_t port_lo, port_w;
-    uint32_t proto;
-    uint32_t idx;
-};
-static_assert(sizeof(RuleRec) == 32, "rule record must stay 32 bytes");
-
-constexpr uint32_t kNoMatch = 0xFFFFFFFFu;
-constexpr uint32_t kMaxRules = 1u << 24;
-constexpr uint32_t kMaxPartitions = 65536;
 
 // A rule list cut at its first catch-all and split into up to four groups by
 // the field each rule is tested on first (the most selective one): the
@@ -39,7 +18,6 @@ constexpr uint32_t kMaxPartitions = 65536;
 // rule's position in the original list).  Rules after the first catch-all can
 // never be a first match and are dropped; the catch-all itself becomes the
 // `tail`, the answer for packets no earlier rule matches.
-enum FirstTest : uint32_t { kFirstDst = 0, kFirstSrc = 1, kFirstPorts = 2, kFirstProto = 3 };
 
 struct ScanGroup {
     const uint2* pairs;

@@ -66,30 +66,6 @@ constexpr uint32_t kRowInvSpan = 66;  // ExpertMeta::inv_span
 constexpr uint32_t kRowPosSpan = 67;  // ExpertMeta::pos_span
 constexpr uint32_t kRowDwords = 68;   // stage-2 row stride (a 16-byte multiple)
 
-// Port/protocol table of the first (up to 64) candidates that leave both
-// addresses unspecified: such a rule matches a packet exactly when both of
-// its port ranges and its protocol test pass.  Per port field, the rules'
-// range ends cut [0, 65535] into elementary intervals (each range is a union
-// of whole intervals) and interval i carries the 64-bit mask of the rules
-// whose range contains it; the protocol gets a mask per value.  The AND of
-// the packet's three masks is the set of these rules it matches, and the
-// lowest set bit is the first of them (bits follow rule order).  A port's
-// interval is found from a 256-entry table on its high byte plus at most
-// `steps` forward steps.  Fixed size, so it is staged into LDS as one block.
-constexpr uint32_t kPtRules = 64;
-constexpr uint32_t kPtMaxIv = 2 * kPtRules + 2;       // intervals per port field, rounded up
-struct alignas(16) PortTable {
-    uint64_t mask_p[256];           // per protocol value
-    uint64_t mask_s[kPtMaxIv];      // per source-port interval
-    uint64_t mask_d[kPtMaxIv];      // per destination-port interval
-    uint32_t b_s[kPtMaxIv + 2];     // interval starts; unused entries (and one past the last) 0x10000
-    uint32_t b_d[kPtMaxIv + 2];
-    uint32_t rule[kPtRules + 4];    // bit r -> rule index | action << 24; entry kPtRules = none
-    uint8_t bucket_s[256];          // interval holding port h << 8
-    uint8_t bucket_d[256];
-};
-static_assert(sizeof(PortTable) % 16 == 0, "staged as 16-byte words");
-constexpr uint32_t kPtNone = 0xFFFFFFFFu;
 
 // The per-lane lists are read with 32-bit buffer offsets: each list array is
 // kept below kMaxListBytes, and kListPastEnd (above it) marks a lane with
@@ -173,6 +149,24 @@ struct LookupArgs {
     uint32_t use_net;         // 0: full binary search only
     unsigned long long* miss; // optional window-miss counter
 };
+
+// What the multi-chain kernels read of one ruleset: one per ruleset in device
+// memory, written at load and rewritten when the learned index is built.
+struct ChainView {
+    const RuleRec* rules;   // the compiled list in rule order
+    const uint2* pairs;     // destination (lo, w) per rule, padded by kPairPadding
+    uint32_t n_rules;
+    uint32_t dflt;          // default action
+    uint32_t has_index;     // `la` describes a built learned index
+    uint32_t lds_b;         // bytes of its LDS image with the boundary arrays (image[1])
+    uint32_t lds_nob;       // bytes of its LDS image without them (image[0])
+    uint32_t pad;
+    ScanPlan plan;          // grouped scan plan (packet split)
+    LookupArgs la;          // the learned lookup: network + error window, no miss counting
+};
+
+// The learned part of a ruleset's ChainView.
+void index_chain_view(const LearnedIndex* ix, ChainView* v);
 
 // ---- training kernels (rmi.hip)
 hipError_t launch_fwd_bwd(const float* params, uint32_t H, const float* u, const float* t,

@@ -5,24 +5,10 @@
 #include <vector>
 
 #include "fw_internal.h"
+#include "lists.h"
 
 namespace fw {
 namespace {
-
-bool is_catch_all(const RuleRec& q) {
-    return q.src_w == 0xFFFFFFFFu && q.dst_w == 0xFFFFFFFFu && q.port_lo == 0 &&
-           q.port_w == 0xFFFFFFFFu && ((q.proto >> 8) & 0xFFu) == 255u;
-}
-
-// The most selective field of a rule that is not a catch-all: the narrower
-// address prefix if either address is specified (destination on a tie), else
-// the ports if either is specified, else the protocol.
-uint32_t first_test(const RuleRec& q) {
-    if (q.dst_w != 0xFFFFFFFFu || q.src_w != 0xFFFFFFFFu)
-        return q.dst_w <= q.src_w ? kFirstDst : kFirstSrc;
-    if (!(q.port_lo == 0 && q.port_w == 0xFFFFFFFFu)) return kFirstPorts;
-    return kFirstProto;
-}
 
 uint2 first_pair(const RuleRec& q, uint32_t kind) {
     switch (kind) {
@@ -37,17 +23,12 @@ uint2 first_pair(const RuleRec& q, uint32_t kind) {
 
 hipError_t make_plan(const RuleRec* recs, uint32_t n, DevicePlan* out) {
     *out = DevicePlan{};
-    std::vector<RuleRec> grp[4];
+    PlanGroups pg;
+    group_rules(recs, n, &pg);
+    const auto& grp = pg.grp;
     ScanPlan plan{};
-    plan.tail_idx = kNoMatch;
-    for (uint32_t r = 0; r < n; ++r) {
-        if (is_catch_all(recs[r])) {
-            plan.tail_idx = recs[r].idx;
-            plan.tail_act = (recs[r].proto >> 16) & 1u;
-            break;
-        }
-        grp[first_test(recs[r])].push_back(recs[r]);
-    }
+    plan.tail_idx = pg.tail_idx;
+    plan.tail_act = pg.tail_act;
     // one allocation: per group, records then padded pairs, each section 256-B aligned
     auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
     size_t bytes = 0;

@@ -1,24 +1,30 @@
 // Serving runtime: resident rulesets, continuous batching of arriving packet
-// batches over several HIP streams, admission by a device-memory budget.
+// batches, admission by a memory budget.
 //
-// Worker threads (four by default) own the device side, each an equal share
-// of the slots.  A request waits in one FIFO queue until a worker has a
-// slot (stream) free and the arena can hold its packets and results; it is
-// then copied in, classified and copied out by that worker, and an event
-// marks its completion.  Several workers issue the HIP calls of different
-// requests in parallel (per-request host work is what bounds throughput for
-// small requests).  Requests on different slots overlap on the device; each
-// is classified exactly as it would be alone.  Copies run either on the
-// request's slot stream, or (pipeline mode) on one shared upload stream and
-// one shared download stream in admission order, with events ordering
-// upload -> classification (slot stream) -> download.
+// Each slot is one host thread with one HIP stream.  A slot that is free
+// admits, in arrival order, every queued request that fits the slot's share
+// of the budget (and the largest free block of the arena), up to max_group
+// requests: a group.  The group is classified by one multi-chain launch with
+// one entry per request (the chain's learned index where one is built, else
+// its grouped scan plan), so per-request host work is a descriptor, not a
+// launch.  Packets reach the GPU one of two ways:
+//  - copy ingest: the group's small requests are packed into page-locked
+//    staging and moved by one copy per packet field, the large ones by their
+//    own copies straight from their buffers (each request at a 16-packet
+//    boundary of the group's device block); the results come back the same
+//    way;
+//  - mapped ingest: the caller's buffers are page-locked host memory mapped
+//    into the device's address space, and the kernel reads the packets and
+//    writes the results in place over PCIe, with no copies at all.
+// Groups on different slots overlap on the device; each request's result is
+// the same as classifying it alone (classification is per packet).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
-#include <map>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -28,10 +34,13 @@
 #include <vector>
 
 #include "../../include/fw.h"
+#include "arena.h"
 #include "index.h"
+#include "multi.h"
 
 namespace fw {
 extern thread_local std::string g_last_error;
+const ChainView* ruleset_chain_view(const fw_ruleset* rs, const ChainView** host);
 
 namespace {
 
@@ -41,47 +50,24 @@ double now_s() {
 }
 
 size_t round256(size_t x) { return (x + 255) & ~size_t(255); }
+size_t round16(size_t x) { return (x + 15) & ~size_t(15); }
 
-// Device bytes of one request: five packet arrays and two result arrays, each 256-B aligned.
-size_t request_bytes(size_t n) {
-    return round256(4 * n) * 2 + round256(2 * n) * 2 + round256(n) + round256(4 * n) +
-           round256(n);
-}
-
-// First-fit allocator over [0, size) with coalescing frees.
-class Arena {
-   public:
-    explicit Arena(size_t size) { free_[0] = size; }
-    bool alloc(size_t need, size_t* off) {
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= need) {
-                *off = it->first;
-                const size_t rest = it->second - need, at = it->first + need;
-                free_.erase(it);
-                if (rest) free_[at] = rest;
-                return true;
-            }
-        }
-        return false;
+// Byte offsets of a group of N packets (N a multiple of 16): the five packet
+// arrays, then the two result arrays, each 256-byte aligned.  [0, in_bytes)
+// is what goes in, [idx, bytes) what comes back.
+struct GroupLayout {
+    size_t src, dst, sp, dp, pr, idx, act, in_bytes, bytes;
+    explicit GroupLayout(size_t N) {
+        src = 0;
+        dst = src + round256(4 * N);
+        sp = dst + round256(4 * N);
+        dp = sp + round256(2 * N);
+        pr = dp + round256(2 * N);
+        idx = pr + round256(N);
+        in_bytes = idx;
+        act = idx + round256(4 * N);
+        bytes = act + round256(N);
     }
-    void release(size_t off, size_t size) {
-        auto it = free_.emplace(off, size).first;
-        auto next = std::next(it);
-        if (next != free_.end() && it->first + it->second == next->first) {
-            it->second += next->second;
-            free_.erase(next);
-        }
-        if (it != free_.begin()) {
-            auto prev = std::prev(it);
-            if (prev->first + prev->second == it->first) {
-                prev->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-
-   private:
-    std::map<size_t, size_t> free_;
 };
 
 struct Request {
@@ -92,158 +78,254 @@ struct Request {
     int32_t* out_idx = nullptr;
     uint8_t* out_act = nullptr;
     fw_request_times times{};
-    int slot = -1;
-    size_t off = 0, bytes = 0;
+    size_t at = 0;   // first packet inside its group (copy ingest)
     fw_status status = FW_OK;
     std::string error;
     bool done = false;
+};
+
+struct Group {
+    std::vector<std::shared_ptr<Request>> reqs;
+    size_t N = 0;               // packets, each request padded to 16
+    size_t off = 0, bytes = 0;  // its block of the arena
 };
 
 }  // namespace
 }  // namespace fw
 
 struct fw_server {
+    struct Slot {
+        hipStream_t stream = nullptr;
+        hipEvent_t done = nullptr;
+        void* d_desc = nullptr;   // descriptor table and counter of its launches
+        void* h_desc = nullptr;   // page-locked staging of the same
+        std::thread thread;
+    };
     std::vector<fw_ruleset*> chains;
     fw_server_opts o{};
     int device = 0;
-    char* arena_base = nullptr;
+    char* d_arena = nullptr;   // copy ingest: packed groups on the device ...
+    char* h_arena = nullptr;   // ... and their page-locked staging, at the same offsets
     std::unique_ptr<fw::Arena> arena;
-    std::vector<hipStream_t> streams;
-    std::vector<hipEvent_t> events;
-    hipStream_t up = nullptr, down = nullptr;        // pipeline mode: shared copy streams
-    std::vector<hipEvent_t> ev_up, ev_comp;          // pipeline mode: per-slot stage events
-    std::vector<std::shared_ptr<fw::Request>> slot_req;   // worker-owned
+    std::vector<Slot> slots;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<std::shared_ptr<fw::Request>> queue;
     std::unordered_map<uint64_t, std::shared_ptr<fw::Request>> reqs;
     uint64_t next_ticket = 1;
     bool stop = false;
-    std::vector<std::thread> workers;
 };
 
 namespace fw {
 namespace {
 
-fw_status launch_request(fw_server* sv, Request& r) {
-    hipStream_t s = sv->streams[r.slot];
-    char* base = sv->arena_base + r.off;
-    const size_t n = r.n;
-    auto* src = reinterpret_cast<uint32_t*>(base);
-    auto* dst = reinterpret_cast<uint32_t*>(base + round256(4 * n));
-    auto* sp = reinterpret_cast<uint16_t*>(base + round256(4 * n) * 2);
-    auto* dp = reinterpret_cast<uint16_t*>(base + round256(4 * n) * 2 + round256(2 * n));
-    auto* pr = reinterpret_cast<uint8_t*>(base + round256(4 * n) * 2 + round256(2 * n) * 2);
-    auto* oi = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(pr) + round256(n));
-    auto* oa = reinterpret_cast<uint8_t*>(reinterpret_cast<char*>(oi) + round256(4 * n));
-    const bool pipe = sv->o.pipeline != 0;
-    hipStream_t in = pipe ? sv->up : s, out = pipe ? sv->down : s;
-    hipError_t e = hipMemcpyAsync(src, r.pk.src_ip, 4 * n, hipMemcpyHostToDevice, in);
-    if (e == hipSuccess) e = hipMemcpyAsync(dst, r.pk.dst_ip, 4 * n, hipMemcpyHostToDevice, in);
-    if (e == hipSuccess) e = hipMemcpyAsync(sp, r.pk.src_port, 2 * n, hipMemcpyHostToDevice, in);
-    if (e == hipSuccess) e = hipMemcpyAsync(dp, r.pk.dst_port, 2 * n, hipMemcpyHostToDevice, in);
-    if (e == hipSuccess) e = hipMemcpyAsync(pr, r.pk.proto, n, hipMemcpyHostToDevice, in);
-    if (pipe && e == hipSuccess) e = hipEventRecord(sv->ev_up[r.slot], in);
-    if (pipe && e == hipSuccess) e = hipStreamWaitEvent(s, sv->ev_up[r.slot], 0);
-    if (e != hipSuccess) return hip_fail(e, "copying packets in");
-    const fw_packets pk{src, dst, sp, dp, pr};
-    fw_classify_opts co{};
-    co.mode = sv->o.mode;
-    co.partitions = sv->o.partitions;
-    co.stream = s;
-    const fw_status st = fw_classify_ex(sv->chains[r.chain], &pk, n, oi, oa, &co);
-    if (st != FW_OK) return st;
-    if (pipe) {
-        e = hipEventRecord(sv->ev_comp[r.slot], s);
-        if (e == hipSuccess) e = hipStreamWaitEvent(out, sv->ev_comp[r.slot], 0);
-        if (e != hipSuccess) return hip_fail(e, "ordering the copy out");
+constexpr uint32_t kMaxSlots = 16;
+
+// Bytes a request of n packets adds to a group.
+size_t request_bytes(size_t n) { return GroupLayout(round16(n)).bytes; }
+
+// Under sv->mu: take queued requests, in arrival order, into a group that
+// fits both the slot's share of the budget and the arena's largest free
+// block; the first request alone needs only the block.  Returns false (and
+// takes nothing) when the first request does not fit yet.
+bool admit(fw_server* sv, Group* g) {
+    const size_t largest = sv->arena->largest();
+    const size_t share = std::max<size_t>(sv->o.mem_budget / sv->o.slots, 1);
+    size_t N = 0;
+    uint32_t take = 0;
+    for (const auto& r : sv->queue) {
+        if (take >= sv->o.max_group) break;
+        const size_t next = N + round16(r->n);
+        const size_t bytes = GroupLayout(next).bytes;
+        if (bytes > largest || (take > 0 && bytes > share)) break;
+        N = next;
+        ++take;
     }
-    e = hipMemcpyAsync(r.out_idx, oi, 4 * n, hipMemcpyDeviceToHost, out);
-    if (e == hipSuccess) e = hipMemcpyAsync(r.out_act, oa, n, hipMemcpyDeviceToHost, out);
-    if (e == hipSuccess) e = hipEventRecord(sv->events[r.slot], out);
-    if (e != hipSuccess) return hip_fail(e, "copying results out");
+    if (take == 0) return false;
+    g->N = N;
+    g->bytes = GroupLayout(N).bytes;
+    if (!sv->arena->alloc(g->bytes, &g->off)) return false;   // cannot happen: fits `largest`
+    const double t = now_s();
+    for (uint32_t k = 0; k < take; ++k) {
+        auto r = sv->queue.front();
+        sv->queue.pop_front();
+        r->times.admit = t;
+        g->reqs.push_back(std::move(r));
+    }
+    return true;
+}
+
+// Copy ingest moves a request of at least this many packets by its own
+// copies straight between its buffers and the group's device block (seven
+// copies; their fixed cost is below the host copying it twice); smaller ones
+// are packed into staging and move with the group's few copies.
+constexpr size_t kDirectCopyMin = 4096;
+
+// Copy ingest: the small requests take the front of the group's block, packed
+// into staging; the large ones follow.  Every request starts at a 16-packet
+// boundary.  Returns the packets of the packed front.
+size_t place(Group& g) {
+    size_t at = 0;
+    for (int pass = 0; pass < 2; ++pass)
+        for (auto& r : g.reqs)
+            if ((r->n < kDirectCopyMin) == (pass == 0)) {
+                r->at = at;
+                at += round16(r->n);
+            }
+    size_t front = 0;
+    for (const auto& r : g.reqs)
+        if (r->n < kDirectCopyMin) front = std::max(front, r->at + round16(r->n));
+    return front;
+}
+
+hipError_t copy_in(fw_server* sv, hipStream_t s, const Group& g, const GroupLayout& L,
+                   size_t front) {
+    char* h = sv->h_arena + g.off;
+    char* d = sv->d_arena + g.off;
+    hipError_t e = hipSuccess;
+    const size_t offs[5] = {L.src, L.dst, L.sp, L.dp, L.pr};
+    const size_t width[5] = {4, 4, 2, 2, 1};
+    for (const auto& r : g.reqs) {
+        const void* src[5] = {r->pk.src_ip, r->pk.dst_ip, r->pk.src_port, r->pk.dst_port,
+                              r->pk.proto};
+        for (int f = 0; f < 5 && e == hipSuccess; ++f) {
+            const size_t at = offs[f] + width[f] * r->at, bytes = width[f] * r->n;
+            if (r->n < kDirectCopyMin)
+                std::memcpy(h + at, src[f], bytes);
+            else
+                e = hipMemcpyAsync(d + at, src[f], bytes, hipMemcpyHostToDevice, s);
+        }
+    }
+    for (int f = 0; f < 5 && e == hipSuccess && front; ++f)
+        e = hipMemcpyAsync(d + offs[f], h + offs[f], width[f] * front, hipMemcpyHostToDevice, s);
+    return e;
+}
+
+hipError_t copy_out(fw_server* sv, hipStream_t s, const Group& g, const GroupLayout& L,
+                    size_t front) {
+    char* h = sv->h_arena + g.off;
+    char* d = sv->d_arena + g.off;
+    hipError_t e = hipSuccess;
+    if (front) e = hipMemcpyAsync(h + L.idx, d + L.idx, 4 * front, hipMemcpyDeviceToHost, s);
+    if (front && e == hipSuccess)
+        e = hipMemcpyAsync(h + L.act, d + L.act, front, hipMemcpyDeviceToHost, s);
+    for (const auto& r : g.reqs) {
+        if (r->n < kDirectCopyMin || e != hipSuccess) continue;
+        e = hipMemcpyAsync(r->out_idx, d + L.idx + 4 * r->at, 4 * r->n, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(r->out_act, d + L.act + r->at, r->n, hipMemcpyDeviceToHost, s);
+    }
+    return e;
+}
+
+// After the group completed: hand out the packed front's results.
+void unpack(fw_server* sv, const Group& g, const GroupLayout& L) {
+    const char* h = sv->h_arena + g.off;
+    for (const auto& r : g.reqs) {
+        if (r->n >= kDirectCopyMin) continue;
+        std::memcpy(r->out_idx, h + L.idx + 4 * r->at, 4 * r->n);
+        std::memcpy(r->out_act, h + L.act + r->at, r->n);
+    }
+}
+
+// Classify one group on a slot; returns once its results are in place.
+fw_status run_group(fw_server* sv, fw_server::Slot& sl, Group& g) {
+    const GroupLayout L(g.N);
+    const bool mapped = sv->o.ingest == 1;
+    std::vector<fw_chain_batch> b(g.reqs.size());
+    hipError_t e = hipSuccess;
+    size_t front = 0;
+    if (mapped) {
+        for (size_t k = 0; k < g.reqs.size(); ++k) {
+            const Request& r = *g.reqs[k];
+            b[k] = fw_chain_batch{sv->chains[r.chain],
+                                  fw_packets{r.pk.src_ip, r.pk.dst_ip, r.pk.src_port,
+                                             r.pk.dst_port, r.pk.proto},
+                                  r.n, r.out_idx, r.out_act};
+        }
+    } else {
+        front = place(g);
+        e = copy_in(sv, sl.stream, g, L, front);
+        if (e != hipSuccess) {
+            (void)hipStreamSynchronize(sl.stream);
+            return hip_fail(e, "copying a group's packets in");
+        }
+        char* d = sv->d_arena + g.off;
+        for (size_t k = 0; k < g.reqs.size(); ++k) {
+            const Request& r = *g.reqs[k];
+            const size_t o = r.at;
+            b[k] = fw_chain_batch{
+                sv->chains[r.chain],
+                fw_packets{reinterpret_cast<const uint32_t*>(d + L.src + 4 * o),
+                           reinterpret_cast<const uint32_t*>(d + L.dst + 4 * o),
+                           reinterpret_cast<const uint16_t*>(d + L.sp + 2 * o),
+                           reinterpret_cast<const uint16_t*>(d + L.dp + 2 * o),
+                           reinterpret_cast<const uint8_t*>(d + L.pr + o)},
+                r.n, reinterpret_cast<int32_t*>(d + L.idx + 4 * o),
+                reinterpret_cast<uint8_t*>(d + L.act + o)};
+        }
+    }
+    MultiConfig cfg;
+    cfg.placement = kPlaceAuto;
+    cfg.use_index = sv->o.mode != FW_MODE_PACKET_SPLIT;
+    cfg.K = g.N >= size_t(8192) * 64u * 2u ? 2 : 1;   // 8,192 waves or more at two per lane
+    e = multi_launch(b.data(), uint32_t(b.size()), cfg, sl.stream, sl.d_desc, sl.h_desc);
+    if (e != hipSuccess) {
+        (void)hipStreamSynchronize(sl.stream);
+        return hip_fail(e, "group launch");
+    }
+    if (!mapped) {
+        e = copy_out(sv, sl.stream, g, L, front);
+        if (e != hipSuccess) {
+            (void)hipStreamSynchronize(sl.stream);
+            return hip_fail(e, "copying a group's results out");
+        }
+    }
+    e = hipEventRecord(sl.done, sl.stream);
+    if (e == hipSuccess) e = hipEventSynchronize(sl.done);
+    if (e != hipSuccess) return hip_fail(e, "group failed on the device");
+    if (!mapped) unpack(sv, g, L);
     return FW_OK;
 }
 
-// Worker owning slots [lo, hi).
-void worker_main(fw_server* sv, uint32_t lo, uint32_t hi) {
+void slot_main(fw_server* sv, uint32_t k) {
     (void)hipSetDevice(sv->device);
-    std::vector<int> free_slots;
-    for (int k = int(hi) - 1; k >= int(lo); --k) free_slots.push_back(k);
-    uint32_t mine = 0;   // requests in flight on this worker's slots
+    fw_server::Slot& sl = sv->slots[k];
     for (;;) {
-        std::vector<std::shared_ptr<Request>> admitted;
+        Group g;
         {
             std::unique_lock<std::mutex> lk(sv->mu);
-            if (mine == 0 && sv->queue.empty()) {
-                if (sv->stop) break;
-                sv->cv_work.wait(lk, [&] { return sv->stop || !sv->queue.empty(); });
-                continue;
-            }
-            // admit in arrival order while a slot is free and the memory fits
-            while (!sv->queue.empty() && !free_slots.empty()) {
-                auto& r = sv->queue.front();
-                size_t off = 0;
-                if (!sv->arena->alloc(r->bytes, &off)) break;
-                r->off = off;
-                r->slot = free_slots.back();
-                free_slots.pop_back();
-                r->times.admit = now_s();
-                admitted.push_back(r);
-                sv->queue.pop_front();
-            }
+            sv->cv_work.wait(lk, [&] { return (sv->stop && sv->queue.empty()) || admit(sv, &g); });
+            if (g.reqs.empty()) break;   // stopping, nothing left
         }
-        bool progressed = !admitted.empty();
-        for (auto& r : admitted) {
-            sv->slot_req[r->slot] = r;
-            r->status = launch_request(sv, *r);
-            if (r->status != FW_OK) r->error = g_last_error;
-            ++mine;
+        const fw_status st = run_group(sv, sl, g);
+        const std::string err = st != FW_OK ? g_last_error : std::string();
+        const double t = now_s();
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->arena->release(g.off, g.bytes);
+        for (auto& r : g.reqs) {
+            r->status = st;
+            r->error = err;
+            r->times.done = t;
+            r->done = true;
         }
-        // completions
-        std::vector<std::shared_ptr<Request>> finished;
-        for (uint32_t k = lo; k < hi; ++k) {
-            auto& r = sv->slot_req[k];
-            if (!r) continue;
-            bool complete = r->status != FW_OK;
-            if (!complete) {
-                const hipError_t q = hipEventQuery(sv->events[k]);
-                if (q == hipSuccess) {
-                    complete = true;
-                } else if (q != hipErrorNotReady) {
-                    r->status = hip_fail(q, "request failed on the device");
-                    r->error = g_last_error;
-                    complete = true;
-                }
-            }
-            if (complete) {
-                if (r->status != FW_OK) {
-                    (void)hipStreamSynchronize(sv->streams[k]);
-                    if (sv->o.pipeline) {
-                        (void)hipStreamSynchronize(sv->up);
-                        (void)hipStreamSynchronize(sv->down);
-                    }
-                }
-                r->times.done = now_s();
-                finished.push_back(r);
-                free_slots.push_back(int(k));
-                r.reset();
-            }
-        }
-        if (!finished.empty()) {
-            progressed = true;
-            mine -= uint32_t(finished.size());
-            std::lock_guard<std::mutex> lk(sv->mu);
-            for (auto& r : finished) {
-                sv->arena->release(r->off, r->bytes);
-                r->done = true;
-            }
-            sv->cv_done.notify_all();
-            sv->cv_work.notify_all();   // freed memory may admit another worker's request
-        }
-        if (!progressed) std::this_thread::yield();
+        sv->cv_done.notify_all();
+        sv->cv_work.notify_all();   // freed memory may admit another slot's group
     }
 }
+
+void destroy_resources(fw_server* sv) {
+    for (auto& sl : sv->slots) {
+        if (sl.stream) (void)hipStreamDestroy(sl.stream);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.d_desc) (void)hipFree(sl.d_desc);
+        if (sl.h_desc) (void)hipHostFree(sl.h_desc);
+    }
+    if (sv->d_arena) (void)hipFree(sv->d_arena);
+    if (sv->h_arena) (void)hipHostFree(sv->h_arena);
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
 }  // namespace
 }  // namespace fw
@@ -261,56 +343,49 @@ fw_status fw_server_create(fw_ruleset* const* chains, uint32_t n_chains, const f
         if (!chains[c]) return fail(FW_E_INVAL, "chain %u is NULL", c);
     fw_server_opts o{};
     if (opts) o = *opts;
-    if (o.slots == 0) o.slots = 8;
-    if (o.slots > 64) return fail(FW_E_INVAL, "at most 64 slots");
+    if (o.slots == 0) o.slots = 4;
+    if (o.slots > kMaxSlots) return fail(FW_E_INVAL, "at most %u slots", kMaxSlots);
+    if (o.max_group == 0) o.max_group = kMultiMaxChains;
+    if (o.max_group > kMultiMaxChains)
+        return fail(FW_E_INVAL, "at most %u requests per group", kMultiMaxChains);
     if (o.mem_budget == 0) o.mem_budget = uint64_t(256) << 20;
-    if (o.mode > FW_MODE_HYBRID) return fail(FW_E_INVAL, "unknown mode %u", o.mode);
-    if (o.pipeline > 1) return fail(FW_E_INVAL, "pipeline must be 0 or 1");
-    if (o.workers > 16) return fail(FW_E_INVAL, "at most 16 workers");
-    if (o.workers == 0) o.workers = 4;
-    if (o.workers > o.slots) o.workers = o.slots;
+    if (o.ingest > 1) return fail(FW_E_INVAL, "ingest must be 0 (copies) or 1 (mapped)");
+    if (o.mode != FW_MODE_AUTO && o.mode != FW_MODE_PACKET_SPLIT && o.mode != FW_MODE_LEARNED)
+        return fail(FW_E_INVAL,
+                    "serving mode must be AUTO, PACKET_SPLIT or LEARNED (groups run as one "
+                    "multi-chain launch)");
+    if (o.mode == FW_MODE_LEARNED) {
+        for (uint32_t c = 0; c < n_chains; ++c) {
+            const ChainView* hv = nullptr;
+            ruleset_chain_view(chains[c], &hv);
+            if (!hv->has_index)
+                return fail(FW_E_NOINDEX, "chain %u has no learned index (mode LEARNED)", c);
+        }
+    }
     fw_server* sv = new (std::nothrow) fw_server();
     if (!sv) return fail(FW_E_NOMEM, "host allocation failed");
     sv->chains.assign(chains, chains + n_chains);
     sv->o = o;
-    hipError_t e = hipGetDevice(&sv->device);
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&sv->arena_base), o.mem_budget);
-    if (e != hipSuccess) {
-        delete sv;
-        return hip_fail(e, "allocating the server arena");
-    }
     sv->arena = std::make_unique<Arena>(size_t(o.mem_budget));
-    sv->streams.assign(o.slots, nullptr);
-    sv->events.assign(o.slots, nullptr);
-    sv->slot_req.assign(o.slots, nullptr);
-    sv->ev_up.assign(o.pipeline ? o.slots : 0, nullptr);
-    sv->ev_comp.assign(o.pipeline ? o.slots : 0, nullptr);
-    for (uint32_t k = 0; k < o.slots && e == hipSuccess; ++k) {
-        e = hipStreamCreateWithFlags(&sv->streams[k], hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&sv->events[k], hipEventDisableTiming);
-        if (o.pipeline && e == hipSuccess)
-            e = hipEventCreateWithFlags(&sv->ev_up[k], hipEventDisableTiming);
-        if (o.pipeline && e == hipSuccess)
-            e = hipEventCreateWithFlags(&sv->ev_comp[k], hipEventDisableTiming);
+    sv->slots.resize(o.slots);
+    hipError_t e = hipGetDevice(&sv->device);
+    if (e == hipSuccess && o.ingest == 0)
+        e = hipMalloc(reinterpret_cast<void**>(&sv->d_arena), o.mem_budget);
+    if (e == hipSuccess && o.ingest == 0)
+        e = hipHostMalloc(reinterpret_cast<void**>(&sv->h_arena), o.mem_budget,
+                          hipHostMallocDefault);
+    for (auto& sl : sv->slots) {
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipMalloc(&sl.d_desc, kMultiScratchBytes);
+        if (e == hipSuccess) e = hipHostMalloc(&sl.h_desc, kMultiScratchBytes, hipHostMallocDefault);
     }
-    if (o.pipeline && e == hipSuccess) e = hipStreamCreateWithFlags(&sv->up, hipStreamNonBlocking);
-    if (o.pipeline && e == hipSuccess)
-        e = hipStreamCreateWithFlags(&sv->down, hipStreamNonBlocking);
     if (e != hipSuccess) {
-        for (auto s : sv->streams)
-            if (s) (void)hipStreamDestroy(s);
-        for (auto s : {sv->up, sv->down})
-            if (s) (void)hipStreamDestroy(s);
-        for (auto& evs : {sv->events, sv->ev_up, sv->ev_comp})
-            for (auto ev : evs)
-                if (ev) (void)hipEventDestroy(ev);
-        (void)hipFree(sv->arena_base);
+        destroy_resources(sv);
         delete sv;
-        return hip_fail(e, "creating server streams");
+        return hip_fail(e, "creating the server");
     }
-    for (uint32_t w = 0; w < o.workers; ++w)
-        sv->workers.emplace_back(worker_main, sv, w * o.slots / o.workers,
-                                 (w + 1) * o.slots / o.workers);
+    for (uint32_t k = 0; k < o.slots; ++k) sv->slots[k].thread = std::thread(slot_main, sv, k);
     *out = sv;
     return FW_OK;
 }
@@ -322,6 +397,11 @@ fw_status fw_server_submit(fw_server* sv, uint32_t chain, const fw_host_packets*
     if (n > 0 && (!pk || !pk->src_ip || !pk->dst_ip || !pk->src_port || !pk->dst_port ||
                   !pk->proto || !out_rule_idx || !out_action))
         return fail(FW_E_INVAL, "NULL buffer");
+    if (n > 0 && sv->o.ingest == 1 &&
+        !(aligned16(pk->src_ip) && aligned16(pk->dst_ip) && aligned16(pk->src_port) &&
+          aligned16(pk->dst_port) && aligned16(pk->proto) && aligned16(out_rule_idx) &&
+          aligned16(out_action)))
+        return fail(FW_E_ALIGN, "mapped ingest needs 16-byte aligned buffers");
     const size_t bytes = request_bytes(n);
     if (bytes > sv->o.mem_budget)
         return fail(FW_E_NOMEM, "request of %zu packets needs %zu bytes, budget %llu", n, bytes,
@@ -332,7 +412,6 @@ fw_status fw_server_submit(fw_server* sv, uint32_t chain, const fw_host_packets*
     r->n = n;
     r->out_idx = out_rule_idx;
     r->out_act = out_action;
-    r->bytes = bytes;
     r->times.submit = now_s();
     std::lock_guard<std::mutex> lk(sv->mu);
     if (sv->stop) return fail(FW_E_INVAL, "server is stopping");
@@ -345,7 +424,7 @@ fw_status fw_server_submit(fw_server* sv, uint32_t chain, const fw_host_packets*
         return FW_OK;
     }
     sv->queue.push_back(r);
-    sv->cv_work.notify_all();
+    sv->cv_work.notify_one();
     return FW_OK;
 }
 
@@ -408,21 +487,14 @@ fw_status fw_server_destroy(fw_server* sv) {
         sv->stop = true;
         sv->cv_work.notify_all();
     }
-    for (auto& t : sv->workers) t.join();
+    for (auto& sl : sv->slots)
+        if (sl.thread.joinable()) sl.thread.join();
     hipError_t e = hipSuccess;
-    for (auto s : sv->streams) {
-        const hipError_t e2 = hipStreamDestroy(s);
+    for (auto& sl : sv->slots) {
+        const hipError_t e2 = hipStreamSynchronize(sl.stream);
         if (e == hipSuccess) e = e2;
     }
-    for (auto s : {sv->up, sv->down}) {
-        if (!s) continue;
-        const hipError_t e2 = hipStreamDestroy(s);
-        if (e == hipSuccess) e = e2;
-    }
-    for (auto& evs : {sv->events, sv->ev_up, sv->ev_comp})
-        for (auto ev : evs) (void)hipEventDestroy(ev);
-    const hipError_t e3 = hipFree(sv->arena_base);
-    if (e == hipSuccess) e = e3;
+    destroy_resources(sv);
     delete sv;
     if (e != hipSuccess) return hip_fail(e, "destroying the server");
     return FW_OK;

@@ -76,9 +76,8 @@ class MultiOpts(ctypes.Structure):
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("slots", ctypes.c_uint32), ("mode", ctypes.c_uint32),
-                ("partitions", ctypes.c_uint32), ("pipeline", ctypes.c_uint32),
-                ("mem_budget", ctypes.c_uint64), ("workers", ctypes.c_uint32),
-                ("_reserved", ctypes.c_uint32)]
+                ("max_group", ctypes.c_uint32), ("ingest", ctypes.c_uint32),
+                ("mem_budget", ctypes.c_uint64), ("_reserved", ctypes.c_uint32 * 2)]
 
 
 class HostPackets(ctypes.Structure):
@@ -430,6 +429,25 @@ def classify_multi(items, stream=None, packets_per_lane=0, placement=0, rule_til
     _check(fn(arr, len(items), ctypes.byref(opts)))
 
 
+class MultiBatch:
+    """A multi-chain call prepared once: the chains' tensors are checked and the C array of
+    fw_chain_batch entries built at construction, so repeated calls marshal only the
+    options (the items must stay alive and unchanged while the object is used)."""
+
+    def __init__(self, items):
+        self.items = list(items)
+        self.arr = _chain_array(self.items)
+
+    def run(self, stream=None, packets_per_lane=0, placement=0, rule_tile=0, no_alloc=False):
+        for _, pk, oi, oa in self.items:
+            _record_on(stream, pk.fields() + (oi, oa))
+        opts = MultiOpts(_stream_ptr(stream), int(packets_per_lane), int(placement),
+                         int(rule_tile), 0)
+        lib = load_library()
+        fn = lib.fw_classify_multi_noalloc if no_alloc else lib.fw_classify_multi
+        _check(fn(self.arr, len(self.items), ctypes.byref(opts)))
+
+
 def autotune_multi(items, stream=None):
     """Time the configuration grid on these chains; returns (options dict, best ms)."""
     arr = _chain_array(items)
@@ -448,19 +466,22 @@ _SERVER_ITEMSIZES = (4, 4, 2, 2, 1, 4, 1)
 class Server:
     """Continuous-batching server over resident rulesets (fw_server_*).
 
-    ``submit`` takes host arrays (numpy, ideally views of pinned torch tensors)
-    that must stay alive until ``wait`` returns for the ticket; it returns the
-    ticket at once.  ``wait`` returns the request's (submit, admit, done)
-    times in seconds.
+    ``submit`` takes host arrays (numpy; with ``ingest="mapped"`` they must be views of
+    pinned torch tensors, 16-byte aligned) that must stay alive until ``wait`` returns for
+    the ticket; it returns the ticket at once.  ``wait`` returns the request's (submit,
+    admit, done) times in seconds.
     """
 
-    def __init__(self, rulesets, slots: int = 8, mode="auto", partitions: int = 0,
-                 mem_budget: int = 0, pipeline: bool = False, workers: int = 0):
+    INGEST = {"copy": 0, "mapped": 1}
+
+    def __init__(self, rulesets, slots: int = 0, mode="auto", mem_budget: int = 0,
+                 ingest="copy", max_group: int = 0):
         lib = load_library()
         self._chains = list(rulesets)
         arr = (ctypes.c_void_p * len(self._chains))(*[r.handle.value for r in self._chains])
         opts = ServerOpts(int(slots), MODES[mode] if isinstance(mode, str) else int(mode),
-                          int(partitions), int(bool(pipeline)), int(mem_budget), int(workers), 0)
+                          int(max_group), self.INGEST[ingest] if isinstance(ingest, str)
+                          else int(ingest), int(mem_budget))
         h = ctypes.c_void_p()
         _check(lib.fw_server_create(arr, len(self._chains), ctypes.byref(opts), ctypes.byref(h)))
         self._h = h

@@ -113,8 +113,9 @@ def test_argument_errors(fw):
     assert out.value is None
     # options are validated before any device work (the chain handle is never touched)
     fake = (ctypes.c_void_p * 1)(1)
-    for opts in (fw.ServerOpts(65, 0, 0, 0, 0, 0, 0), fw.ServerOpts(8, 9, 0, 0, 0, 0, 0),
-                 fw.ServerOpts(8, 0, 0, 2, 0, 0, 0), fw.ServerOpts(8, 0, 0, 0, 0, 17, 0)):
+    for opts in (fw.ServerOpts(17, 0, 0, 0, 0), fw.ServerOpts(4, 9, 0, 0, 0),
+                 fw.ServerOpts(4, 2, 0, 0, 0), fw.ServerOpts(4, 4, 0, 0, 0),
+                 fw.ServerOpts(4, 0, 1025, 0, 0), fw.ServerOpts(4, 0, 0, 2, 0)):
         assert lib.fw_server_create(fake, 1, ctypes.byref(opts), ctypes.byref(out)) == fw.E_INVAL
         assert out.value is None
     assert lib.fw_server_submit(None, 0, None, 0, None, None, None) == fw.E_INVAL

@@ -41,7 +41,7 @@ def _check(work, items, what):
         np.testing.assert_array_equal(oa.cpu().numpy(), want_a, err_msg=f"{what} chain {c} act")
 
 
-@pytest.mark.parametrize("placement,tile", [(1, 0), (3, 0), (2, 256), (2, 1024)])
+@pytest.mark.parametrize("placement,tile", [(4, 0), (1, 0), (3, 0), (2, 256), (2, 1024)])
 @pytest.mark.parametrize("K", [1, 2, 4])
 def test_every_configuration(K, placement, tile):
     fw = fwmod()
@@ -64,7 +64,7 @@ def test_autotuned_full_shape_sampled():
     say(f"multi autotune over {sum(len(p) for _, p in work)} packets")
     best, ms = fw.autotune_multi(items)
     say(f"  best {best} {ms:.3f} ms")
-    assert best["packets_per_lane"] in (1, 2, 4) and best["placement"] in (1, 2, 3)
+    assert best["packets_per_lane"] in (1, 2, 4) and best["placement"] in (1, 2, 3, 4)
     for _, _, oi, oa in items:
         oi.fill_(7)
     fw.classify_multi(items)                    # tuned options
@@ -75,5 +75,48 @@ def test_autotuned_full_shape_sampled():
         want_i, want_a = oracle.classify(rules, pk.subset(sel), threads=8)
         np.testing.assert_array_equal(oi.cpu().numpy()[sel], want_i, err_msg=f"chain {c}")
         np.testing.assert_array_equal(oa.cpu().numpy()[sel], want_a, err_msg=f"chain {c}")
+    for rs in rss:
+        rs.close()
+
+
+@pytest.mark.parametrize("big_index", [False, True])
+@pytest.mark.parametrize("K", [1, 2, 4])
+def test_learned_and_scanned_chains_in_one_launch(K, big_index):
+    """Placement 4 routes chains with a learned index through the learned lookup (their LDS
+    images staged as work-groups move between chains) and the rest through the grouped-plan
+    scan, in one launch.  With big_index one chain's boundary array is too large for LDS, so
+    every index in the launch is searched in global memory.  Each chain against the oracle,
+    and again on a second call with fewer chains."""
+    import torch
+    fw = fwmod()
+    work = []
+    for c, (R, n, skew) in enumerate([(10_000, 150_000, True), (2_000, 40_000, True),
+                                      (300, 9_000, False), (5_000, 70_000, True),
+                                      (40, 1_000, False), (1_500, 33_000, False)]):
+        rules = gen.make_rules(R, 300 + c, skew=skew)
+        work.append((rules, gen.make_packets(rules, n, 300 + c)))
+    if big_index:
+        rules = gen.make_rules(30_000, 399, skew=True)
+        rules.dst_plen[rules.dst_plen == 0] = 24
+        work.append((rules, gen.make_packets(rules, 60_000, 399)))
+    items, rss = [], []
+    for c, (rules, pk) in enumerate(work):
+        rs = fw.Ruleset(rules)
+        if c % 2 == 0 or (big_index and c == len(work) - 1):
+            rs.build_learned_index(epochs1=300, epochs2=600, seed=c)
+        rss.append(rs)
+        n = len(pk)
+        items.append((rs, fw.DevicePackets.from_host(pk),
+                      torch.full((n,), 7, dtype=torch.int32, device="cuda"),
+                      torch.full((n,), 9, dtype=torch.uint8, device="cuda")))
+    torch.cuda.synchronize()
+    for what, pick in (("all chains", list(range(len(items)))), ("three chains", [1, 2, 3])):
+        say(f"multi learned+scan K={K} big_index={big_index}: {what}")
+        sub = [items[i] for i in pick]
+        for _, _, oi, oa in sub:
+            oi.fill_(7)
+            oa.fill_(9)
+        fw.classify_multi(sub, packets_per_lane=K, placement=4)
+        _check([work[i] for i in pick], sub, f"K={K} {what}")
     for rs in rss:
         rs.close()

@@ -207,15 +207,13 @@ def test_boundary_packets(wild):
 
 
 @pytest.mark.parametrize("seed", [1, 2, 3, 4, 5])
-def test_10000_rules_16M_packets_sampled(seed):
-    """10,000 skewed rules x 16,777,216 packets, seeds 1-5: packet split, rule split and hybrid;
-    a sample vs the oracle."""
+def test_10000_rules_16M_packets_whole_batch(seed):
+    """10,000 skewed rules x 16,777,216 packets, seeds 1-5: packet split, rule split and hybrid,
+    every packet against the oracle."""
     import torch
     fw = fwmod()
     rules, pk = gen.workload("learned_10000x16M", seed=seed)
-    rng = np.random.Generator(np.random.PCG64(5))
-    sample = np.sort(rng.choice(len(pk), 40_000, replace=False))
-    want = oracle.classify(rules, pk.subset(sample), threads=16)
+    want = oracle.classify(rules, pk, threads=16)
     dp = fw.DevicePackets.from_host(pk)
     with fw.Ruleset(rules) as rs:
         for kw in (dict(mode="packet_split"), dict(mode="rule_split", partitions=16),
@@ -223,11 +221,31 @@ def test_10000_rules_16M_packets_sampled(seed):
             say(f"10000x16M seed={seed} {kw}")
             idx, act = rs.classify(dp, **kw)
             torch.cuda.synchronize()
-            got = (idx.cpu().numpy()[sample], act.cpu().numpy()[sample])
-            assert_same(got, want, f"10000x16M seed {seed} {kw}")
-            # every index is -1 or a real rule, and actions agree with the rule table
-            ia = idx.cpu().numpy()
-            assert ia.min() >= -1 and ia.max() < len(rules)
+            assert_same((idx.cpu().numpy(), act.cpu().numpy()), want, f"10000x16M seed {seed} {kw}")
+
+
+@pytest.mark.parametrize("wl,seed", [("learned_10000x16M", 1), ("scan_1000x1M", 2),
+                                     ("scan_100x10k", 3)])
+def test_auto_without_index_every_batch_size(wl, seed):
+    """Mode AUTO without an index picks rule split, the hybrid or packet split by batch size
+    (and reachable rules): batches on both sides of every threshold, each against the oracle,
+    and each equal to packet split on the same batch."""
+    import torch
+    fw = fwmod()
+    rules, pk = gen.workload(wl, seed=seed, n_packets=300_000)
+    want = oracle.classify(rules, pk, threads=16)
+    dp = fw.DevicePackets.from_host(pk)
+    with fw.Ruleset(rules) as rs:
+        for n in (1, 63, 64, 1000, 4096, 4097, 16384, 32768, 32769, 65536, 262143, 262144,
+                  300_000):
+            say(f"auto {wl} seed={seed} n={n}")
+            sub = dp.slice(0, n)
+            idx, act = rs.classify(sub)
+            ps = rs.classify(sub, mode="packet_split")
+            torch.cuda.synchronize()
+            got = (idx.cpu().numpy(), act.cpu().numpy())
+            assert_same(got, (want[0][:n], want[1][:n]), f"auto {wl} n={n}")
+            assert_same(got, (ps[0].cpu().numpy(), ps[1].cpu().numpy()), f"auto vs scan n={n}")
 
 
 def test_determinism_and_streams():

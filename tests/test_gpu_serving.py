@@ -36,26 +36,32 @@ def _requests(chains, n_req, seed, max_batch=20_000):
 
 
 def _run(server, reqs):
-    """Prepare every request's pinned buffers first, then submit them back to back."""
+    """Prepare every request's pinned buffers first (results too: mapped ingest writes them
+    in place), then submit them back to back."""
     keep = []
     for c, pk in reqs:
         bufs = [_pinned(a) for a in (pk.src_ip, pk.dst_ip, pk.sport, pk.dport, pk.proto)]
-        keep.append((c, bufs, np.empty(len(pk), np.int32), np.empty(len(pk), np.uint8)))
+        oi = _pinned(np.full(len(pk), -7, np.int32))
+        oa = _pinned(np.full(len(pk), 9, np.uint8))
+        bufs += [oi, oa]
+        keep.append((c, bufs[:5], oi[1], oa[1]))
     tickets = [server.submit(c, *[b[1] for b in bufs], oi, oa) for c, bufs, oi, oa in keep]
     times = [server.wait(t) for t in tickets]
     return [(k[2], k[3]) for k in keep], times
 
 
-@pytest.mark.parametrize("pipeline,workers", [(False, 1), (True, 1), (False, 4), (True, 3)])
-def test_mix_equals_alone_equals_oracle(pipeline, workers):
+@pytest.mark.parametrize("ingest,slots,max_group", [("copy", 1, 0), ("copy", 4, 0),
+                                                    ("mapped", 4, 0), ("mapped", 3, 5),
+                                                    ("copy", 16, 2)])
+def test_mix_equals_alone_equals_oracle(ingest, slots, max_group):
     fw = fwmod()
     chains = [gen.make_rules(n, 70 + i, skew=True) for i, n in enumerate((200, 1000, 3000))]
     rs = [fw.Ruleset(c) for c in chains]
     rs[1].build_learned_index(epochs1=300, epochs2=600)
     reqs = _requests(chains, 48, 5)
-    say(f"serving: mix of 48 requests over 3 chains, 8 slots, pipeline={pipeline}, "
-        f"workers={workers}")
-    with fw.Server(rs, slots=8, pipeline=pipeline, workers=workers) as sv:
+    say(f"serving: mix of 48 requests over 3 chains, {slots} slots, ingest={ingest}, "
+        f"max_group={max_group}")
+    with fw.Server(rs, slots=slots, ingest=ingest, max_group=max_group) as sv:
         mix, times = _run(sv, reqs)
     say("serving: the same requests one at a time")
     with fw.Server(rs, slots=1) as sv:
@@ -84,7 +90,7 @@ def test_memory_budget_admission():
     reqs = _requests(chains, 20, 6, max_batch=8192)
     budget = 8192 * 18 + 8 * 256        # room for about one of the largest requests
     say("serving: tight memory budget")
-    with fw.Server(rs, slots=8, mem_budget=budget, pipeline=True, workers=4) as sv:
+    with fw.Server(rs, slots=4, mem_budget=budget) as sv:
         res, times = _run(sv, reqs)
         big = gen.make_packets(chains[0], 20_000, 3)
         oi = np.empty(20_000, np.int32)
@@ -92,6 +98,7 @@ def test_memory_budget_admission():
         with pytest.raises(fw.FwError) as ei:
             sv.submit(0, big.src_ip, big.dst_ip, big.sport, big.dport, big.proto, oi, oa)
         assert ei.value.status == fw.E_NOMEM
+    # admitted groups never held more than the budget at once
     for (c, pk), (i, a) in zip(reqs, res):
         want = oracle.classify(chains[c], pk)
         np.testing.assert_array_equal(i, want[0])
@@ -147,5 +154,40 @@ def test_serving_chains_of_2k_10k_50k_rules():
         np.testing.assert_array_equal(m[1], a[1], err_msg=f"request {k} action mix vs alone")
         np.testing.assert_array_equal(m[0], want[0], err_msg=f"request {k} vs oracle")
         np.testing.assert_array_equal(m[1], want[1], err_msg=f"request {k} action vs oracle")
+    for r in rs:
+        r.close()
+
+
+def test_server_options_and_modes():
+    """Packet-split mode ignores built indexes, learned mode needs one on every chain, and the
+    split forms are refused (groups run as one multi-chain launch); mapped ingest refuses
+    buffers that are not 16-byte aligned.  Results against the oracle."""
+    fw = fwmod()
+    chains = [gen.make_rules(n, 90 + i, skew=True) for i, n in enumerate((500, 2000))]
+    rs = [fw.Ruleset(c) for c in chains]
+    rs[0].build_learned_index(epochs1=300, epochs2=600)
+    reqs = _requests(chains, 12, 7, max_batch=5000)
+    for mode in ("packet_split", "auto"):
+        say(f"serving mode {mode}")
+        with fw.Server(rs, mode=mode) as sv:
+            res, _ = _run(sv, reqs)
+        for (c, pk), (i, a) in zip(reqs, res):
+            want = oracle.classify(chains[c], pk)
+            np.testing.assert_array_equal(i, want[0])
+            np.testing.assert_array_equal(a, want[1])
+    with pytest.raises(fw.FwError) as ei:
+        fw.Server(rs, mode="learned")
+    assert ei.value.status == fw.E_NOINDEX
+    for mode in ("rule_split", "hybrid"):
+        with pytest.raises(fw.FwError) as ei:
+            fw.Server(rs, mode=mode)
+        assert ei.value.status == fw.E_INVAL
+    with fw.Server(rs, ingest="mapped") as sv:
+        t, a = _pinned(np.zeros(80, np.uint32))
+        b = a[1:65]                                  # 4 bytes past an aligned start
+        with pytest.raises(fw.FwError) as ei:
+            sv.submit(0, b, a[:64], np.zeros(64, np.uint16), np.zeros(64, np.uint16),
+                      np.zeros(64, np.uint8), np.zeros(64, np.int32), np.zeros(64, np.uint8))
+        assert ei.value.status == fw.E_ALIGN
     for r in rs:
         r.close()
