@@ -590,6 +590,10 @@ def main():
                     help="skip the PCIe-inclusive leg (whole batch from pinned host memory)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (for scaling HBM counters)")
+    ap.add_argument("--probe-batch", type=int, default=0,
+                    help="profiling aid: classify the first N packets 25 times in each scan mode "
+                         "named by --modes (packet_split, rule_split_p16, rule_split_p64, "
+                         "hybrid_p16), print a short JSON line and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the packet-split "
@@ -611,6 +615,22 @@ def main():
     torch.cuda.synchronize()
 
     rs = fw.Ruleset(rules)
+    if args.probe_batch:
+        table = {"packet_split": dict(mode="packet_split"),
+                 "rule_split_p16": dict(mode="rule_split", partitions=16),
+                 "rule_split_p64": dict(mode="rule_split", partitions=64),
+                 "hybrid_p16": dict(mode="hybrid", partitions=16)}
+        names = args.modes.split(",") if args.modes else list(table)
+        sub = dp.slice(0, min(args.probe_batch, n))
+        for name in names:
+            for _ in range(25):
+                rs.classify(sub, stream=stream, out_idx=out_i, out_act=out_a, **table[name])
+            torch.cuda.synchronize()
+            log(f"probe {name}: 25 calls of {len(sub)} packets")
+        rs.close()
+        print(json.dumps({"probe_batch": len(sub), "modes": names, "workload": args.workload}),
+              flush=True)
+        return
     log("building the learned index (trained)")
     t0 = time.perf_counter()
     index_stats = rs.build_learned_index(seed=args.seed)
@@ -798,7 +818,8 @@ def main():
         "p99_us": latency.get(head, {}).get("p99_us"),
         "p50_us": latency.get(head, {}).get("p50_us"),
         "modes": results, "latency": latency,
-        "scan_rule_checks": checks, "learned_candidate_checks": work["candidate_checks"],
+        "scan_rule_checks": checks,
+        "learned_candidate_checks": work["candidate_checks"] if roofline else None,
         "index": index_stats, "index_untrained": untrained_stats, "network_gain": gain,
         "network_gain_other_indexes": gain_configs,
         "roofline": roofline, "roofline_binary_search": roofline_bs,

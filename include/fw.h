@@ -404,7 +404,9 @@ typedef struct fw_server_opts {
                                request rounded up to 16 packets, each array to 256 bytes);
                                with copies it is also the device memory and the page-locked
                                staging the server holds; 0 = 256 MiB */
-    uint32_t _reserved[2];
+    uint64_t max_group_packets; /* packets coalesced into one launch (a larger request still
+                                   runs, alone); every request of a group completes when the
+                                   group does; 0 = 1,048,576 */
 } fw_server_opts;
 
 /* A batch of packet headers in HOST memory (structure of arrays): any host

@@ -125,8 +125,10 @@ constexpr uint32_t kMaxSlots = 16;
 size_t request_bytes(size_t n) { return GroupLayout(round16(n)).bytes; }
 
 // Under sv->mu: take queued requests, in arrival order, into a group that
-// fits both the slot's share of the budget and the arena's largest free
-// block; the first request alone needs only the block.  Returns false (and
+// fits the slot's share of the budget, the arena's largest free block and the
+// group caps (requests and packets: every request of a group completes when
+// the group does, so the cap bounds what a request waits for beside its own
+// work); the first request alone needs only the block.  Returns false (and
 // takes nothing) when the first request does not fit yet.
 bool admit(fw_server* sv, Group* g) {
     const size_t largest = sv->arena->largest();
@@ -137,7 +139,8 @@ bool admit(fw_server* sv, Group* g) {
         if (take >= sv->o.max_group) break;
         const size_t next = N + round16(r->n);
         const size_t bytes = GroupLayout(next).bytes;
-        if (bytes > largest || (take > 0 && bytes > share)) break;
+        if (bytes > largest || (take > 0 && (bytes > share || next > sv->o.max_group_packets)))
+            break;
         N = next;
         ++take;
     }
@@ -346,6 +349,7 @@ fw_status fw_server_create(fw_ruleset* const* chains, uint32_t n_chains, const f
     if (o.slots == 0) o.slots = 4;
     if (o.slots > kMaxSlots) return fail(FW_E_INVAL, "at most %u slots", kMaxSlots);
     if (o.max_group == 0) o.max_group = kMultiMaxChains;
+    if (o.max_group_packets == 0) o.max_group_packets = uint64_t(1) << 20;
     if (o.max_group > kMultiMaxChains)
         return fail(FW_E_INVAL, "at most %u requests per group", kMultiMaxChains);
     if (o.mem_budget == 0) o.mem_budget = uint64_t(256) << 20;

@@ -77,7 +77,7 @@ class MultiOpts(ctypes.Structure):
 class ServerOpts(ctypes.Structure):
     _fields_ = [("slots", ctypes.c_uint32), ("mode", ctypes.c_uint32),
                 ("max_group", ctypes.c_uint32), ("ingest", ctypes.c_uint32),
-                ("mem_budget", ctypes.c_uint64), ("_reserved", ctypes.c_uint32 * 2)]
+                ("mem_budget", ctypes.c_uint64), ("max_group_packets", ctypes.c_uint64)]
 
 
 class HostPackets(ctypes.Structure):
@@ -475,13 +475,13 @@ class Server:
     INGEST = {"copy": 0, "mapped": 1}
 
     def __init__(self, rulesets, slots: int = 0, mode="auto", mem_budget: int = 0,
-                 ingest="copy", max_group: int = 0):
+                 ingest="copy", max_group: int = 0, max_group_packets: int = 0):
         lib = load_library()
         self._chains = list(rulesets)
         arr = (ctypes.c_void_p * len(self._chains))(*[r.handle.value for r in self._chains])
         opts = ServerOpts(int(slots), MODES[mode] if isinstance(mode, str) else int(mode),
                           int(max_group), self.INGEST[ingest] if isinstance(ingest, str)
-                          else int(ingest), int(mem_budget))
+                          else int(ingest), int(mem_budget), int(max_group_packets))
         h = ctypes.c_void_p()
         _check(lib.fw_server_create(arr, len(self._chains), ctypes.byref(opts), ctypes.byref(h)))
         self._h = h

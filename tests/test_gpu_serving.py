@@ -178,6 +178,14 @@ def test_server_options_and_modes():
     with pytest.raises(fw.FwError) as ei:
         fw.Server(rs, mode="learned")
     assert ei.value.status == fw.E_NOINDEX
+    rs[1].build_learned_index(epochs1=300, epochs2=600)
+    say("serving mode learned")
+    with fw.Server(rs, mode="learned", ingest="mapped", slots=2) as sv:
+        res, _ = _run(sv, reqs)
+    for (c, pk), (i, a) in zip(reqs, res):
+        want = oracle.classify(chains[c], pk)
+        np.testing.assert_array_equal(i, want[0])
+        np.testing.assert_array_equal(a, want[1])
     for mode in ("rule_split", "hybrid"):
         with pytest.raises(fw.FwError) as ei:
             fw.Server(rs, mode=mode)

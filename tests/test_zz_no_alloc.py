@@ -84,3 +84,40 @@ def test_noalloc_rejects_too_many_chains_on_device():
     arr = (fw.ChainBatch * 1025)()
     assert lib.fw_classify_multi_noalloc(arr, 1025, None) == fw.E_INVAL
     assert "1024" in lib.fw_last_error().decode()
+
+
+def test_noalloc_with_learned_chains():
+    """The no-allocation entry point on chains with learned indexes (the default placement
+    routes them through the learned lookup): equal to fw_classify_multi and the oracle, on two
+    calls in a row, the second with fewer and smaller chains."""
+    import torch
+    fw = fwmod()
+    stream_ptr = torch.cuda.current_stream().cuda_stream
+    work = []
+    for c, (R, n) in enumerate([(3000, 60_000), (800, 20_000), (5000, 90_000), (120, 3_000)]):
+        rules = gen.make_rules(R, 500 + c, skew=True)
+        work.append((rules, gen.make_packets(rules, n, 500 + c)))
+    small = [(r, p.subset(slice(0, len(p) // 3))) for r, p in work[1:3]]
+    for what, w in (("four chains", work), ("two smaller chains", small)):
+        items, rss = _items(w)
+        for k, rs in enumerate(rss):
+            if k % 2 == 0:
+                rs.build_learned_index(epochs1=300, epochs2=600, seed=k)
+        torch.cuda.synchronize()
+        say(f"no-alloc multi with learned chains: {what}")
+        _launch(items, False, stream_ptr)
+        torch.cuda.synchronize()
+        ref = _results(items)
+        for _, _, oi, oa in items:
+            oi.fill_(7)
+            oa.fill_(9)
+        _launch(items, True, stream_ptr)
+        torch.cuda.synchronize()
+        for c, ((rules, pk), (ri, ra), (gi, ga)) in enumerate(zip(w, ref, _results(items))):
+            np.testing.assert_array_equal(gi, ri, err_msg=f"{what} chain {c} idx")
+            np.testing.assert_array_equal(ga, ra, err_msg=f"{what} chain {c} act")
+            wi, wa = oracle.classify(rules, pk, threads=8)
+            np.testing.assert_array_equal(gi, wi, err_msg=f"{what} chain {c} vs oracle")
+            np.testing.assert_array_equal(ga, wa, err_msg=f"{what} chain {c} act vs oracle")
+        for rs in rss:
+            rs.close()
