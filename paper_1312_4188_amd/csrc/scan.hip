@@ -175,7 +175,11 @@ __global__ __launch_bounds__(1024) void k_hybrid(const uint2* __restrict__ pairs
     }
     __syncthreads();
 
-    WaveScan<K, false> ws;   // its two work-groups per CU need the scalar registers
+    // The per-rule form even with one packet per lane: taking a block's eight
+    // first tests before one branch measured no faster here (the chunk merge
+    // dominates), and its scalar registers would cost the launch its second
+    // work-group per CU at four per lane.
+    WaveScan<K, false> ws;
     ws.init(pk, first, n, dflt);
     const uint64_t r0 = uint64_t(w) * S;
     const uint32_t begin = uint32_t(r0 < n_rules ? r0 : n_rules);
