@@ -25,6 +25,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <exception>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -301,7 +302,13 @@ void slot_main(fw_server* sv, uint32_t k) {
             sv->cv_work.wait(lk, [&] { return (sv->stop && sv->queue.empty()) || admit(sv, &g); });
             if (g.reqs.empty()) break;   // stopping, nothing left
         }
-        const fw_status st = run_group(sv, sl, g);
+        fw_status st;
+        try {   // host allocations inside may throw; a worker thread must not let them escape
+            st = run_group(sv, sl, g);
+        } catch (const std::exception&) {
+            (void)hipStreamSynchronize(sl.stream);
+            st = fail(FW_E_NOMEM, "host allocation failed while running a group");
+        }
         const std::string err = st != FW_OK ? g_last_error : std::string();
         const double t = now_s();
         std::lock_guard<std::mutex> lk(sv->mu);
