@@ -351,7 +351,7 @@ fw_status fw_classify_multi(const fw_chain_batch *batches, uint32_t n_chains,
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * launch as fw_classify_multi with the same options and results, but its
  * chain descriptor table and work-queue counter live in a static device array
- * the library holds on each GPU it runs on (about 80 KiB, kept until the
+ * the library holds on each GPU it runs on (about 104 KiB, kept until the
  * process ends) instead of memory allocated for the call.  It calls no
  * hipMalloc, hipFree or other device-allocating routine; the array's address
  * is looked up once per device on the first call there.  Every call on one

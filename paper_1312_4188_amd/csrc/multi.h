@@ -13,9 +13,14 @@ namespace fw {
 
 struct ChainView;
 
-// One chain's batch as the multi-chain kernels read it (80 bytes).
+// One chain's batch as the multi-chain kernels read it (104 bytes).  The
+// fields the scans use are copied from the ruleset's view, so a kernel reads
+// them straight from the descriptor (scalar loads) rather than through
+// `view`, a pointer read from memory that the kernel's own stores may alias.
 struct ChainDesc {
     const ChainView* view;   // the ruleset (device copy)
+    const RuleRec* rules;    // view->rules
+    const uint2* pairs;      // view->pairs
     const uint32_t* src;
     const uint32_t* dst;
     const uint16_t* sport;
@@ -24,7 +29,9 @@ struct ChainDesc {
     int32_t* out_idx;
     uint8_t* out_act;
     uint64_t n;
-    uint32_t item_begin, pad;
+    uint32_t n_rules, dflt;  // view->n_rules, view->dflt
+    uint32_t item_begin;
+    uint32_t has_index;      // view->has_index
 };
 
 // Placements (fw_multi_opts.placement): grouped plan and learned index, or
@@ -44,7 +51,7 @@ struct MultiConfig {
 // holds up to kMultiMaxChains descriptors.
 constexpr uint32_t kMultiMaxChains = 1024;
 constexpr size_t kMultiCounterBytes = 256;
-constexpr size_t kMultiScratchBytes = kMultiCounterBytes + 80u * kMultiMaxChains;
+constexpr size_t kMultiScratchBytes = kMultiCounterBytes + sizeof(ChainDesc) * kMultiMaxChains;
 
 // One persistent launch over the batches (checked by check_multi_batches),
 // asynchronous on `s`.  The counter and table go to `scratch_mem` when given

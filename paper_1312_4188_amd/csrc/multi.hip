@@ -41,11 +41,11 @@ namespace fw {
 // and its host mirror in *host.
 const ChainView* ruleset_chain_view(const fw_ruleset* rs, const ChainView** host);
 
-static_assert(sizeof(ChainDesc) == 80, "descriptor layout");
+static_assert(sizeof(ChainDesc) == 104, "descriptor layout");
 
 namespace {
 
-constexpr uint32_t kDescPerChunk = 32;   // 2.5 KiB of kernel arguments per upload launch
+constexpr uint32_t kDescPerChunk = 32;   // 3.25 KiB of kernel arguments per upload launch
 
 // Scratch of fw_classify_multi_noalloc: the work-queue counter, then the
 // descriptor table of up to kMultiMaxChains chains (see kMultiScratchBytes),
@@ -127,7 +127,7 @@ template <int K>
 __device__ __attribute__((noinline)) void auto_scan_item(const ChainDesc& c, size_t base) {
     const ChainView& v = *c.view;
     WaveScan<K> w;
-    w.init(packets_of(c), base, c.n, v.dflt);
+    w.init(packets_of(c), base, c.n, c.dflt);
     w.scan_plan(v.plan);
     w.store(c.out_idx, c.out_act, c.n);
 }
@@ -148,7 +148,7 @@ __global__ __launch_bounds__(kLearnedBlock, K >= 4 ? 4 : 8) void k_multi_auto(
         if (item >= total_items) break;
         const ChainDesc& c = cd[chain_of(cd, n_chains, item)];
         const size_t base = size_t(item - c.item_begin) * (size_t(kLearnedBlock) * K) + wave_off;
-        if (use_index && c.view->has_index) {
+        if (use_index && c.has_index) {
             auto_learned_item<K, B_LDS>(c, base, smem, staged != c.view);
             staged = c.view;
         } else if (base < c.n) {
@@ -169,10 +169,9 @@ __global__ __launch_bounds__(256) void k_multi_scalar(const ChainDesc* __restric
         item = __builtin_amdgcn_readfirstlane(item);
         if (item >= total_items) break;
         const ChainDesc& c = cd[chain_of(cd, n_chains, item)];
-        const ChainView& v = *c.view;
         const size_t first = size_t(item - c.item_begin) * (64u * K);
-        scan_wave<K>(v.pairs, v.rules, v.n_rules, packets_of(c), first, c.n, c.out_idx,
-                     c.out_act, v.dflt);
+        scan_wave<K>(c.pairs, c.rules, c.n_rules, packets_of(c), first, c.n, c.out_idx,
+                     c.out_act, c.dflt);
     }
 }
 
@@ -189,11 +188,10 @@ __global__ __launch_bounds__(256) void k_multi_vector(const ChainDesc* __restric
         item = __builtin_amdgcn_readfirstlane(item);
         if (item >= total_items) break;
         const ChainDesc& c = cd[chain_of(cd, n_chains, item)];
-        const ChainView& v = *c.view;
         const size_t first = size_t(item - c.item_begin) * (64u * K);
         WaveScan<K> w;
-        w.init(packets_of(c), first, c.n, v.dflt);
-        w.scan_vector(v.pairs, v.rules, v.n_rules);
+        w.init(packets_of(c), first, c.n, c.dflt);
+        w.scan_vector(c.pairs, c.rules, c.n_rules);
         w.store(c.out_idx, c.out_act, c.n);
     }
 }
@@ -216,19 +214,18 @@ __global__ __launch_bounds__(256) void k_multi_lds(const ChainDesc* __restrict__
         __syncthreads();
         if (item >= total_items) break;
         const ChainDesc& c = cd[chain_of(cd, n_chains, item)];
-        const ChainView& v = *c.view;
         const size_t first = size_t(item - c.item_begin) * (256u * K) + size_t(wave) * 64u * K;
         WaveScan<K> w;
         const bool active = first < c.n;
-        if (active) w.init(packets_of(c), first, c.n, v.dflt);
+        if (active) w.init(packets_of(c), first, c.n, c.dflt);
         int live = active && w.any_live();
-        for (uint32_t r0 = 0; r0 < v.n_rules; r0 += TILE) {
+        for (uint32_t r0 = 0; r0 < c.n_rules; r0 += TILE) {
             if (!__syncthreads_or(live)) break;
-            const uint32_t cnt = min(uint32_t(TILE), v.n_rules - r0);
-            const uint32_t* g = reinterpret_cast<const uint32_t*>(v.rules + r0);
+            const uint32_t cnt = min(uint32_t(TILE), c.n_rules - r0);
+            const uint32_t* g = reinterpret_cast<const uint32_t*>(c.rules + r0);
             uint32_t* l = reinterpret_cast<uint32_t*>(s_rules);
             for (uint32_t k = threadIdx.x; k < cnt * 8u; k += blockDim.x) l[k] = g[k];
-            for (uint32_t k = threadIdx.x; k < cnt; k += blockDim.x) s_pairs[k] = v.pairs[r0 + k];
+            for (uint32_t k = threadIdx.x; k < cnt; k += blockDim.x) s_pairs[k] = c.pairs[r0 + k];
             __syncthreads();
             if (live) live = w.template scan<FirstField::Dst>(s_pairs, s_rules, cnt, r0);
         }
@@ -343,6 +340,11 @@ hipError_t multi_launch(const fw_chain_batch* b, uint32_t n_chains, MultiConfig 
         std::memset(&d, 0, sizeof d);
         const ChainView* hv = nullptr;
         d.view = ruleset_chain_view(cb.rs, &hv);
+        d.rules = hv->rules;
+        d.pairs = hv->pairs;
+        d.n_rules = hv->n_rules;
+        d.dflt = hv->dflt;
+        d.has_index = hv->has_index;
         d.src = cb.pk.src_ip;
         d.dst = cb.pk.dst_ip;
         d.sport = cb.pk.src_port;
