@@ -417,8 +417,11 @@ def multichain_leg(seed: int, steps: int, log_fn):
     torch.cuda.synchronize()
     threads = max(1, min(16, os.cpu_count() or 1))
     want = [oracle.classify(r, p, threads=threads) for r, p in work]
+    # the scan's algorithmic work: first-match index + 1 per packet, else the chain's length
+    checks = int(sum(np.where(w[0] < 0, len(r), w[0].astype(np.int64) + 1).sum()
+                     for w, (r, _) in zip(want, work)))
     out = {"chains": len(items), "packets": total,
-           "rules_total": int(sum(len(r) for r, _ in work))}
+           "rules_total": int(sum(len(r) for r, _ in work)), "rule_checks": checks}
 
     call = fw.MultiBatch(items)        # marshalled once: the timed calls are the library's
 
@@ -429,6 +432,10 @@ def multichain_leg(seed: int, steps: int, log_fn):
         for cname, kw in configs.items():
             ms, _ = time_steps(lambda: call.run(stream=stream, **kw), steps, 2, stream)
             res["configs"][cname] = {"ms": ms, "mpps": total / ms / 1e3}
+            if name == "scan":
+                res["configs"][cname]["rule_checks_per_s"] = checks / (ms * 1e-3)
+                res["configs"][cname]["valu_frac"] = (checks * OPS_PER_CHECK / (ms * 1e-3)
+                                                      / 1e12 / VALU_INT32_PEAK_TOPS)
         reps = sorted([res["configs"]["tuned"]["ms"]] +
                       [time_steps(lambda: call.run(stream=stream), steps, 1, stream)[0]
                        for _ in range(5)])
@@ -455,7 +462,12 @@ def multichain_leg(seed: int, steps: int, log_fn):
         for rs, dp, oi, oa in items:
             rs.classify(dp, mode="packet_split", stream=stream, out_idx=oi, out_act=oa)
     ms, _ = time_steps(per_chain, steps, 2, stream)
-    out["scan"]["configs"]["one_launch_per_chain"] = {"ms": ms, "mpps": total / ms / 1e3}
+    out["scan"]["configs"]["one_launch_per_chain"] = {
+        "ms": ms, "mpps": total / ms / 1e3, "rule_checks_per_s": checks / (ms * 1e-3),
+        "valu_frac": checks * OPS_PER_CHECK / (ms * 1e-3) / 1e12 / VALU_INT32_PEAK_TOPS}
+    tuned = out["scan"]["configs"]["tuned"]
+    log_fn(f"  multichain scan: {checks} rule checks, tuned {tuned['rule_checks_per_s'] / 1e12:.2f} "
+           f"T checks/s, {tuned['valu_frac']:.3f} of the VALU peak at {OPS_PER_CHECK} ops per check")
 
     t0 = time.perf_counter()
     for k, rs in enumerate(rss):
@@ -547,6 +559,26 @@ def host_cpu_model() -> str:
     except OSError:
         pass
     return "unknown"
+
+
+def copy_peak_gbs(torch, stream, reps: int = 10) -> float:
+    """Measured HBM ceiling: a plain 256 MiB device-to-device copy (bytes read plus bytes
+    written per copy), median over `reps` event-timed copies on `stream`."""
+    a = torch.empty(64 << 20, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    b.copy_(a)
+    times = []
+    with torch.cuda.stream(stream):
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            b.copy_(a)
+            e1.record(stream)
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1) * 1e-3)
+    times.sort()
+    return 2 * a.numel() * 4 / times[len(times) // 2] / 1e9
 
 
 def cpu_baseline(rules, pk, n_sample: int, n_single: int = 1_048_576):
@@ -717,6 +749,8 @@ def main():
 
     head = next(iter(modes))
     ms = results[head]["ms"]
+    copy_gbs = copy_peak_gbs(torch, stream)
+    log(f"  device copy (256 MiB, median of 10): {copy_gbs:.0f} GB/s")
     traffic = committed_traffic(args.workload)
     counters = committed_valu_counters(args.workload)
 
@@ -733,6 +767,7 @@ def main():
              "ops_per_check": OPS_PER_CHECK,
              "algorithmic_hbm_bytes": n * BYTES_PER_PACKET,
              "hbm_gbs": hbm / t / 1e9, "hbm_frac": hbm / t / 1e9 / HBM_PEAK_GBS,
+             "hbm_copy_gbs": copy_gbs, "hbm_frac_of_copy": hbm / t / 1e9 / copy_gbs,
              "hbm_source": "rocprofv3 FETCH_SIZE + WRITE_SIZE" if tr is not None
                            else "algorithmic, 18 B per packet"}
         if "candidate_checks" in work:
