@@ -216,6 +216,13 @@ typedef struct fw_index_stats {
     float err_mean;         /* mean per-expert error bound */
     float loss1, loss2;     /* final training losses of stage 1 and stage 2 */
     float train_ms;         /* wall time of the GPU training */
+    uint32_t weights_rounded; /* stage-2 weights that IEEE half, the lookup's storage
+                               * for them, does not hold exactly even with each hidden
+                               * unit's exact power-of-two scaling chosen to avoid it;
+                               * rounded to nearest (an input weight whose unit has a
+                               * zero output weight is not counted: that unit adds
+                               * nothing); 0: the lookup's products are those of the
+                               * bf16 network */
     uint64_t device_bytes;  /* device memory held by the index */
 } fw_index_stats;
 

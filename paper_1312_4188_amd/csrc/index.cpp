@@ -55,6 +55,7 @@ struct LearnedIndex {
     ExpertMeta* d_meta = nullptr;
     std::vector<uint32_t> B, off, L_idx, G_idx, err;
     std::vector<float> weights;   // stage 1 then experts, bf16 values widened to float
+    uint32_t weights_rounded = 0; // stage-2 weights IEEE half does not hold exactly
     uint64_t device_bytes = 0;
 };
 
@@ -89,6 +90,23 @@ float from_bf16(uint16_t h) {
     return f;
 }
 
+// IEEE binary16 bits of f, rounded to nearest even.  A bf16 value (8
+// significant bits) converts exactly when its magnitude is 0 or at least
+// 2^-14, the smallest normal half; below that it is rounded to a multiple of
+// 2^-24.
+uint16_t to_f16(float f) {
+    const _Float16 h = static_cast<_Float16>(f);
+    uint16_t u;
+    std::memcpy(&u, &h, 2);
+    return u;
+}
+
+float from_f16(uint16_t u) {
+    _Float16 h;
+    std::memcpy(&h, &u, 2);
+    return static_cast<float>(h);
+}
+
 // splitmix64: a counter-based generator for the seeded weight initialisation.
 struct SplitMix {
     uint64_t s;
@@ -120,33 +138,57 @@ void init_network(float* p, uint32_t H, SplitMix& rng) {
 
 // Fold each hidden unit's ReLU into a clamp to [0, 1].  Unit (w1, b1, w2)
 // on inputs v in [0, 1] has pre-activation z = w1 v + b1 <= |w1| + |b1| < 2^k
-// for the k below; scaling w1 and b1 by 2^-k and w2 by 2^k leaves w2 max(z, 0)
-// unchanged, and since scaling by a power of two is exact in floating point
-// (bf16 and fp32 share the exponent range), the fp32 products and sums the
-// lookup forms are bit for bit those of the unscaled unit; the scaled
-// pre-activation is at most 1, so max(z, 0) equals clamp(z, 0, 1), which the
-// hardware applies to the multiply-add for free.  A unit whose scaled values
-// would not round-trip (far outside any trained range) is left as it is; the
-// error bounds are measured with the lookup's own arithmetic either way.
+// for every k from the one below up; scaling w1 and b1 by 2^-k and w2 by 2^k
+// leaves w2 max(z, 0) unchanged, and since scaling by a power of two is exact
+// in floating point (bf16 and fp32 share the exponent range), the fp32
+// products and sums the lookup forms are bit for bit those of the unscaled
+// unit; the scaled pre-activation is at most 1, so max(z, 0) equals
+// clamp(z, 0, 1), which the hardware applies to the multiply-add for free.
+// Among the first 24 such k, the smallest that `cost(w1', w2')` rates lowest
+// is taken (the stage-2 rows store w1' and w2' as IEEE half, which holds only
+// part of the fp32 range exactly).  A unit whose scaled values would not
+// round-trip (far outside any trained range) is left as it is; the error
+// bounds are measured with the lookup's own arithmetic either way.
 // `row` is one network in 32-slot segments [w1][b1][w2].
-template <class Get, class Put>
-void fold_relu(Get get, Put put) {
+template <class Get, class Put, class Cost>
+void fold_relu(Get get, Put put, Cost cost) {
     for (uint32_t i = 0; i < 32; ++i) {
         const float a = get(i), b = get(32 + i), c = get(64 + i);
         const float m = std::fabs(a) + std::fabs(b);
         if (!(m > 0.0f) || !std::isfinite(m)) continue;
-        int k = 0;
-        std::frexp(m, &k);                    // m < 2^k
-        const float a2 = std::ldexp(a, -k), b2 = std::ldexp(b, -k), c2 = std::ldexp(c, k);
-        const bool exact = std::ldexp(a2, k) == a && std::ldexp(b2, k) == b &&
-                           std::ldexp(c2, -k) == c && std::isfinite(c2) &&
-                           (a2 == 0.0f || std::isnormal(a2)) && (b2 == 0.0f || std::isnormal(b2)) &&
-                           (c2 == 0.0f || std::isnormal(c2));
-        if (!exact) continue;
-        put(i, a2);
-        put(32 + i, b2);
-        put(64 + i, c2);
+        int k0 = 0;
+        std::frexp(m, &k0);                   // m < 2^k0
+        int best = 0;
+        uint32_t best_cost = ~0u;
+        for (int k = k0; k < k0 + 24; ++k) {
+            const float a2 = std::ldexp(a, -k), b2 = std::ldexp(b, -k), c2 = std::ldexp(c, k);
+            const bool exact = std::ldexp(a2, k) == a && std::ldexp(b2, k) == b &&
+                               std::ldexp(c2, -k) == c && std::isfinite(c2) &&
+                               (a2 == 0.0f || std::isnormal(a2)) &&
+                               (b2 == 0.0f || std::isnormal(b2)) &&
+                               (c2 == 0.0f || std::isnormal(c2));
+            if (!exact) continue;
+            const uint32_t q = cost(a2, c2);
+            if (q < best_cost) {
+                best_cost = q;
+                best = k;
+            }
+            if (q == 0) break;
+        }
+        if (best_cost == ~0u) continue;
+        put(i, std::ldexp(a, -best));
+        put(32 + i, std::ldexp(b, -best));
+        put(64 + i, std::ldexp(c, best));
     }
+}
+
+// Whether IEEE half holds f exactly.
+bool half_exact(float f) { return from_f16(to_f16(f)) == f; }
+
+// Stage-2 weights of a unit that half would round: w2, and w1 unless w2 is
+// zero (the unit then adds exactly nothing, whatever w1 is).
+uint32_t half_rounding(float w1, float w2) {
+    return uint32_t(!half_exact(w2)) + uint32_t(w2 != 0.0f && !half_exact(w1));
 }
 
 // Slot of parameter k of the training layout [w1 (H), b1 (H), w2 (H), b2] in
@@ -329,12 +371,14 @@ std::vector<uint8_t> lds_image(const LearnedIndex* ix, const std::vector<float>&
     return img;
 }
 
-// Pair dword of a stage-2 hidden unit: w1's bf16 bits in the low half, and a
-// high half chosen so that the whole dword read as fp32, which the lookup
-// takes as the unit's bias, is the nearest such value to b1.  The low bits add
-// less than one bf16 step to the magnitude of the high half's value, so the
-// candidates are b1's own pattern and the one a step toward zero; the bias
-// applied is then within half a bf16 step of b1.
+// Pair dword of a stage-2 hidden unit: w1 as IEEE half in the low half (the
+// lookup's mixed-precision multiply-add reads it there as an fp16 operand; the
+// bf16 w1 converts exactly, see to_f16), and a high half chosen so that the
+// whole dword read as fp32, which the lookup takes as the unit's bias, is the
+// nearest such value to b1.  The low bits add less than one bf16 step to the
+// magnitude of the high half's value, so the candidates are b1's own pattern
+// and the one a step toward zero; the bias applied is then within half a bf16
+// step of b1.
 uint32_t pair_dword(uint16_t w1, uint16_t b1) {
     const float want = from_bf16(b1);
     auto as_float = [](uint32_t u) {
@@ -351,19 +395,25 @@ uint32_t pair_dword(uint16_t w1, uint16_t b1) {
 }
 
 // Stage-2 rows (see kRowDwords) from bf16 networks in 32-slot segments
-// [w1][b1][w2][b2]: dword k = pair_dword(w1[k], b1[k]); w2[k] and b2 widened
-// to fp32 (a bf16 value is the top half of its fp32 pattern); the expert's
-// key_lo, inv_span and pos_span beside the bias.
+// [w1][b1][w2][b2]: dword k = pair_dword(half w1[k], b1[k]); w2 as IEEE half,
+// two units to a dword (even unit in the low half); b2 widened to fp32 (a bf16
+// value is the top half of its fp32 pattern); the expert's key_lo, inv_span
+// and pos_span beside the bias.  *rounded counts the weights half does not
+// hold exactly (see half_rounding).
 std::vector<uint32_t> stage2_rows(const std::vector<uint16_t>& seg, uint32_t E,
-                                  const std::vector<ExpertMeta>& meta) {
+                                  const std::vector<ExpertMeta>& meta, uint32_t* rounded) {
     std::vector<uint32_t> out(size_t(E) * kRowDwords, 0);
+    *rounded = 0;
+    auto half = [](uint16_t bf) { return uint32_t(to_f16(from_bf16(bf))); };
     for (uint32_t e = 0; e < E; ++e) {
         const uint16_t* r = seg.data() + size_t(e) * kInferStride;
         uint32_t* o = out.data() + size_t(e) * kRowDwords;
         for (uint32_t k = 0; k < 32; ++k) {
-            o[kRowPairs + k] = pair_dword(r[k], r[32 + k]);
-            o[kRowOut + k] = uint32_t(r[64 + k]) << 16;
+            o[kRowPairs + k] = pair_dword(uint16_t(half(r[k])), r[32 + k]);
+            *rounded += half_rounding(from_bf16(r[k]), from_bf16(r[64 + k]));
         }
+        for (uint32_t k = 0; k < 16; ++k)
+            o[kRowOut + k] = half(r[64 + 2 * k]) | (half(r[64 + 2 * k + 1]) << 16);
         o[kRowBias] = uint32_t(r[96]) << 16;
         o[kRowKeyLo] = meta[e].key_lo;
         std::memcpy(&o[kRowInvSpan], &meta[e].inv_span, 4);
@@ -563,7 +613,8 @@ fw_status build_index(const fw_rule* rules, const RuleRec* recs, uint32_t n_rule
     std::vector<float> w1q(kGradCols, 0.0f);   // inference layout, see kInferStride
     for (uint32_t k = 0; k < P; ++k) w1q[infer_slot(k, H)] = from_bf16(to_bf16(w1[k]));
     std::vector<float> w1_trained(w1q);        // exported as trained; the lookup gets the fold
-    fold_relu([&](uint32_t k) { return w1q[k]; }, [&](uint32_t k, float v) { w1q[k] = v; });
+    fold_relu([&](uint32_t k) { return w1q[k]; }, [&](uint32_t k, float v) { w1q[k] = v; },
+              [](float, float) { return 0u; });   // stage 1 stays fp32
     if ((e = upload(ix->d_w1, w1q, s)) != hipSuccess)
         return fail_train(e, "uploading stage-1 weights");
 
@@ -650,9 +701,10 @@ fw_status build_index(const fw_rule* rules, const RuleRec* recs, uint32_t n_rule
         }
         uint16_t* row = w2q.data() + size_t(ex) * kInferStride;
         fold_relu([&](uint32_t k) { return from_bf16(row[k]); },
-                  [&](uint32_t k, float v) { row[k] = to_bf16(v); });   // exact: v is bf16
+                  [&](uint32_t k, float v) { row[k] = to_bf16(v); },    // exact: v is bf16
+                  half_rounding);
     }
-    const std::vector<uint32_t> w2r = stage2_rows(w2q, E, meta);
+    const std::vector<uint32_t> w2r = stage2_rows(w2q, E, meta, &ix->weights_rounded);
     if ((e = upload(ix->d_w2, w2r, s)) != hipSuccess ||
         (e = upload(ix->d_meta, meta, s)) != hipSuccess)
         return fail_train(e, "uploading stage-2 weights");
@@ -703,6 +755,7 @@ fw_status build_index(const fw_rule* rules, const RuleRec* recs, uint32_t n_rule
         stats->train_ms = float(std::chrono::duration<double, std::milli>(
                                     std::chrono::steady_clock::now() - t_start)
                                     .count());
+        stats->weights_rounded = ix->weights_rounded;
         stats->device_bytes = ix->device_bytes;
     }
     *out = ix;

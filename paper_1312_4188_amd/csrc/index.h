@@ -50,21 +50,24 @@ constexpr uint32_t kNoExpert = 0xFFFFFFFFu;
 // Inference layout of one stage-1 network (fp32): [w1][b1][w2][b2] in
 // 32-slot segments, padded to 104 entries (a multiple of 8); hidden units past
 // H are zero.  A stage-2 row (kRowDwords dwords) holds one expert: dword k
-// pairs w1[k] (bf16, low half) with b1[k] (the whole dword read as fp32, its
-// high half b1's bf16 pattern or the one next to it), dwords 32 + k hold
-// w2[k] and dword 64 holds b2, both as fp32 (bf16 values widened, exact);
-// dwords 65..67 carry the expert's input scaling (key_lo, inv_span) and
-// pos_span, read with the bias in one 16-byte load.  Rows of all-fp32 weights
-// would not fit the LDS budget of the lookup at 10,000 rules; fp32 w2 saves
-// the lookup one widening per unit.
+// pairs w1[k] (its bf16 value as IEEE half, low half) with b1[k] (the whole
+// dword read as fp32, its high half b1's bf16 pattern or the one next to it);
+// dwords 32..47 hold w2 as IEEE half, two units each (unit 2i in the low
+// half); dword 48 holds b2 as fp32 (its bf16 value widened, exact); dwords
+// 49..51 carry the expert's input scaling (key_lo, inv_span) and pos_span,
+// read with the bias in one 16-byte load.  The lookup's mixed-precision
+// multiply-adds read the half weights where they lie, so each hidden unit
+// costs two instructions and the row 13 16-byte LDS reads.  A bf16 value
+// converts to half exactly from 2^-14 up (half's normal range); the index
+// build counts any weight outside it (fw_index_stats.weights_rounded).
 constexpr uint32_t kInferStride = 104;
 constexpr uint32_t kRowPairs = 0;     // pair dword of hidden unit 0 in a stage-2 row
-constexpr uint32_t kRowOut = 32;      // dword of w2[0]
-constexpr uint32_t kRowBias = 64;     // dword of b2
-constexpr uint32_t kRowKeyLo = 65;    // ExpertMeta::key_lo
-constexpr uint32_t kRowInvSpan = 66;  // ExpertMeta::inv_span
-constexpr uint32_t kRowPosSpan = 67;  // ExpertMeta::pos_span
-constexpr uint32_t kRowDwords = 68;   // stage-2 row stride (a 16-byte multiple)
+constexpr uint32_t kRowOut = 32;      // dword of w2[0] (low half) and w2[1] (high half)
+constexpr uint32_t kRowBias = 48;     // dword of b2
+constexpr uint32_t kRowKeyLo = 49;    // ExpertMeta::key_lo
+constexpr uint32_t kRowInvSpan = 50;  // ExpertMeta::inv_span
+constexpr uint32_t kRowPosSpan = 51;  // ExpertMeta::pos_span
+constexpr uint32_t kRowDwords = 52;   // stage-2 row stride (a 16-byte multiple)
 
 
 // The per-lane lists are read with 32-bit buffer offsets: each list array is
@@ -82,8 +85,8 @@ struct LdsExpert {
 };
 
 // LDS stride of the expert rows, chosen so that lanes reading different
-// experts spread over all LDS banks: a row of 68 dwords puts expert e at
-// bank offset 68 e, which takes 8 values modulo 32 banks and 16 modulo 64
+// experts spread over all LDS banks: a row of 52 dwords puts expert e at
+// bank offset 52 e, which takes 8 values modulo 32 banks and 16 modulo 64
 // (each 16-byte read covering 4 banks); the 8-byte records take 32.
 static_assert(kRowDwords % 4 == 0 && kRowPosSpan < kRowDwords, "stage-2 row layout");
 

@@ -12,8 +12,8 @@ namespace fw {
 
 // ------------------------------------------------------------------ inference
 // Stage 1 is kept as fp32 (the bf16 values widened) in four 32-slot segments
-// [w1][b1][w2][b2]; stage 2 as rows of (w1, b1) pair dwords and widened w2, b2
-// (see kRowDwords).  Hidden units past H carry zero weights and add nothing.
+// [w1][b1][w2][b2]; stage 2 as rows of (half w1, b1) pair dwords and widened
+// w2, b2 (see kRowDwords).  Hidden units past H carry zero weights and add nothing.
 // Every routine below is shared by the error-bound kernel and the lookup
 // kernels, so the recorded error bounds describe exactly the lookup's
 // arithmetic.
@@ -59,11 +59,12 @@ __device__ __forceinline__ uint32_t route(const float* w1, uint32_t E, uint32_t 
 
 // Stage 2: position estimate of x inside expert e's range of positions (the
 // row carries the expert's input scaling and position span; pos_lo is its
-// first position).  Hidden unit k takes w1 from the low half of its pair
-// dword with one shift (exact) and its bias as the whole dword read as fp32
-// (the index build picks the high half for it), forms fp32 max(w1 v + b1, 0)
-// as one clamped multiply-add, and adds its fp32 w2 share with a second:
-// three instructions per unit.
+// first position).  Hidden unit k takes w1 as the fp16 value in the low half
+// of its pair dword and its bias as the whole dword read as fp32 (the index
+// build picks the high half for it), forms fp32 max(w1 v + b1, 0) as one
+// clamped mixed-precision multiply-add (the half operand widened exactly, the
+// arithmetic fp32), and adds its fp32 w2 share with a second: two
+// instructions per unit.
 __device__ __forceinline__ int32_t position(const uint32_t* row, int32_t pos_lo, uint32_t x) {
     const uint32_t key_lo = row[kRowKeyLo];
     const float inv_span = __uint_as_float(row[kRowInvSpan]);
@@ -71,16 +72,20 @@ __device__ __forceinline__ int32_t position(const uint32_t* row, int32_t pos_lo,
     const float v = x >= key_lo ? fminf(float(x - key_lo) * inv_span, 1.0f) : 0.0f;
     float y = __uint_as_float(row[kRowBias]);
 #pragma unroll
-    for (uint32_t c = 0; c < kSeg; c += 4) {
-        const uint4 p = *reinterpret_cast<const uint4*>(row + kRowPairs + c);
-        const float4 o = *reinterpret_cast<const float4*>(row + kRowOut + c);
-        const uint32_t pr[4] = {p.x, p.y, p.z, p.w};
-        const float op[4] = {o.x, o.y, o.z, o.w};
+    for (uint32_t c = 0; c < kSeg; c += 8) {
+        const uint4 p0 = *reinterpret_cast<const uint4*>(row + kRowPairs + c);
+        const uint4 p1 = *reinterpret_cast<const uint4*>(row + kRowPairs + c + 4);
+        const uint4 o = *reinterpret_cast<const uint4*>(row + kRowOut + c / 2);
+        const uint32_t pr[8] = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w};
+        const uint32_t oh[4] = {o.x, o.y, o.z, o.w};
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const float w1 = __uint_as_float(pr[i] << 16);
+        for (int i = 0; i < 8; ++i) {
+            const float w1 = float(__builtin_bit_cast(_Float16, uint16_t(pr[i] & 0xFFFFu)));
             const float b1 = __uint_as_float(pr[i]);
-            y = fmaf(op[i], relu01(fmaf(w1, v, b1)), y);
+            const uint32_t ob = oh[i / 2];
+            const float w2 = float(__builtin_bit_cast(
+                _Float16, uint16_t((i & 1) ? (ob >> 16) : (ob & 0xFFFFu))));
+            y = fmaf(w2, relu01(fmaf(w1, v, b1)), y);
         }
     }
     const float q = fminf(fmaxf(y * pos_span, 0.0f), pos_span);  // NaN -> 0

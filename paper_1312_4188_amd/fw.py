@@ -60,7 +60,8 @@ class IndexStats(ctypes.Structure):
                 ("n_list_entries", ctypes.c_uint64), ("max_list", ctypes.c_uint32),
                 ("err_max", ctypes.c_uint32), ("err_mean", ctypes.c_float),
                 ("loss1", ctypes.c_float), ("loss2", ctypes.c_float),
-                ("train_ms", ctypes.c_float), ("device_bytes", ctypes.c_uint64)]
+                ("train_ms", ctypes.c_float), ("weights_rounded", ctypes.c_uint32),
+                ("device_bytes", ctypes.c_uint64)]
 
 
 class ChainBatch(ctypes.Structure):

@@ -106,6 +106,8 @@ def test_learned_10000_rules_whole_batch(seed):
         say(f"learned 10000x16M seed={seed} build")
         st = rs.build_learned_index()
         say(f"  stats {st}")
+        # every stage-2 weight held exactly in the lookup's half storage
+        assert st["weights_rounded"] == 0
         for lookup in (0, 1):
             idx, act, miss = rs.classify(dp, mode="learned", lookup=lookup, count_misses=True)
             torch.cuda.synchronize()
@@ -139,6 +141,7 @@ def test_learned_50000_rule_chain(seed, all_dst):
         say(f"learned 50000-rule chain seed={seed} all_dst={all_dst} build")
         st = rs.build_learned_index(seed=seed)
         say(f"  stats {st}")
+        assert st["weights_rounded"] == 0
         if all_dst:
             assert st["n_boundaries"] * 4 > 80 * 1024
         for kw in (dict(), dict(packets_per_lane=1), dict(packets_per_lane=4),
