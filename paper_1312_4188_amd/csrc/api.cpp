@@ -13,6 +13,7 @@
 #include "../../include/fw.h"
 #include "fw_internal.h"
 #include "index.h"
+#include "guard.h"
 
 struct fw_ruleset {
     uint32_t n_rules = 0;
@@ -157,82 +158,86 @@ extern "C" {
 
 fw_status fw_load_ruleset(const fw_rule* rules, uint32_t n_rules, uint8_t default_action,
                           fw_ruleset** out) {
-    if (!out) return fail(FW_E_INVAL, "out is NULL");
-    *out = nullptr;
-    if (n_rules > 0 && !rules) return fail(FW_E_INVAL, "rules is NULL");
-    if (n_rules > kMaxRules) return fail(FW_E_INVAL, "at most %u rules", kMaxRules);
-    if (default_action > 1) return fail(FW_E_INVAL, "default_action must be 0 or 1");
-    for (uint32_t i = 0; i < n_rules; ++i) {
-        const fw_rule& r = rules[i];
-        if (r.src_plen > 32 || r.dst_plen > 32)
-            return fail(FW_E_INVAL, "rule %u: prefix length above 32", i);
-        if (r.sport_lo > r.sport_hi || r.dport_lo > r.dport_hi)
-            return fail(FW_E_INVAL, "rule %u: port range with lo > hi", i);
-        if (r.action > 1) return fail(FW_E_INVAL, "rule %u: action must be 0 or 1", i);
-    }
-    fw_ruleset* rs = new (std::nothrow) fw_ruleset();
-    if (!rs) return fail(FW_E_NOMEM, "host allocation failed");
-    try {
-        rs->source.assign(rules, rules + n_rules);
-        rs->h_rules.resize(n_rules);
-    } catch (...) {
-        delete rs;
-        return fail(FW_E_NOMEM, "host allocation failed");
-    }
-    for (uint32_t i = 0; i < n_rules; ++i) rs->h_rules[i] = compile_rule(rules[i], i);
-    rs->n_rules = n_rules;
-    rs->default_action = default_action;
-    std::vector<uint2> pairs(size_t(n_rules) + kPairPadding, uint2{0u, 0u});
-    for (uint32_t i = 0; i < n_rules; ++i)
-        pairs[i] = uint2{rs->h_rules[i].dst_lo, rs->h_rules[i].dst_w};
-    hipError_t e = hipGetDevice(&rs->device);
-    if (e == hipSuccess)
-        e = hipMalloc(&rs->d_rules, sizeof(RuleRec) * (n_rules ? n_rules : 1));
-    if (e == hipSuccess) e = hipMalloc(&rs->d_pairs, sizeof(uint2) * pairs.size());
-    if (e == hipSuccess && n_rules)
-        e = hipMemcpy(rs->d_rules, rs->h_rules.data(), sizeof(RuleRec) * n_rules,
-                      hipMemcpyHostToDevice);
-    if (e == hipSuccess)
-        e = hipMemcpy(rs->d_pairs, pairs.data(), sizeof(uint2) * pairs.size(),
-                      hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = make_plan(rs->h_rules.data(), n_rules, &rs->plan);
-    if (e == hipSuccess) {
-        ChainView& v = rs->h_view;
-        v.rules = rs->d_rules;
-        v.pairs = rs->d_pairs;
-        v.n_rules = n_rules;
-        v.dflt = default_action;
-        v.plan = rs->plan.plan;
-        e = hipMalloc(&rs->d_view, sizeof(ChainView));
-    }
-    if (e == hipSuccess) e = upload_view(rs);
-    if (e != hipSuccess) {
-        if (rs->d_view) (void)hipFree(rs->d_view);
-        if (rs->d_rules) (void)hipFree(rs->d_rules);
-        if (rs->d_pairs) (void)hipFree(rs->d_pairs);
-        free_plan(&rs->plan);
-        delete rs;
-        return hip_fail(e, "uploading the ruleset");
-    }
-    *out = rs;
-    return FW_OK;
+    return guarded([&]() -> fw_status {
+        if (!out) return fail(FW_E_INVAL, "out is NULL");
+        *out = nullptr;
+        if (n_rules > 0 && !rules) return fail(FW_E_INVAL, "rules is NULL");
+        if (n_rules > kMaxRules) return fail(FW_E_INVAL, "at most %u rules", kMaxRules);
+        if (default_action > 1) return fail(FW_E_INVAL, "default_action must be 0 or 1");
+        for (uint32_t i = 0; i < n_rules; ++i) {
+            const fw_rule& r = rules[i];
+            if (r.src_plen > 32 || r.dst_plen > 32)
+                return fail(FW_E_INVAL, "rule %u: prefix length above 32", i);
+            if (r.sport_lo > r.sport_hi || r.dport_lo > r.dport_hi)
+                return fail(FW_E_INVAL, "rule %u: port range with lo > hi", i);
+            if (r.action > 1) return fail(FW_E_INVAL, "rule %u: action must be 0 or 1", i);
+        }
+        fw_ruleset* rs = new (std::nothrow) fw_ruleset();
+        if (!rs) return fail(FW_E_NOMEM, "host allocation failed");
+        try {
+            rs->source.assign(rules, rules + n_rules);
+            rs->h_rules.resize(n_rules);
+        } catch (...) {
+            delete rs;
+            return fail(FW_E_NOMEM, "host allocation failed");
+        }
+        for (uint32_t i = 0; i < n_rules; ++i) rs->h_rules[i] = compile_rule(rules[i], i);
+        rs->n_rules = n_rules;
+        rs->default_action = default_action;
+        std::vector<uint2> pairs(size_t(n_rules) + kPairPadding, uint2{0u, 0u});
+        for (uint32_t i = 0; i < n_rules; ++i)
+            pairs[i] = uint2{rs->h_rules[i].dst_lo, rs->h_rules[i].dst_w};
+        hipError_t e = hipGetDevice(&rs->device);
+        if (e == hipSuccess)
+            e = hipMalloc(&rs->d_rules, sizeof(RuleRec) * (n_rules ? n_rules : 1));
+        if (e == hipSuccess) e = hipMalloc(&rs->d_pairs, sizeof(uint2) * pairs.size());
+        if (e == hipSuccess && n_rules)
+            e = hipMemcpy(rs->d_rules, rs->h_rules.data(), sizeof(RuleRec) * n_rules,
+                          hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(rs->d_pairs, pairs.data(), sizeof(uint2) * pairs.size(),
+                          hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = make_plan(rs->h_rules.data(), n_rules, &rs->plan);
+        if (e == hipSuccess) {
+            ChainView& v = rs->h_view;
+            v.rules = rs->d_rules;
+            v.pairs = rs->d_pairs;
+            v.n_rules = n_rules;
+            v.dflt = default_action;
+            v.plan = rs->plan.plan;
+            e = hipMalloc(&rs->d_view, sizeof(ChainView));
+        }
+        if (e == hipSuccess) e = upload_view(rs);
+        if (e != hipSuccess) {
+            if (rs->d_view) (void)hipFree(rs->d_view);
+            if (rs->d_rules) (void)hipFree(rs->d_rules);
+            if (rs->d_pairs) (void)hipFree(rs->d_pairs);
+            free_plan(&rs->plan);
+            delete rs;
+            return hip_fail(e, "uploading the ruleset");
+        }
+        *out = rs;
+        return FW_OK;
+    });
 }
 
 fw_status fw_free_ruleset(fw_ruleset* rs) {
-    if (!rs) return FW_OK;
-    hipError_t e = hipDeviceSynchronize();
-    destroy_index(rs->index);
-    rs->index = nullptr;
-    free_plan(&rs->plan);
-    for (void* p : {static_cast<void*>(rs->d_rules), static_cast<void*>(rs->d_pairs),
-                    static_cast<void*>(rs->d_view)}) {
-        if (!p) continue;
-        const hipError_t e2 = hipFree(p);
-        if (e == hipSuccess) e = e2;
-    }
-    delete rs;
-    if (e != hipSuccess) return hip_fail(e, "freeing the ruleset");
-    return FW_OK;
+    return guarded([&]() -> fw_status {
+        if (!rs) return FW_OK;
+        hipError_t e = hipDeviceSynchronize();
+        destroy_index(rs->index);
+        rs->index = nullptr;
+        free_plan(&rs->plan);
+        for (void* p : {static_cast<void*>(rs->d_rules), static_cast<void*>(rs->d_pairs),
+                        static_cast<void*>(rs->d_view)}) {
+            if (!p) continue;
+            const hipError_t e2 = hipFree(p);
+            if (e == hipSuccess) e = e2;
+        }
+        delete rs;
+        if (e != hipSuccess) return hip_fail(e, "freeing the ruleset");
+        return FW_OK;
+    });
 }
 
 uint32_t fw_ruleset_size(const fw_ruleset* rs) { return rs ? rs->n_rules : 0u; }
@@ -240,160 +245,174 @@ uint32_t fw_ruleset_size(const fw_ruleset* rs) { return rs ? rs->n_rules : 0u; }
 fw_status fw_classify_ex(const fw_ruleset* rs, const fw_packets* pk, size_t n,
                          int32_t* out_rule_idx, uint8_t* out_action,
                          const fw_classify_opts* opts) {
-    fw_classify_opts o{};
-    if (opts) o = *opts;
-    fw_status st = check_classify_args(rs, pk, n, out_rule_idx, out_action);
-    if (st != FW_OK) return st;
-    if (o.mode > FW_MODE_HYBRID) return fail(FW_E_INVAL, "unknown mode %u", o.mode);
-    if (o.packets_per_lane != 0 && o.packets_per_lane != 1 && o.packets_per_lane != 2 &&
-        o.packets_per_lane != 4)
-        return fail(FW_E_INVAL, "packets_per_lane must be 0, 1, 2 or 4");
-    uint32_t P = o.partitions ? o.partitions : 16u;
-    if (P > kMaxPartitions) return fail(FW_E_INVAL, "at most %u partitions", kMaxPartitions);
-    if (o.mode == FW_MODE_HYBRID && P > 16)
-        return fail(FW_E_INVAL, "hybrid mode takes 1..16 partitions (one wave each)");
-    if (o.mode == FW_MODE_LEARNED && !rs->index)
-        return fail(FW_E_NOINDEX, "no learned index: call fw_build_learned_index first");
-    if (n == 0) {
+    return guarded([&]() -> fw_status {
+        fw_classify_opts o{};
+        if (opts) o = *opts;
+        fw_status st = check_classify_args(rs, pk, n, out_rule_idx, out_action);
+        if (st != FW_OK) return st;
+        if (o.mode > FW_MODE_HYBRID) return fail(FW_E_INVAL, "unknown mode %u", o.mode);
+        if (o.packets_per_lane != 0 && o.packets_per_lane != 1 && o.packets_per_lane != 2 &&
+            o.packets_per_lane != 4)
+            return fail(FW_E_INVAL, "packets_per_lane must be 0, 1, 2 or 4");
+        uint32_t P = o.partitions ? o.partitions : 16u;
+        if (P > kMaxPartitions) return fail(FW_E_INVAL, "at most %u partitions", kMaxPartitions);
+        if (o.mode == FW_MODE_HYBRID && P > 16)
+            return fail(FW_E_INVAL, "hybrid mode takes 1..16 partitions (one wave each)");
+        if (o.mode == FW_MODE_LEARNED && !rs->index)
+            return fail(FW_E_NOINDEX, "no learned index: call fw_build_learned_index first");
+        if (n == 0) {
+            if (o.window_misses) *o.window_misses = 0;
+            return FW_OK;
+        }
+        st = check_device_state();
+        if (st != FW_OK) return st;
+        hipStream_t stream = static_cast<hipStream_t>(o.stream);
+        const PacketsDev pd = to_dev(pk);
+        uint32_t mode = o.mode;
+        // the split forms partition the rules up to and including the first catch-all: later
+        // rules can never be a first match
+        const uint32_t reachable =
+            rs->plan.plan.tail_idx == kNoMatch ? rs->n_rules : rs->plan.plan.tail_idx + 1u;
+        if (mode == FW_MODE_AUTO) {
+            if (rs->index) {
+                mode = FW_MODE_LEARNED;
+            } else {
+                const AutoChoice c = auto_scan_mode(n, reachable);
+                mode = c.mode;
+                if (c.partitions) P = c.partitions;
+            }
+        }
+        hipError_t e = hipSuccess;
+        switch (mode) {
+            case FW_MODE_PACKET_SPLIT:
+                e = launch_packet_split(rs->plan.plan, pd, n, out_rule_idx, out_action,
+                                        rs->default_action,
+                                        o.packets_per_lane ? int(o.packets_per_lane)
+                                                           : int(default_packets_per_lane(n, 4)),
+                                        stream);
+                break;
+            case FW_MODE_RULE_SPLIT:
+                e = launch_rule_split(rs->d_rules, reachable, P, pd, n, out_rule_idx, out_action,
+                                      rs->default_action, stream);
+                break;
+            case FW_MODE_HYBRID:
+                e = launch_hybrid(rs->d_pairs, rs->d_rules, reachable, P, pd, n, out_rule_idx,
+                                  out_action, rs->default_action,
+                                  o.packets_per_lane ? int(o.packets_per_lane)
+                                                     : int(hybrid_packets_per_lane(n, P)),
+                                  stream);
+                break;
+            case FW_MODE_LEARNED:
+                return classify_learned(rs->index, rs->default_action, pd, n, out_rule_idx,
+                                        out_action, o.lookup,
+                                        o.packets_per_lane ? o.packets_per_lane
+                                                           : default_packets_per_lane(n, 2),
+                                        stream, o.window_misses);
+            default:
+                return fail(FW_E_INVAL, "unknown mode %u", mode);
+        }
+        if (e != hipSuccess) return hip_fail(e, "kernel launch");
         if (o.window_misses) *o.window_misses = 0;
         return FW_OK;
-    }
-    st = check_device_state();
-    if (st != FW_OK) return st;
-    hipStream_t stream = static_cast<hipStream_t>(o.stream);
-    const PacketsDev pd = to_dev(pk);
-    uint32_t mode = o.mode;
-    // the split forms partition the rules up to and including the first catch-all: later
-    // rules can never be a first match
-    const uint32_t reachable =
-        rs->plan.plan.tail_idx == kNoMatch ? rs->n_rules : rs->plan.plan.tail_idx + 1u;
-    if (mode == FW_MODE_AUTO) {
-        if (rs->index) {
-            mode = FW_MODE_LEARNED;
-        } else {
-            const AutoChoice c = auto_scan_mode(n, reachable);
-            mode = c.mode;
-            if (c.partitions) P = c.partitions;
-        }
-    }
-    hipError_t e = hipSuccess;
-    switch (mode) {
-        case FW_MODE_PACKET_SPLIT:
-            e = launch_packet_split(rs->plan.plan, pd, n, out_rule_idx, out_action,
-                                    rs->default_action,
-                                    o.packets_per_lane ? int(o.packets_per_lane)
-                                                       : int(default_packets_per_lane(n, 4)),
-                                    stream);
-            break;
-        case FW_MODE_RULE_SPLIT:
-            e = launch_rule_split(rs->d_rules, reachable, P, pd, n, out_rule_idx, out_action,
-                                  rs->default_action, stream);
-            break;
-        case FW_MODE_HYBRID:
-            e = launch_hybrid(rs->d_pairs, rs->d_rules, reachable, P, pd, n, out_rule_idx,
-                              out_action, rs->default_action,
-                              o.packets_per_lane ? int(o.packets_per_lane)
-                                                 : int(hybrid_packets_per_lane(n, P)),
-                              stream);
-            break;
-        case FW_MODE_LEARNED:
-            return classify_learned(rs->index, rs->default_action, pd, n, out_rule_idx,
-                                    out_action, o.lookup,
-                                    o.packets_per_lane ? o.packets_per_lane
-                                                       : default_packets_per_lane(n, 2),
-                                    stream, o.window_misses);
-        default:
-            return fail(FW_E_INVAL, "unknown mode %u", mode);
-    }
-    if (e != hipSuccess) return hip_fail(e, "kernel launch");
-    if (o.window_misses) *o.window_misses = 0;
-    return FW_OK;
+    });
 }
 
 fw_status fw_classify(const fw_ruleset* rs, const fw_packets* pk, size_t n,
                       int32_t* out_rule_idx, uint8_t* out_action) {
-    return fw_classify_ex(rs, pk, n, out_rule_idx, out_action, nullptr);
+    return guarded([&]() -> fw_status {
+        return fw_classify_ex(rs, pk, n, out_rule_idx, out_action, nullptr);
+    });
 }
 
 fw_status fw_closed_loop(const fw_ruleset* rs, const fw_packets* pk, uint32_t n_batches,
                          const size_t* start, const size_t* count, int32_t* out_rule_idx,
                          uint8_t* out_action, const fw_classify_opts* opts, double* seconds) {
-    if (!rs || !pk) return fail(FW_E_INVAL, "ruleset or packets is NULL");
-    if (n_batches == 0) return FW_OK;
-    if (!start || !count || !seconds) return fail(FW_E_INVAL, "NULL argument");
-    // checked here, before the slices are offset (an offset NULL is not NULL)
-    if (!pk->src_ip || !pk->dst_ip || !pk->src_port || !pk->dst_port || !pk->proto)
-        return fail(FW_E_INVAL, "a packet field pointer is NULL");
-    fw_classify_opts o{};
-    if (opts) o = *opts;
-    hipStream_t stream = static_cast<hipStream_t>(o.stream);
-    for (uint32_t k = 0; k < n_batches; ++k) {
-        if (start[k] % 16u) return fail(FW_E_ALIGN, "batch %u starts at %zu, not a multiple of 16",
-                                        k, start[k]);
-        const size_t s0 = start[k];
-        const fw_packets sub{pk->src_ip + s0, pk->dst_ip + s0, pk->src_port + s0,
-                             pk->dst_port + s0, pk->proto + s0};
-        const auto t0 = std::chrono::steady_clock::now();
-        const fw_status st = fw_classify_ex(rs, &sub, count[k], out_rule_idx, out_action, &o);
-        if (st != FW_OK) return st;
-        const hipError_t e = hipStreamSynchronize(stream);
-        if (e != hipSuccess) return hip_fail(e, "closed-loop batch");
-        seconds[k] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    }
-    return FW_OK;
+    return guarded([&]() -> fw_status {
+        if (!rs || !pk) return fail(FW_E_INVAL, "ruleset or packets is NULL");
+        if (n_batches == 0) return FW_OK;
+        if (!start || !count || !seconds) return fail(FW_E_INVAL, "NULL argument");
+        // checked here, before the slices are offset (an offset NULL is not NULL)
+        if (!pk->src_ip || !pk->dst_ip || !pk->src_port || !pk->dst_port || !pk->proto)
+            return fail(FW_E_INVAL, "a packet field pointer is NULL");
+        fw_classify_opts o{};
+        if (opts) o = *opts;
+        hipStream_t stream = static_cast<hipStream_t>(o.stream);
+        for (uint32_t k = 0; k < n_batches; ++k) {
+            if (start[k] % 16u)
+                return fail(FW_E_ALIGN, "batch %u starts at %zu, not a multiple of 16", k,
+                            start[k]);
+            const size_t s0 = start[k];
+            const fw_packets sub{pk->src_ip + s0, pk->dst_ip + s0, pk->src_port + s0,
+                                 pk->dst_port + s0, pk->proto + s0};
+            const auto t0 = std::chrono::steady_clock::now();
+            const fw_status st = fw_classify_ex(rs, &sub, count[k], out_rule_idx, out_action, &o);
+            if (st != FW_OK) return st;
+            const hipError_t e = hipStreamSynchronize(stream);
+            if (e != hipSuccess) return hip_fail(e, "closed-loop batch");
+            seconds[k] =
+                std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        }
+        return FW_OK;
+    });
 }
 
 fw_status fw_build_learned_index(fw_ruleset* rs, const fw_index_opts* opts,
                                  fw_index_stats* stats) {
-    if (!rs) return fail(FW_E_INVAL, "ruleset is NULL");
-    fw_index_opts o{};
-    if (opts) o = *opts;
-    LearnedIndex* built = nullptr;
-    const fw_status st = build_index(rs->source.data(), rs->h_rules.data(), rs->n_rules, o,
-                                     stats, &built);
-    if (st != FW_OK) return st;
-    // classifications enqueued earlier may still read the old index or the ruleset's view
-    hipError_t e = hipDeviceSynchronize();
-    if (e != hipSuccess) {
-        destroy_index(built);
-        return hip_fail(e, "waiting for work on the previous index");
-    }
-    ChainView v = rs->h_view;
-    index_chain_view(built, &v);
-    const ChainView old_view = rs->h_view;
-    rs->h_view = v;
-    e = upload_view(rs);
-    if (e != hipSuccess) {
-        rs->h_view = old_view;
-        (void)upload_view(rs);
-        destroy_index(built);
-        return hip_fail(e, "publishing the learned index");
-    }
-    if (rs->index) destroy_index(rs->index);
-    rs->index = built;
-    return FW_OK;
+    return guarded([&]() -> fw_status {
+        if (!rs) return fail(FW_E_INVAL, "ruleset is NULL");
+        fw_index_opts o{};
+        if (opts) o = *opts;
+        LearnedIndex* built = nullptr;
+        const fw_status st = build_index(rs->source.data(), rs->h_rules.data(), rs->n_rules, o,
+                                         stats, &built);
+        if (st != FW_OK) return st;
+        // classifications enqueued earlier may still read the old index or the ruleset's view
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) {
+            destroy_index(built);
+            return hip_fail(e, "waiting for work on the previous index");
+        }
+        ChainView v = rs->h_view;
+        index_chain_view(built, &v);
+        const ChainView old_view = rs->h_view;
+        rs->h_view = v;
+        e = upload_view(rs);
+        if (e != hipSuccess) {
+            rs->h_view = old_view;
+            (void)upload_view(rs);
+            destroy_index(built);
+            return hip_fail(e, "publishing the learned index");
+        }
+        if (rs->index) destroy_index(rs->index);
+        rs->index = built;
+        return FW_OK;
+    });
 }
 
 fw_status fw_index_lookup(const fw_ruleset* rs, const uint32_t* keys, size_t n,
                           int32_t* out_interval, uint32_t lookup, void* stream) {
-    if (!rs) return fail(FW_E_INVAL, "ruleset is NULL");
-    if (!rs->index) return fail(FW_E_NOINDEX, "no learned index");
-    if (n == 0) return FW_OK;
-    if (!keys || !out_interval) return fail(FW_E_INVAL, "NULL buffer");
-    if (!aligned16(keys) || !aligned16(out_interval))
-        return fail(FW_E_ALIGN, "buffers must be 16-byte aligned");
-    if (lookup > 1) return fail(FW_E_INVAL, "lookup must be 0 or 1");
-    const fw_status st = check_device_state();
-    if (st != FW_OK) return st;
-    return index_lookup(rs->index, keys, n, out_interval, lookup,
-                        static_cast<hipStream_t>(stream));
+    return guarded([&]() -> fw_status {
+        if (!rs) return fail(FW_E_INVAL, "ruleset is NULL");
+        if (!rs->index) return fail(FW_E_NOINDEX, "no learned index");
+        if (n == 0) return FW_OK;
+        if (!keys || !out_interval) return fail(FW_E_INVAL, "NULL buffer");
+        if (!aligned16(keys) || !aligned16(out_interval))
+            return fail(FW_E_ALIGN, "buffers must be 16-byte aligned");
+        if (lookup > 1) return fail(FW_E_INVAL, "lookup must be 0 or 1");
+        const fw_status st = check_device_state();
+        if (st != FW_OK) return st;
+        return index_lookup(rs->index, keys, n, out_interval, lookup,
+                            static_cast<hipStream_t>(stream));
+    });
 }
 
 fw_status fw_index_export(const fw_ruleset* rs, uint32_t what, void* host, size_t cap,
                           size_t* size) {
-    if (!rs) return fail(FW_E_INVAL, "ruleset is NULL");
-    if (!rs->index) return fail(FW_E_NOINDEX, "no learned index");
-    return index_export(rs->index, what, host, cap, size);
+    return guarded([&]() -> fw_status {
+        if (!rs) return fail(FW_E_INVAL, "ruleset is NULL");
+        if (!rs->index) return fail(FW_E_NOINDEX, "no learned index");
+        return index_export(rs->index, what, host, cap, size);
+    });
 }
 
 const char* fw_last_error(void) { return g_last_error.c_str(); }

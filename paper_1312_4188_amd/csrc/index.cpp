@@ -26,6 +26,7 @@
 
 #include "index.h"
 #include "lists.h"
+#include "guard.h"
 
 namespace fw {
 
@@ -850,62 +851,70 @@ extern "C" {
 fw_status fw_rmi_gradients(uint32_t E, uint32_t H, const float* params, size_t n, const float* u,
                            const float* t, const uint32_t* expert, uint32_t use_mfma, float* grad,
                            float* loss) {
-    if (E == 0 || E > kMaxExperts) return fail(FW_E_INVAL, "E must be 1..%u", kMaxExperts);
-    if (H == 0 || H > kMaxHidden) return fail(FW_E_INVAL, "H must be 1..%u", kMaxHidden);
-    if (!params || !grad || (n && (!u || !t || !expert)))
-        return fail(FW_E_INVAL, "NULL argument");
-    if (n > (size_t(1) << 31)) return fail(FW_E_INVAL, "at most 2^31 samples");
-    for (size_t k = 0; k < n; ++k)
-        if (expert[k] >= E) return fail(FW_E_INVAL, "sample %zu: network index out of range", k);
-    const uint32_t P = 3 * H + 1;
-    std::vector<size_t> order(n);
-    std::iota(order.begin(), order.end(), size_t(0));
-    std::stable_sort(order.begin(), order.end(),
-                     [&](size_t a, size_t b) { return expert[a] < expert[b]; });
-    std::vector<float> hu(n), ht(n);
-    std::vector<uint32_t> hex(n);
-    for (size_t k = 0; k < n; ++k) {
-        hu[k] = u[order[k]];
-        ht[k] = t[order[k]];
-        hex[k] = expert[order[k]];
-    }
-    std::vector<float> hp(params, params + size_t(E) * P);
-    hipStream_t s = nullptr;
-    Trainer tr;
-    hipError_t e = tr.init(E, H, n, use_mfma != 0, s);
-    if (e == hipSuccess) e = tr.load(hu, ht, hex, hp, s);
-    if (e == hipSuccess) e = tr.gradients(s);
-    if (e == hipSuccess)
-        e = hipMemcpy(grad, tr.grad, sizeof(float) * size_t(E) * P, hipMemcpyDeviceToHost);
-    if (e == hipSuccess && loss) e = hipMemcpy(loss, tr.loss, sizeof(float) * E, hipMemcpyDeviceToHost);
-    tr.release();
-    if (e != hipSuccess) return hip_fail(e, "gradient kernels");
-    return FW_OK;
+    return guarded([&]() -> fw_status {
+        if (E == 0 || E > kMaxExperts) return fail(FW_E_INVAL, "E must be 1..%u", kMaxExperts);
+        if (H == 0 || H > kMaxHidden) return fail(FW_E_INVAL, "H must be 1..%u", kMaxHidden);
+        if (!params || !grad || (n && (!u || !t || !expert)))
+            return fail(FW_E_INVAL, "NULL argument");
+        if (n > (size_t(1) << 31)) return fail(FW_E_INVAL, "at most 2^31 samples");
+        for (size_t k = 0; k < n; ++k)
+            if (expert[k] >= E)
+                return fail(FW_E_INVAL, "sample %zu: network index out of range", k);
+        const uint32_t P = 3 * H + 1;
+        std::vector<size_t> order(n);
+        std::iota(order.begin(), order.end(), size_t(0));
+        std::stable_sort(order.begin(), order.end(),
+                         [&](size_t a, size_t b) { return expert[a] < expert[b]; });
+        std::vector<float> hu(n), ht(n);
+        std::vector<uint32_t> hex(n);
+        for (size_t k = 0; k < n; ++k) {
+            hu[k] = u[order[k]];
+            ht[k] = t[order[k]];
+            hex[k] = expert[order[k]];
+        }
+        std::vector<float> hp(params, params + size_t(E) * P);
+        hipStream_t s = nullptr;
+        Trainer tr;
+        hipError_t e = tr.init(E, H, n, use_mfma != 0, s);
+        if (e == hipSuccess) e = tr.load(hu, ht, hex, hp, s);
+        if (e == hipSuccess) e = tr.gradients(s);
+        if (e == hipSuccess)
+            e = hipMemcpy(grad, tr.grad, sizeof(float) * size_t(E) * P, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && loss)
+            e = hipMemcpy(loss, tr.loss, sizeof(float) * E, hipMemcpyDeviceToHost);
+        tr.release();
+        if (e != hipSuccess) return hip_fail(e, "gradient kernels");
+        return FW_OK;
+    });
 }
 
 fw_status fw_rmi_adam_step(size_t count, float* params, const float* grad, float* m, float* v,
                            uint32_t step, float lr, float beta1, float beta2, float eps) {
-    if (!params || !grad || !m || !v) return fail(FW_E_INVAL, "NULL argument");
-    if (step == 0) return fail(FW_E_INVAL, "step counts from 1");
-    if (count > (size_t(1) << 31)) return fail(FW_E_INVAL, "at most 2^31 parameters");
-    if (count == 0) return FW_OK;
-    float* d = nullptr;
-    hipError_t e = hipMalloc(&d, sizeof(float) * count * 4);
-    if (e != hipSuccess) return hip_fail(e, "allocation");
-    float *dp = d, *dg = d + count, *dm = d + 2 * count, *dv = d + 3 * count;
-    e = hipMemcpy(dp, params, sizeof(float) * count, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(dg, grad, sizeof(float) * count, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(dm, m, sizeof(float) * count, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(dv, v, sizeof(float) * count, hipMemcpyHostToDevice);
-    const float bc1 = float(1.0 - std::pow(double(beta1), double(step)));
-    const float bc2 = float(1.0 - std::pow(double(beta2), double(step)));
-    if (e == hipSuccess) e = launch_adam(dp, dg, dm, dv, count, lr, beta1, beta2, eps, bc1, bc2, nullptr);
-    if (e == hipSuccess) e = hipMemcpy(params, dp, sizeof(float) * count, hipMemcpyDeviceToHost);
-    if (e == hipSuccess) e = hipMemcpy(m, dm, sizeof(float) * count, hipMemcpyDeviceToHost);
-    if (e == hipSuccess) e = hipMemcpy(v, dv, sizeof(float) * count, hipMemcpyDeviceToHost);
-    (void)hipFree(d);
-    if (e != hipSuccess) return hip_fail(e, "Adam kernel");
-    return FW_OK;
+    return guarded([&]() -> fw_status {
+        if (!params || !grad || !m || !v) return fail(FW_E_INVAL, "NULL argument");
+        if (step == 0) return fail(FW_E_INVAL, "step counts from 1");
+        if (count > (size_t(1) << 31)) return fail(FW_E_INVAL, "at most 2^31 parameters");
+        if (count == 0) return FW_OK;
+        float* d = nullptr;
+        hipError_t e = hipMalloc(&d, sizeof(float) * count * 4);
+        if (e != hipSuccess) return hip_fail(e, "allocation");
+        float *dp = d, *dg = d + count, *dm = d + 2 * count, *dv = d + 3 * count;
+        e = hipMemcpy(dp, params, sizeof(float) * count, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(dg, grad, sizeof(float) * count, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(dm, m, sizeof(float) * count, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(dv, v, sizeof(float) * count, hipMemcpyHostToDevice);
+        const float bc1 = float(1.0 - std::pow(double(beta1), double(step)));
+        const float bc2 = float(1.0 - std::pow(double(beta2), double(step)));
+        if (e == hipSuccess)
+            e = launch_adam(dp, dg, dm, dv, count, lr, beta1, beta2, eps, bc1, bc2, nullptr);
+        if (e == hipSuccess)
+            e = hipMemcpy(params, dp, sizeof(float) * count, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(m, dm, sizeof(float) * count, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(v, dv, sizeof(float) * count, hipMemcpyDeviceToHost);
+        (void)hipFree(d);
+        if (e != hipSuccess) return hip_fail(e, "Adam kernel");
+        return FW_OK;
+    });
 }
 
 }  // extern "C"

@@ -32,6 +32,7 @@
 #include "learned_core.h"
 #include "multi.h"
 #include "scan_core.h"
+#include "guard.h"
 
 struct fw_ruleset;
 
@@ -497,94 +498,101 @@ extern "C" {
 
 fw_status fw_classify_multi(const fw_chain_batch* batches, uint32_t n_chains,
                             const fw_multi_opts* opts) {
-    fw_multi_opts o{};
-    if (opts) o = *opts;
-    fw_status st = check_multi_batches(batches, n_chains);
-    if (st != FW_OK) return st;
-    MultiConfig cfg;
-    st = resolve(batches, n_chains, o, &cfg);
-    if (st != FW_OK) return st;
-    const hipError_t e = multi_launch(batches, n_chains, cfg, static_cast<hipStream_t>(o.stream),
-                                      nullptr, nullptr);
-    if (e != hipSuccess) return hip_fail(e, "multi-chain launch");
-    return FW_OK;
+    return guarded([&]() -> fw_status {
+        fw_multi_opts o{};
+        if (opts) o = *opts;
+        fw_status st = check_multi_batches(batches, n_chains);
+        if (st != FW_OK) return st;
+        MultiConfig cfg;
+        st = resolve(batches, n_chains, o, &cfg);
+        if (st != FW_OK) return st;
+        const hipError_t e = multi_launch(batches, n_chains, cfg,
+                                          static_cast<hipStream_t>(o.stream), nullptr, nullptr);
+        if (e != hipSuccess) return hip_fail(e, "multi-chain launch");
+        return FW_OK;
+    });
 }
 
 fw_status fw_classify_multi_noalloc(const fw_chain_batch* batches, uint32_t n_chains,
                                     const fw_multi_opts* opts) {
-    fw_multi_opts o{};
-    if (opts) o = *opts;
-    if (n_chains > kMultiMaxChains)
-        return fail(FW_E_INVAL, "fw_classify_multi_noalloc takes at most %u chains (got %u)",
-                    kMultiMaxChains, n_chains);
-    fw_status st = check_multi_batches(batches, n_chains);
-    if (st != FW_OK) return st;
-    MultiConfig cfg;
-    st = resolve(batches, n_chains, o, &cfg);
-    if (st != FW_OK) return st;
-    void* mem = nullptr;
-    hipError_t e = scratch_address(&mem);
-    if (e != hipSuccess) return hip_fail(e, "looking up the scratch array");
-    e = multi_launch(batches, n_chains, cfg, static_cast<hipStream_t>(o.stream), mem, nullptr);
-    if (e != hipSuccess) return hip_fail(e, "multi-chain launch (no allocation)");
-    return FW_OK;
+    return guarded([&]() -> fw_status {
+        fw_multi_opts o{};
+        if (opts) o = *opts;
+        if (n_chains > kMultiMaxChains)
+            return fail(FW_E_INVAL, "fw_classify_multi_noalloc takes at most %u chains (got %u)",
+                        kMultiMaxChains, n_chains);
+        fw_status st = check_multi_batches(batches, n_chains);
+        if (st != FW_OK) return st;
+        MultiConfig cfg;
+        st = resolve(batches, n_chains, o, &cfg);
+        if (st != FW_OK) return st;
+        void* mem = nullptr;
+        hipError_t e = scratch_address(&mem);
+        if (e != hipSuccess) return hip_fail(e, "looking up the scratch array");
+        e = multi_launch(batches, n_chains, cfg, static_cast<hipStream_t>(o.stream), mem, nullptr);
+        if (e != hipSuccess) return hip_fail(e, "multi-chain launch (no allocation)");
+        return FW_OK;
+    });
 }
 
 fw_status fw_autotune_multi(const fw_chain_batch* batches, uint32_t n_chains, void* stream,
                             fw_multi_opts* best, float* best_ms) {
-    fw_status st = check_multi_batches(batches, n_chains);
-    if (st != FW_OK) return st;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    hipEvent_t a = nullptr, z = nullptr;
-    hipError_t e = hipEventCreate(&a);
-    if (e == hipSuccess) e = hipEventCreate(&z);
-    MultiConfig win;
-    float win_ms = -1.0f;
-    MultiConfig placements[5];
-    placements[0].placement = kPlaceAuto;
-    placements[1].placement = kPlaceScalar;
-    placements[2].placement = kPlaceVector;
-    placements[3].placement = kPlaceLds;
-    placements[3].tile = 256;
-    placements[4].placement = kPlaceLds;
-    placements[4].tile = 1024;
-    for (int K : {1, 2, 4}) {
-        for (MultiConfig c : placements) {
-            if (e != hipSuccess) break;
-            c.K = K;
-            e = multi_launch(batches, n_chains, c, s, nullptr, nullptr);   // warm-up
-            float ms_best = -1.0f;
-            for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
-                e = hipEventRecord(a, s);
-                if (e == hipSuccess) e = multi_launch(batches, n_chains, c, s, nullptr, nullptr);
-                if (e == hipSuccess) e = hipEventRecord(z, s);
-                if (e == hipSuccess) e = hipEventSynchronize(z);
-                float ms = 0.0f;
-                if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, z);
-                if (e == hipSuccess && (ms_best < 0 || ms < ms_best)) ms_best = ms;
-            }
-            if (e == hipSuccess && (win_ms < 0 || ms_best < win_ms)) {
-                win_ms = ms_best;
-                win = c;
+    return guarded([&]() -> fw_status {
+        fw_status st = check_multi_batches(batches, n_chains);
+        if (st != FW_OK) return st;
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        hipEvent_t a = nullptr, z = nullptr;
+        hipError_t e = hipEventCreate(&a);
+        if (e == hipSuccess) e = hipEventCreate(&z);
+        MultiConfig win;
+        float win_ms = -1.0f;
+        MultiConfig placements[5];
+        placements[0].placement = kPlaceAuto;
+        placements[1].placement = kPlaceScalar;
+        placements[2].placement = kPlaceVector;
+        placements[3].placement = kPlaceLds;
+        placements[3].tile = 256;
+        placements[4].placement = kPlaceLds;
+        placements[4].tile = 1024;
+        for (int K : {1, 2, 4}) {
+            for (MultiConfig c : placements) {
+                if (e != hipSuccess) break;
+                c.K = K;
+                e = multi_launch(batches, n_chains, c, s, nullptr, nullptr);   // warm-up
+                float ms_best = -1.0f;
+                for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+                    e = hipEventRecord(a, s);
+                    if (e == hipSuccess)
+                        e = multi_launch(batches, n_chains, c, s, nullptr, nullptr);
+                    if (e == hipSuccess) e = hipEventRecord(z, s);
+                    if (e == hipSuccess) e = hipEventSynchronize(z);
+                    float ms = 0.0f;
+                    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, z);
+                    if (e == hipSuccess && (ms_best < 0 || ms < ms_best)) ms_best = ms;
+                }
+                if (e == hipSuccess && (win_ms < 0 || ms_best < win_ms)) {
+                    win_ms = ms_best;
+                    win = c;
+                }
             }
         }
-    }
-    if (a) (void)hipEventDestroy(a);
-    if (z) (void)hipEventDestroy(z);
-    if (e != hipSuccess) return hip_fail(e, "autotuning");
-    {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tuned[shape_key(batches, n_chains)] = win;
-    }
-    if (best) {
-        std::memset(best, 0, sizeof *best);
-        best->stream = stream;
-        best->packets_per_lane = uint32_t(win.K);
-        best->placement = win.placement;
-        best->rule_tile = win.tile;
-    }
-    if (best_ms) *best_ms = win_ms;
-    return FW_OK;
+        if (a) (void)hipEventDestroy(a);
+        if (z) (void)hipEventDestroy(z);
+        if (e != hipSuccess) return hip_fail(e, "autotuning");
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tuned[shape_key(batches, n_chains)] = win;
+        }
+        if (best) {
+            std::memset(best, 0, sizeof *best);
+            best->stream = stream;
+            best->packets_per_lane = uint32_t(win.K);
+            best->placement = win.placement;
+            best->rule_tile = win.tile;
+        }
+        if (best_ms) *best_ms = win_ms;
+        return FW_OK;
+    });
 }
 
 }  // extern "C"

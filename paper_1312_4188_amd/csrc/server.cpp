@@ -38,6 +38,7 @@
 #include "arena.h"
 #include "index.h"
 #include "multi.h"
+#include "guard.h"
 
 namespace fw {
 extern thread_local std::string g_last_error;
@@ -346,169 +347,204 @@ extern "C" {
 
 fw_status fw_server_create(fw_ruleset* const* chains, uint32_t n_chains, const fw_server_opts* opts,
                            fw_server** out) {
-    if (!out) return fail(FW_E_INVAL, "out is NULL");
-    *out = nullptr;
-    if (!chains || n_chains == 0) return fail(FW_E_INVAL, "no chains");
-    for (uint32_t c = 0; c < n_chains; ++c)
-        if (!chains[c]) return fail(FW_E_INVAL, "chain %u is NULL", c);
-    fw_server_opts o{};
-    if (opts) o = *opts;
-    if (o.slots == 0) o.slots = 4;
-    if (o.slots > kMaxSlots) return fail(FW_E_INVAL, "at most %u slots", kMaxSlots);
-    if (o.max_group == 0) o.max_group = kMultiMaxChains;
-    if (o.max_group_packets == 0) o.max_group_packets = uint64_t(1) << 20;
-    if (o.max_group > kMultiMaxChains)
-        return fail(FW_E_INVAL, "at most %u requests per group", kMultiMaxChains);
-    if (o.mem_budget == 0) o.mem_budget = uint64_t(256) << 20;
-    if (o.ingest > 1) return fail(FW_E_INVAL, "ingest must be 0 (copies) or 1 (mapped)");
-    if (o.mode != FW_MODE_AUTO && o.mode != FW_MODE_PACKET_SPLIT && o.mode != FW_MODE_LEARNED)
-        return fail(FW_E_INVAL,
-                    "serving mode must be AUTO, PACKET_SPLIT or LEARNED (groups run as one "
-                    "multi-chain launch)");
-    if (o.mode == FW_MODE_LEARNED) {
-        for (uint32_t c = 0; c < n_chains; ++c) {
-            const ChainView* hv = nullptr;
-            ruleset_chain_view(chains[c], &hv);
-            if (!hv->has_index)
-                return fail(FW_E_NOINDEX, "chain %u has no learned index (mode LEARNED)", c);
+    return guarded([&]() -> fw_status {
+        if (!out) return fail(FW_E_INVAL, "out is NULL");
+        *out = nullptr;
+        if (!chains || n_chains == 0) return fail(FW_E_INVAL, "no chains");
+        for (uint32_t c = 0; c < n_chains; ++c)
+            if (!chains[c]) return fail(FW_E_INVAL, "chain %u is NULL", c);
+        fw_server_opts o{};
+        if (opts) o = *opts;
+        if (o.slots == 0) o.slots = 4;
+        if (o.slots > kMaxSlots) return fail(FW_E_INVAL, "at most %u slots", kMaxSlots);
+        if (o.max_group == 0) o.max_group = kMultiMaxChains;
+        if (o.max_group_packets == 0) o.max_group_packets = uint64_t(1) << 20;
+        if (o.max_group > kMultiMaxChains)
+            return fail(FW_E_INVAL, "at most %u requests per group", kMultiMaxChains);
+        if (o.mem_budget == 0) o.mem_budget = uint64_t(256) << 20;
+        if (o.ingest > 1) return fail(FW_E_INVAL, "ingest must be 0 (copies) or 1 (mapped)");
+        if (o.mode != FW_MODE_AUTO && o.mode != FW_MODE_PACKET_SPLIT && o.mode != FW_MODE_LEARNED)
+            return fail(FW_E_INVAL,
+                        "serving mode must be AUTO, PACKET_SPLIT or LEARNED (groups run as one "
+                        "multi-chain launch)");
+        if (o.mode == FW_MODE_LEARNED) {
+            for (uint32_t c = 0; c < n_chains; ++c) {
+                const ChainView* hv = nullptr;
+                ruleset_chain_view(chains[c], &hv);
+                if (!hv->has_index)
+                    return fail(FW_E_NOINDEX, "chain %u has no learned index (mode LEARNED)", c);
+            }
         }
-    }
-    fw_server* sv = new (std::nothrow) fw_server();
-    if (!sv) return fail(FW_E_NOMEM, "host allocation failed");
-    sv->chains.assign(chains, chains + n_chains);
-    sv->o = o;
-    sv->arena = std::make_unique<Arena>(size_t(o.mem_budget));
-    sv->slots.resize(o.slots);
-    hipError_t e = hipGetDevice(&sv->device);
-    if (e == hipSuccess && o.ingest == 0)
-        e = hipMalloc(reinterpret_cast<void**>(&sv->d_arena), o.mem_budget);
-    if (e == hipSuccess && o.ingest == 0)
-        e = hipHostMalloc(reinterpret_cast<void**>(&sv->h_arena), o.mem_budget,
-                          hipHostMallocDefault);
-    for (auto& sl : sv->slots) {
-        if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipMalloc(&sl.d_desc, kMultiScratchBytes);
-        if (e == hipSuccess) e = hipHostMalloc(&sl.h_desc, kMultiScratchBytes, hipHostMallocDefault);
-    }
-    if (e != hipSuccess) {
-        destroy_resources(sv);
-        delete sv;
-        return hip_fail(e, "creating the server");
-    }
-    for (uint32_t k = 0; k < o.slots; ++k) sv->slots[k].thread = std::thread(slot_main, sv, k);
-    *out = sv;
-    return FW_OK;
+        // owned here until every resource and worker is in place; a failure on
+        // the way (a HIP error, or an exception guarded() turns into a status)
+        // frees what was made
+        std::unique_ptr<fw_server> own(new fw_server());
+        fw_server* sv = own.get();
+        sv->chains.assign(chains, chains + n_chains);
+        sv->o = o;
+        sv->arena = std::make_unique<Arena>(size_t(o.mem_budget));
+        sv->slots.resize(o.slots);
+        struct Cleanup {   // resources made so far, unless released
+            fw_server* sv;
+            ~Cleanup() {
+                if (sv) destroy_resources(sv);
+            }
+        } cleanup{sv};
+        hipError_t e = hipGetDevice(&sv->device);
+        if (e == hipSuccess && o.ingest == 0)
+            e = hipMalloc(reinterpret_cast<void**>(&sv->d_arena), o.mem_budget);
+        if (e == hipSuccess && o.ingest == 0)
+            e = hipHostMalloc(reinterpret_cast<void**>(&sv->h_arena), o.mem_budget,
+                              hipHostMallocDefault);
+        for (auto& sl : sv->slots) {
+            if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+            if (e == hipSuccess) e = hipMalloc(&sl.d_desc, kMultiScratchBytes);
+            if (e == hipSuccess)
+                e = hipHostMalloc(&sl.h_desc, kMultiScratchBytes, hipHostMallocDefault);
+        }
+        if (e != hipSuccess) return hip_fail(e, "creating the server");
+        try {
+            for (uint32_t k = 0; k < o.slots; ++k)
+                sv->slots[k].thread = std::thread(slot_main, sv, k);
+        } catch (...) {   // stop and join the workers already started
+            {
+                std::lock_guard<std::mutex> lk(sv->mu);
+                sv->stop = true;
+                sv->cv_work.notify_all();
+            }
+            for (auto& sl : sv->slots)
+                if (sl.thread.joinable()) sl.thread.join();
+            throw;
+        }
+        cleanup.sv = nullptr;
+        *out = own.release();
+        return FW_OK;
+    });
 }
 
 fw_status fw_server_submit(fw_server* sv, uint32_t chain, const fw_host_packets* pk, size_t n,
                            int32_t* out_rule_idx, uint8_t* out_action, uint64_t* ticket) {
-    if (!sv || !ticket) return fail(FW_E_INVAL, "NULL server or ticket");
-    if (chain >= sv->chains.size()) return fail(FW_E_INVAL, "chain %u out of range", chain);
-    if (n > 0 && (!pk || !pk->src_ip || !pk->dst_ip || !pk->src_port || !pk->dst_port ||
-                  !pk->proto || !out_rule_idx || !out_action))
-        return fail(FW_E_INVAL, "NULL buffer");
-    if (n > 0 && sv->o.ingest == 1 &&
-        !(aligned16(pk->src_ip) && aligned16(pk->dst_ip) && aligned16(pk->src_port) &&
-          aligned16(pk->dst_port) && aligned16(pk->proto) && aligned16(out_rule_idx) &&
-          aligned16(out_action)))
-        return fail(FW_E_ALIGN, "mapped ingest needs 16-byte aligned buffers");
-    const size_t bytes = request_bytes(n);
-    if (bytes > sv->o.mem_budget)
-        return fail(FW_E_NOMEM, "request of %zu packets needs %zu bytes, budget %llu", n, bytes,
-                    (unsigned long long)sv->o.mem_budget);
-    auto r = std::make_shared<Request>();
-    r->chain = chain;
-    if (pk) r->pk = *pk;
-    r->n = n;
-    r->out_idx = out_rule_idx;
-    r->out_act = out_action;
-    r->times.submit = now_s();
-    std::lock_guard<std::mutex> lk(sv->mu);
-    if (sv->stop) return fail(FW_E_INVAL, "server is stopping");
-    r->ticket = sv->next_ticket++;
-    *ticket = r->ticket;
-    sv->reqs[r->ticket] = r;
-    if (n == 0) {
-        r->times.admit = r->times.done = r->times.submit;
-        r->done = true;
+    return guarded([&]() -> fw_status {
+        if (!sv || !ticket) return fail(FW_E_INVAL, "NULL server or ticket");
+        if (chain >= sv->chains.size()) return fail(FW_E_INVAL, "chain %u out of range", chain);
+        if (n > 0 && (!pk || !pk->src_ip || !pk->dst_ip || !pk->src_port || !pk->dst_port ||
+                      !pk->proto || !out_rule_idx || !out_action))
+            return fail(FW_E_INVAL, "NULL buffer");
+        if (n > 0 && sv->o.ingest == 1 &&
+            !(aligned16(pk->src_ip) && aligned16(pk->dst_ip) && aligned16(pk->src_port) &&
+              aligned16(pk->dst_port) && aligned16(pk->proto) && aligned16(out_rule_idx) &&
+              aligned16(out_action)))
+            return fail(FW_E_ALIGN, "mapped ingest needs 16-byte aligned buffers");
+        const size_t bytes = request_bytes(n);
+        if (bytes > sv->o.mem_budget)
+            return fail(FW_E_NOMEM, "request of %zu packets needs %zu bytes, budget %llu", n, bytes,
+                        (unsigned long long)sv->o.mem_budget);
+        auto r = std::make_shared<Request>();
+        r->chain = chain;
+        if (pk) r->pk = *pk;
+        r->n = n;
+        r->out_idx = out_rule_idx;
+        r->out_act = out_action;
+        r->times.submit = now_s();
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if (sv->stop) return fail(FW_E_INVAL, "server is stopping");
+        r->ticket = sv->next_ticket++;
+        *ticket = r->ticket;
+        sv->reqs[r->ticket] = r;
+        if (n == 0) {
+            r->times.admit = r->times.done = r->times.submit;
+            r->done = true;
+            return FW_OK;
+        }
+        sv->queue.push_back(r);
+        sv->cv_work.notify_one();
         return FW_OK;
-    }
-    sv->queue.push_back(r);
-    sv->cv_work.notify_one();
-    return FW_OK;
+    });
 }
 
 fw_status fw_server_wait(fw_server* sv, uint64_t ticket, fw_request_times* times) {
-    if (!sv) return fail(FW_E_INVAL, "NULL server");
-    std::unique_lock<std::mutex> lk(sv->mu);
-    auto it = sv->reqs.find(ticket);
-    if (it == sv->reqs.end()) return fail(FW_E_INVAL, "unknown ticket %llu", (unsigned long long)ticket);
-    auto r = it->second;
-    sv->cv_done.wait(lk, [&] { return r->done; });
-    sv->reqs.erase(ticket);
-    lk.unlock();
-    if (times) *times = r->times;
-    if (r->status != FW_OK) g_last_error = r->error;
-    return r->status;
+    return guarded([&]() -> fw_status {
+        if (!sv) return fail(FW_E_INVAL, "NULL server");
+        std::unique_lock<std::mutex> lk(sv->mu);
+        auto it = sv->reqs.find(ticket);
+        if (it == sv->reqs.end())
+            return fail(FW_E_INVAL, "unknown ticket %llu", (unsigned long long)ticket);
+        auto r = it->second;
+        sv->cv_done.wait(lk, [&] { return r->done; });
+        sv->reqs.erase(ticket);
+        lk.unlock();
+        if (times) *times = r->times;
+        if (r->status != FW_OK) g_last_error = r->error;
+        return r->status;
+    });
 }
 
 fw_status fw_server_replay(fw_server* sv, uint32_t n_req, const double* arrival_s,
                            const uint32_t* chain, const size_t* offset, const size_t* n,
                            const fw_host_packets* pool, int32_t* out_idx, uint8_t* out_action,
                            fw_request_times* times) {
-    if (!sv) return fail(FW_E_INVAL, "NULL server");
-    if (n_req == 0) return FW_OK;
-    if (!arrival_s || !chain || !offset || !n || !pool || !out_idx || !out_action)
-        return fail(FW_E_INVAL, "NULL argument");
-    for (uint32_t k = 1; k < n_req; ++k)
-        if (arrival_s[k] < arrival_s[k - 1]) return fail(FW_E_INVAL, "arrivals must not decrease");
-    std::vector<uint64_t> tickets(n_req, 0);
-    const double t0 = now_s();
-    fw_status st = FW_OK;
-    uint32_t submitted = 0;
-    for (uint32_t k = 0; k < n_req; ++k) {
-        const double due = t0 + arrival_s[k];
-        while (now_s() < due) {
+    return guarded([&]() -> fw_status {
+        if (!sv) return fail(FW_E_INVAL, "NULL server");
+        if (n_req == 0) return FW_OK;
+        if (!arrival_s || !chain || !offset || !n || !pool || !out_idx || !out_action)
+            return fail(FW_E_INVAL, "NULL argument");
+        for (uint32_t k = 1; k < n_req; ++k)
+            if (arrival_s[k] < arrival_s[k - 1])
+                return fail(FW_E_INVAL, "arrivals must not decrease");
+        std::vector<uint64_t> tickets(n_req, 0);
+        const double t0 = now_s();
+        fw_status st = FW_OK;
+        uint32_t submitted = 0;
+        for (uint32_t k = 0; k < n_req; ++k) {
+            // sleep to within 200 us of the arrival, then spin for an exact submit time
+            const double due = t0 + arrival_s[k], early = due - 2e-4;
+            const double wait = early - now_s();
+            if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(wait));
+            while (now_s() < due) {
+            }
+            const size_t o = offset[k];
+            const fw_host_packets pk{pool->src_ip + o, pool->dst_ip + o, pool->src_port + o,
+                                     pool->dst_port + o, pool->proto + o};
+            st = fw_server_submit(sv, chain[k], &pk, n[k], out_idx + o, out_action + o,
+                                  &tickets[k]);
+            if (st != FW_OK) break;
+            ++submitted;
         }
-        const size_t o = offset[k];
-        const fw_host_packets pk{pool->src_ip + o, pool->dst_ip + o, pool->src_port + o,
-                                 pool->dst_port + o, pool->proto + o};
-        st = fw_server_submit(sv, chain[k], &pk, n[k], out_idx + o, out_action + o, &tickets[k]);
-        if (st != FW_OK) break;
-        ++submitted;
-    }
-    const std::string submit_error = st != FW_OK ? g_last_error : std::string();
-    fw_status first_err = st;
-    for (uint32_t k = 0; k < submitted; ++k) {
-        fw_request_times t{};
-        const fw_status w = fw_server_wait(sv, tickets[k], &t);
-        if (w != FW_OK && first_err == FW_OK) first_err = w;
-        t.submit = t0 + arrival_s[k];
-        if (times) times[k] = t;
-    }
-    if (st != FW_OK) g_last_error = submit_error;
-    return first_err;
+        const std::string submit_error = st != FW_OK ? g_last_error : std::string();
+        fw_status first_err = st;
+        for (uint32_t k = 0; k < submitted; ++k) {
+            fw_request_times t{};
+            const fw_status w = fw_server_wait(sv, tickets[k], &t);
+            if (w != FW_OK && first_err == FW_OK) first_err = w;
+            t.submit = t0 + arrival_s[k];
+            if (times) times[k] = t;
+        }
+        if (st != FW_OK) g_last_error = submit_error;
+        return first_err;
+    });
 }
 
 fw_status fw_server_destroy(fw_server* sv) {
-    if (!sv) return FW_OK;
-    {
-        std::lock_guard<std::mutex> lk(sv->mu);
-        sv->stop = true;
-        sv->cv_work.notify_all();
-    }
-    for (auto& sl : sv->slots)
-        if (sl.thread.joinable()) sl.thread.join();
-    hipError_t e = hipSuccess;
-    for (auto& sl : sv->slots) {
-        const hipError_t e2 = hipStreamSynchronize(sl.stream);
-        if (e == hipSuccess) e = e2;
-    }
-    destroy_resources(sv);
-    delete sv;
-    if (e != hipSuccess) return hip_fail(e, "destroying the server");
-    return FW_OK;
+    return guarded([&]() -> fw_status {
+        if (!sv) return FW_OK;
+        {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            sv->stop = true;
+            sv->cv_work.notify_all();
+        }
+        for (auto& sl : sv->slots)
+            if (sl.thread.joinable()) sl.thread.join();
+        hipError_t e = hipSuccess;
+        for (auto& sl : sv->slots) {
+            const hipError_t e2 = hipStreamSynchronize(sl.stream);
+            if (e == hipSuccess) e = e2;
+        }
+        destroy_resources(sv);
+        delete sv;
+        if (e != hipSuccess) return hip_fail(e, "destroying the server");
+        return FW_OK;
+    });
 }
 
 }  // extern "C"

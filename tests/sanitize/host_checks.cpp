@@ -1,17 +1,37 @@
 // Host-only parts of the library under the address and undefined-behaviour
 // sanitizers: the arena allocator of the serving runtime, the candidate lists
-// and lookup tables of the learned index, and the grouping of a rule list
-// into a scan plan.  Each is driven with seeded random inputs and edge cases
+// and lookup tables of the learned index, the grouping of a rule list into a
+// scan plan, and the guard that keeps C++ exceptions from crossing the C
+// interface.  Each is driven with seeded random inputs and edge cases
 // and checked against a brute-force definition written here.  Exit status 0
 // when every check passes.
 #include <algorithm>
+#include <cstdarg>
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <system_error>
 #include <vector>
 
 #include "../../paper_1312_4188_amd/csrc/arena.h"
+#include "../../paper_1312_4188_amd/csrc/guard.h"
 #include "../../paper_1312_4188_amd/csrc/lists.h"
+
+// The library's fail() (which records the message for fw_last_error) lives
+// with the HIP code; guarded() only needs its contract: record, return st.
+static std::string g_last_message;
+fw_status fw::fail(fw_status st, const char* fmt, ...) {
+    char buf[256];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_message = buf;
+    return st;
+}
 
 using fw::RuleRec;
 
@@ -242,10 +262,36 @@ void check_arena(Rng& g) {
     CHECK(a.largest() == size && a.blocks().size() == 1, "arena: not whole after releasing all");
 }
 
+// guarded(): a body's own status passes through; any exception out of it
+// becomes FW_E_NOMEM with a message, and nothing escapes.
+void check_guard() {
+    CHECK(fw::guarded([] { return FW_OK; }) == FW_OK, "guard: FW_OK not passed through");
+    CHECK(fw::guarded([] { return FW_E_ALIGN; }) == FW_E_ALIGN, "guard: status not passed");
+    g_last_message.clear();
+    CHECK(fw::guarded([]() -> fw_status { throw std::bad_alloc(); }) == FW_E_NOMEM,
+          "guard: bad_alloc");
+    CHECK(g_last_message.find("host resources exhausted") != std::string::npos,
+          "guard: no message for bad_alloc");
+    CHECK(fw::guarded([]() -> fw_status {
+              throw std::system_error(std::make_error_code(std::errc::resource_unavailable_try_again));
+          }) == FW_E_NOMEM,
+          "guard: system_error");
+    CHECK(fw::guarded([]() -> fw_status { throw std::length_error("vector"); }) == FW_E_NOMEM,
+          "guard: length_error");
+    CHECK(fw::guarded([]() -> fw_status { throw 42; }) == FW_E_NOMEM, "guard: non-std exception");
+    CHECK(fw::guarded([]() -> fw_status {
+              std::vector<int> v(1000, 7);
+              if (v[999] == 7) throw std::runtime_error("after allocating");
+              return FW_OK;
+          }) == FW_E_NOMEM,
+          "guard: exception after allocations (their memory must be freed: ASan leak check)");
+}
+
 }  // namespace
 
 int main() {
     Rng g{12345};
+    check_guard();
     check_arena(g);
     struct Case {
         uint32_t R;
