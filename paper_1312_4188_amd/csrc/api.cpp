@@ -172,15 +172,16 @@ fw_status fw_load_ruleset(const fw_rule* rules, uint32_t n_rules, uint8_t defaul
                 return fail(FW_E_INVAL, "rule %u: port range with lo > hi", i);
             if (r.action > 1) return fail(FW_E_INVAL, "rule %u: action must be 0 or 1", i);
         }
-        fw_ruleset* rs = new (std::nothrow) fw_ruleset();
-        if (!rs) return fail(FW_E_NOMEM, "host allocation failed");
-        try {
-            rs->source.assign(rules, rules + n_rules);
-            rs->h_rules.resize(n_rules);
-        } catch (...) {
+        fw_ruleset* rs = new fw_ruleset();
+        ScopeExit undo([rs] {   // a failed or throwing step below frees what was made
+            if (rs->d_view) (void)hipFree(rs->d_view);
+            if (rs->d_rules) (void)hipFree(rs->d_rules);
+            if (rs->d_pairs) (void)hipFree(rs->d_pairs);
+            free_plan(&rs->plan);
             delete rs;
-            return fail(FW_E_NOMEM, "host allocation failed");
-        }
+        });
+        rs->source.assign(rules, rules + n_rules);
+        rs->h_rules.resize(n_rules);
         for (uint32_t i = 0; i < n_rules; ++i) rs->h_rules[i] = compile_rule(rules[i], i);
         rs->n_rules = n_rules;
         rs->default_action = default_action;
@@ -208,14 +209,8 @@ fw_status fw_load_ruleset(const fw_rule* rules, uint32_t n_rules, uint8_t defaul
             e = hipMalloc(&rs->d_view, sizeof(ChainView));
         }
         if (e == hipSuccess) e = upload_view(rs);
-        if (e != hipSuccess) {
-            if (rs->d_view) (void)hipFree(rs->d_view);
-            if (rs->d_rules) (void)hipFree(rs->d_rules);
-            if (rs->d_pairs) (void)hipFree(rs->d_pairs);
-            free_plan(&rs->plan);
-            delete rs;
-            return hip_fail(e, "uploading the ruleset");
-        }
+        if (e != hipSuccess) return hip_fail(e, "uploading the ruleset");
+        undo.dismiss();
         *out = rs;
         return FW_OK;
     });

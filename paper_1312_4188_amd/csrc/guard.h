@@ -6,6 +6,7 @@
 
 #include <exception>
 #include <new>
+#include <utility>
 
 #include "../../include/fw.h"
 
@@ -27,5 +28,23 @@ fw_status guarded(F&& body) noexcept {
         return FW_E_NOMEM;
     }
 }
+
+// Undoes a partly built object when its scope ends by an early return or an
+// exception, unless dismissed once the object is complete.
+template <class F>
+class ScopeExit {
+   public:
+    explicit ScopeExit(F f) : f_(std::move(f)) {}
+    ScopeExit(const ScopeExit&) = delete;
+    ScopeExit& operator=(const ScopeExit&) = delete;
+    ~ScopeExit() {
+        if (on_) f_();
+    }
+    void dismiss() { on_ = false; }
+
+   private:
+    F f_;
+    bool on_ = true;
+};
 
 }  // namespace fw

@@ -447,8 +447,9 @@ fw_status build_index(const fw_rule* rules, const RuleRec* recs, uint32_t n_rule
     hipStream_t s = static_cast<hipStream_t>(o.stream);
     const auto t_start = std::chrono::steady_clock::now();
 
-    LearnedIndex* ix = new (std::nothrow) LearnedIndex();
-    if (!ix) return fail(FW_E_NOMEM, "host allocation failed");
+    LearnedIndex* ix = new LearnedIndex();
+    // until the index is complete, any return or exception frees what it holds
+    ScopeExit drop_ix([&] { destroy_index(ix); });
     std::vector<RuleRec> L, S, G;
     fw_status st = FW_OK;
     try {
@@ -478,15 +479,10 @@ fw_status build_index(const fw_rule* rules, const RuleRec* recs, uint32_t n_rule
     } catch (const std::bad_alloc&) {
         st = fail(FW_E_NOMEM, "host allocation failed while building candidate lists");
     }
-    if (st != FW_OK) {
-        delete ix;
-        return st;
-    }
-    if (ix->nL * sizeof(RuleRec) > kMaxListBytes || ix->nS * sizeof(RuleRec) > kMaxListBytes) {
-        delete ix;
+    if (st != FW_OK) return st;
+    if (ix->nL * sizeof(RuleRec) > kMaxListBytes || ix->nS * sizeof(RuleRec) > kMaxListBytes)
         return fail(FW_E_NOMEM, "candidate lists exceed %llu bytes",
                     (unsigned long long)kMaxListBytes);
-    }
     const uint32_t M = ix->M, E = o.experts, H = o.hidden, P = 3 * H + 1;
     ix->E = E;
     ix->H = H;
@@ -500,19 +496,13 @@ fw_status build_index(const fw_rule* rules, const RuleRec* recs, uint32_t n_rule
                           sizeof(PortTable) + (uint64_t(1) << 12) * 2 +
                           LdsLayout(E, M, ix->Ms, ix->pt_shape[3], false).bytes +
                           LdsLayout(E, M, ix->Ms, ix->pt_shape[3], true).bytes;
-    if (o.mem_budget && keep > o.mem_budget) {
-        delete ix;
+    if (o.mem_budget && keep > o.mem_budget)
         return fail(FW_E_NOMEM, "learned index needs %llu bytes, budget is %llu",
                     (unsigned long long)keep, (unsigned long long)o.mem_budget);
-    }
 
     hipError_t e = hipSuccess;
     uint64_t bytes = 0;
-    auto bail = [&](hipError_t err, const char* what) {
-        free_index_memory(ix);
-        delete ix;
-        return hip_fail(err, what);
-    };
+    auto bail = [&](hipError_t err, const char* what) { return hip_fail(err, what); };
     if ((e = dalloc(&ix->d_B, M, &bytes)) != hipSuccess ||
         (e = dalloc(&ix->d_off, size_t(M) + 1, &bytes)) != hipSuccess ||
         (e = dalloc(&ix->d_L, ix->nL, &bytes)) != hipSuccess ||
@@ -560,24 +550,22 @@ fw_status build_index(const fw_rule* rules, const RuleRec* recs, uint32_t n_rule
     uint32_t* d_route = nullptr;
     uint32_t* d_err = nullptr;
     uint64_t scratch = 0;
-    if ((e = dalloc(&d_keys, N, &scratch)) != hipSuccess ||
-        (e = dalloc(&d_pos, N, &scratch)) != hipSuccess ||
-        (e = dalloc(&d_route, N, &scratch)) != hipSuccess ||
-        (e = dalloc(&d_err, E, &scratch)) != hipSuccess) {
-        for (void* p : {static_cast<void*>(d_keys), static_cast<void*>(d_pos),
-                        static_cast<void*>(d_route), static_cast<void*>(d_err)})
-            if (p) (void)hipFree(p);
-        return bail(e, "allocating training buffers");
-    }
     auto free_scratch = [&]() {
         for (void* p : {static_cast<void*>(d_keys), static_cast<void*>(d_pos),
                         static_cast<void*>(d_route), static_cast<void*>(d_err)})
             if (p) (void)hipFree(p);
+        d_keys = nullptr;
+        d_pos = nullptr;
+        d_route = nullptr;
+        d_err = nullptr;
     };
-    auto fail_train = [&](hipError_t err, const char* what) {
-        free_scratch();
-        return bail(err, what);
-    };
+    ScopeExit drop_scratch([&] { free_scratch(); });   // freed early below on success
+    if ((e = dalloc(&d_keys, N, &scratch)) != hipSuccess ||
+        (e = dalloc(&d_pos, N, &scratch)) != hipSuccess ||
+        (e = dalloc(&d_route, N, &scratch)) != hipSuccess ||
+        (e = dalloc(&d_err, E, &scratch)) != hipSuccess)
+        return bail(e, "allocating training buffers");
+    auto fail_train = bail;
     if ((e = upload(d_keys, keys, s)) != hipSuccess || (e = upload(d_pos, pos, s)) != hipSuccess)
         return fail_train(e, "uploading training keys");
 
@@ -589,10 +577,9 @@ fw_status build_index(const fw_rule* rules, const RuleRec* recs, uint32_t n_rule
     init_network(w1.data(), H, rng);
     {
         Trainer tr;
-        if ((e = tr.init(1, H, N, o.use_mfma != 0, s)) != hipSuccess) {
-            tr.release();
+        ScopeExit tr_release([&] { tr.release(); });
+        if ((e = tr.init(1, H, N, o.use_mfma != 0, s)) != hipSuccess)
             return fail_train(e, "allocating stage-1 training");
-        }
         std::vector<float> hu(N), ht(N);
         std::vector<uint32_t> hex(N, 0);
         for (size_t k = 0; k < N; ++k) {
@@ -662,10 +649,9 @@ fw_status build_index(const fw_rule* rules, const RuleRec* recs, uint32_t n_rule
     for (uint32_t ex = 0; ex < E; ++ex) init_network(w2.data() + size_t(ex) * P, H, rng);
     {
         Trainer tr;
-        if ((e = tr.init(E, H, N, o.use_mfma != 0, s)) != hipSuccess) {
-            tr.release();
+        ScopeExit tr_release([&] { tr.release(); });
+        if ((e = tr.init(E, H, N, o.use_mfma != 0, s)) != hipSuccess)
             return fail_train(e, "allocating stage-2 training");
-        }
         std::vector<float> hu(N), ht(N);
         std::vector<uint32_t> hex(N);
         for (size_t k = 0; k < N; ++k) {
@@ -759,6 +745,7 @@ fw_status build_index(const fw_rule* rules, const RuleRec* recs, uint32_t n_rule
         stats->weights_rounded = ix->weights_rounded;
         stats->device_bytes = ix->device_bytes;
     }
+    drop_ix.dismiss();
     *out = ix;
     return FW_OK;
 }
@@ -875,6 +862,7 @@ fw_status fw_rmi_gradients(uint32_t E, uint32_t H, const float* params, size_t n
         std::vector<float> hp(params, params + size_t(E) * P);
         hipStream_t s = nullptr;
         Trainer tr;
+        ScopeExit tr_release([&] { tr.release(); });
         hipError_t e = tr.init(E, H, n, use_mfma != 0, s);
         if (e == hipSuccess) e = tr.load(hu, ht, hex, hp, s);
         if (e == hipSuccess) e = tr.gradients(s);

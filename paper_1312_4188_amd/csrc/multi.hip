@@ -368,6 +368,10 @@ hipError_t multi_launch(const fw_chain_batch* b, uint32_t n_chains, MultiConfig 
     hipError_t e = hipSuccess;
     if (!scratch_mem) e = hipMallocAsync(&mem, kMultiCounterBytes + sizeof(ChainDesc) * nc, s);
     if (e != hipSuccess) return e;
+    // released on the stream below; this frees it when a step in between throws
+    // (the occupancy cache allocates)
+    ScopeExit release_on_throw([&] { (void)hipFreeAsync(mem, s); });
+    if (scratch_mem) release_on_throw.dismiss();
     uint32_t* counter = static_cast<uint32_t*>(mem);
     ChainDesc* table = reinterpret_cast<ChainDesc*>(static_cast<char*>(mem) + kMultiCounterBytes);
     if (host_staging) {
@@ -442,6 +446,7 @@ hipError_t multi_launch(const fw_chain_batch* b, uint32_t n_chains, MultiConfig 
 #undef FW_MULTI_AUTO
 #undef FW_MULTI
     if (scratch_mem) return e;
+    release_on_throw.dismiss();
     const hipError_t e2 = hipFreeAsync(mem, s);
     return e != hipSuccess ? e : e2;
 }

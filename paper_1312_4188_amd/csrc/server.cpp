@@ -384,12 +384,7 @@ fw_status fw_server_create(fw_ruleset* const* chains, uint32_t n_chains, const f
         sv->o = o;
         sv->arena = std::make_unique<Arena>(size_t(o.mem_budget));
         sv->slots.resize(o.slots);
-        struct Cleanup {   // resources made so far, unless released
-            fw_server* sv;
-            ~Cleanup() {
-                if (sv) destroy_resources(sv);
-            }
-        } cleanup{sv};
+        ScopeExit cleanup([sv] { destroy_resources(sv); });   // resources made so far
         hipError_t e = hipGetDevice(&sv->device);
         if (e == hipSuccess && o.ingest == 0)
             e = hipMalloc(reinterpret_cast<void**>(&sv->d_arena), o.mem_budget);
@@ -417,7 +412,7 @@ fw_status fw_server_create(fw_ruleset* const* chains, uint32_t n_chains, const f
                 if (sl.thread.joinable()) sl.thread.join();
             throw;
         }
-        cleanup.sv = nullptr;
+        cleanup.dismiss();
         *out = own.release();
         return FW_OK;
     });
