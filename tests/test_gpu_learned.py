@@ -21,6 +21,56 @@ pytestmark = pytest.mark.gpu
 FAST = dict(epochs1=300, epochs2=600)
 
 
+def _check_half_rounding(rs, st, hidden=32):
+    """The lookup stores each expert's w1 and w2 as IEEE half after scaling hidden unit
+    (w1, b1, w2) to (w1 2^-k, b1 2^-k, w2 2^k) with 2^k > |w1| + |b1| (so ReLU becomes a
+    clamp to [0, 1]); among the first 24 such k it takes the smallest that half rounds the
+    fewest of (w2, and w1 when w2 is not zero).  Recomputed here from the exported bf16
+    weights of the experts: the index's count must agree, and every weight half rounds must
+    lie below half's normal range (2^-14), so none overflows and each moves by at most
+    2^-25."""
+    H, P = hidden, 3 * hidden + 1
+    nets = rs.export(5).astype(np.float32).reshape(-1, P)[1:]   # the experts (stage 2)
+
+    def exact(x):
+        with np.errstate(over="ignore"):
+            h = np.float16(x)
+        return bool(np.isfinite(h)) and np.float32(h) == np.float32(x)
+
+    count, worst = 0, 0.0
+    for net in nets:
+        for i in range(H):
+            a, b, c = (np.float32(net[i]), np.float32(net[H + i]), np.float32(net[2 * H + i]))
+            m = np.float32(abs(a) + abs(b))
+            if not (m > 0) or not np.isfinite(m):
+                continue
+            k0 = int(np.frexp(m)[1])
+            best = None
+            for k in range(k0, k0 + 24):
+                a2, b2, c2 = np.ldexp(a, -k), np.ldexp(b, -k), np.ldexp(c, k)
+                if not (np.ldexp(a2, k) == a and np.ldexp(b2, k) == b and np.ldexp(c2, -k) == c
+                        and np.isfinite(c2)
+                        and all(x == 0 or abs(x) >= np.finfo(np.float32).tiny
+                                for x in (a2, b2, c2))):
+                    continue
+                bad = [c2] if not exact(c2) else []
+                if c2 != 0 and not exact(a2):
+                    bad.append(a2)
+                if best is None or len(bad) < len(best):
+                    best = bad
+                if not bad:
+                    break
+            if best is None:   # no scaling round-trips: the unit is stored unscaled
+                best = [c] if not exact(c) else []
+                if c != 0 and not exact(a):
+                    best.append(a)
+            for x in best:
+                count += 1
+                worst = max(worst, abs(float(x)))
+    assert st["weights_rounded"] == count, (st["weights_rounded"], count)
+    assert worst < 2.0 ** -14, worst
+
+
 def _learned_np(rules, pk, build_kw=None, **kw):
     import torch
     fw = fwmod()
@@ -106,8 +156,7 @@ def test_learned_10000_rules_whole_batch(seed):
         say(f"learned 10000x16M seed={seed} build")
         st = rs.build_learned_index()
         say(f"  stats {st}")
-        # every stage-2 weight held exactly in the lookup's half storage
-        assert st["weights_rounded"] == 0
+        _check_half_rounding(rs, st)
         for lookup in (0, 1):
             idx, act, miss = rs.classify(dp, mode="learned", lookup=lookup, count_misses=True)
             torch.cuda.synchronize()
@@ -141,7 +190,7 @@ def test_learned_50000_rule_chain(seed, all_dst):
         say(f"learned 50000-rule chain seed={seed} all_dst={all_dst} build")
         st = rs.build_learned_index(seed=seed)
         say(f"  stats {st}")
-        assert st["weights_rounded"] == 0
+        _check_half_rounding(rs, st)
         if all_dst:
             assert st["n_boundaries"] * 4 > 80 * 1024
         for kw in (dict(), dict(packets_per_lane=1), dict(packets_per_lane=4),
