@@ -35,7 +35,7 @@ VALU_INT32_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # Algorithmic cost of one rule check: the destination test every check makes
 # (one subtract, one unsigned compare); deeper field tests are not counted.
 OPS_PER_CHECK = 2
-# The survey's pricing of a learned-path candidate check: every field test, the select of the
+# A fuller pricing of a learned-path candidate check: every field test, the select of the
 # answer and the list step, about 7 lane-ops; reported beside the lower bound above.
 OPS_PER_CHECK_FULL = 7
 BYTES_PER_PACKET = 13 + 5          # 5-tuple in (4+4+2+2+1), index + action out (4+1)
@@ -425,11 +425,11 @@ def multichain_leg(seed: int, steps: int, log_fn):
 
     call = fw.MultiBatch(items)        # marshalled once: the timed calls are the library's
 
-    def phase(name, configs):
+    def phase(name, variants):
         best, tuned_ms = fw.autotune_multi(items)
         log_fn(f"  multichain {name}: autotuned {best} ({tuned_ms:.3f} ms)")
         res = {"tuned": best, "autotune_best_ms": tuned_ms, "configs": {}}
-        for cname, kw in configs.items():
+        for cname, kw in variants.items():
             ms, _ = time_steps(lambda: call.run(stream=stream, **kw), steps, 2, stream)
             res["configs"][cname] = {"ms": ms, "mpps": total / ms / 1e3}
             if name == "scan":
@@ -450,13 +450,13 @@ def multichain_leg(seed: int, steps: int, log_fn):
         log_fn(f"  multichain {name}: every chain bit-exact vs the oracle: {res['bit_exact']}")
         return res
 
-    configs = {"tuned": {}}
+    variants = {"tuned": {}}
     for K in (1, 2, 4):
-        configs[f"plan_k{K}"] = dict(packets_per_lane=K, placement=4)
-        configs[f"scalar_k{K}"] = dict(packets_per_lane=K, placement=1)
-        configs[f"vector_k{K}"] = dict(packets_per_lane=K, placement=3)
-        configs[f"lds1024_k{K}"] = dict(packets_per_lane=K, placement=2, rule_tile=1024)
-    out["scan"] = phase("scan", configs)
+        variants[f"plan_k{K}"] = dict(packets_per_lane=K, placement=4)
+        variants[f"scalar_k{K}"] = dict(packets_per_lane=K, placement=1)
+        variants[f"vector_k{K}"] = dict(packets_per_lane=K, placement=3)
+        variants[f"lds1024_k{K}"] = dict(packets_per_lane=K, placement=2, rule_tile=1024)
+    out["scan"] = phase("scan", variants)
 
     def per_chain():
         for rs, dp, oi, oa in items:
@@ -771,7 +771,7 @@ def main():
              "hbm_source": "rocprofv3 FETCH_SIZE + WRITE_SIZE" if tr is not None
                            else "algorithmic, 18 B per packet"}
         if "candidate_checks" in work:
-            # survey pricing of a candidate check: ~7 lane-ops (all field tests, select, step)
+            # the fuller pricing of a candidate check: ~7 lane-ops (all field tests, select, step)
             ops7 = work["lane_ops"] + (OPS_PER_CHECK_FULL - OPS_PER_CHECK) * work["candidate_checks"]
             r["frac_at_7_ops_per_check"] = ops7 / t / 1e12 / VALU_INT32_PEAK_TOPS
             # records gathered from the per-lane lists: served by L2 and LDS, not HBM
