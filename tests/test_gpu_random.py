@@ -57,3 +57,34 @@ def test_random_rulesets_every_path(seed):
             idx, act = rs.classify(dp, **kw)[:2]
             torch.cuda.synchronize()
             assert_same((idx.cpu().numpy(), act.cpu().numpy()), want, f"seed={seed} {kw}")
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_large_rulesets(seed):
+    """Larger seeded rulesets (1,000-30,000 rules, mostly skewed prefixes, some with every
+    destination specified so that tens of thousands of boundaries sit in global memory) and
+    batches of 100,000-1,000,000 packets: every learned variant, AUTO, packet split and the
+    hybrid against the oracle, and the index's half-storage rounding count."""
+    import torch
+    fw = fwmod()
+    rng = np.random.Generator(np.random.PCG64(77 + seed))
+    R = int(rng.integers(1000, 30000))
+    rules = gen.make_rules(R, 5000 + seed, skew=bool(rng.random() < 0.7))
+    if rng.random() < 0.3:
+        rules.dst_plen[rules.dst_plen == 0] = int(rng.choice([8, 16, 24]))
+    n = int(rng.integers(100_000, 1_000_000))
+    pk = gen.make_packets(rules, n, 6000 + seed)
+    want = oracle.classify(rules, pk, threads=16)
+    say(f"random large seed={seed} R={R} n={n}")
+    with fw.Ruleset(rules) as rs:
+        dp = fw.DevicePackets.from_host(pk)
+        st = rs.build_learned_index(seed=seed)
+        say(f"  |B|={st['n_boundaries']} err_mean={st['err_mean']:.1f}")
+        assert st["weights_rounded"] == 0
+        runs = [dict(mode="learned", packets_per_lane=k) for k in (1, 2, 4)]
+        runs += [dict(mode="learned", lookup=1), dict(mode="auto"), dict(mode="packet_split"),
+                 dict(mode="hybrid", partitions=16)]
+        for kw in runs:
+            idx, act = rs.classify(dp, **kw)[:2]
+            torch.cuda.synchronize()
+            assert_same((idx.cpu().numpy(), act.cpu().numpy()), want, f"seed={seed} {kw}")
