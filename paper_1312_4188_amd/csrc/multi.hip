@@ -18,6 +18,7 @@
 // placement grid on the caller's own batches and caches the fastest choice
 // per batch shape.
 #include <algorithm>
+#include <chrono>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -559,6 +560,14 @@ fw_status fw_autotune_multi(const fw_chain_batch* batches, uint32_t n_chains, vo
         placements[3].tile = 256;
         placements[4].placement = kPlaceLds;
         placements[4].tile = 1024;
+        // the GPU reaches its steady clocks only after some tens of milliseconds of
+        // sustained work: run the default configuration that long before timing any
+        const auto t0 = std::chrono::steady_clock::now();
+        while (e == hipSuccess &&
+               std::chrono::steady_clock::now() - t0 < std::chrono::milliseconds(30)) {
+            e = multi_launch(batches, n_chains, MultiConfig{}, s, nullptr, nullptr);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+        }
         for (int K : {1, 2, 4}) {
             for (MultiConfig c : placements) {
                 if (e != hipSuccess) break;
