@@ -707,6 +707,9 @@ def main():
              "auto_no_index": (rs_plain, dict(mode="auto"))}
     if args.modes:
         keep = args.modes.split(",")
+        unknown = [k for k in keep if k not in modes]
+        if unknown:
+            raise SystemExit(f"unknown mode(s) {', '.join(unknown)}; known: {', '.join(modes)}")
         modes = {k: modes[k] for k in keep}
     results = {}
     ref = None
