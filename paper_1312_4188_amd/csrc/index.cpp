@@ -529,6 +529,11 @@ fw_status build_index(const fw_rule* rules, const RuleRec* recs, uint32_t n_rule
         (e = make_plan(G.data(), uint32_t(G.size()), &ix->gplan)) != hipSuccess)
         return bail(e, "uploading the learned index");
     ix->device_bytes += ix->gplan.bytes;
+    // the lookup scans this plan without address tests (its rules leave both
+    // addresses unspecified, so it has port- and protocol-first groups only)
+    for (uint32_t g = 0; g < ix->gplan.plan.n_groups; ++g)
+        if (ix->gplan.plan.g[g].kind == kFirstDst || ix->gplan.plan.g[g].kind == kFirstSrc)
+            return bail(hipErrorInvalidValue, "an address-first group in the wildcard plan");
 
     // ---- training samples: both ends of every interval, target = its position
     std::vector<uint32_t> keys;

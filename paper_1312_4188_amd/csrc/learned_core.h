@@ -425,7 +425,7 @@ __device__ __forceinline__ void learned_tile(const LookupArgs& a, const IndexVie
         w.act[s] = lact[s];
     }
     if constexpr (PLAN)
-        w.scan_plan(a.G);
+        w.template scan_plan<false>(a.G);   // both addresses unspecified in every rule
     else
         w.seed_tail(a.G);
     w.store(out_idx, out_act, n);

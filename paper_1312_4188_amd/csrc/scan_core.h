@@ -174,19 +174,35 @@ struct WaveScan {
     // Remaining tests of a rule some live lane passed on its first field.  A
     // rule tested first on the ports has both addresses unspecified, one
     // tested first on the protocol has addresses and ports unspecified, so
-    // those tests are skipped.  With SEEDED, a lane takes the rule only if it
-    // beats the lane's current answer.  Matched lanes leave the live masks.
+    // those tests are skipped.  After an address, the other address is tested
+    // on its own first: about half the rules some lane passes on one address
+    // fail on the other in every lane, and leave without the port and protocol
+    // tests.  With SEEDED, a lane takes the rule only if it beats the lane's
+    // current answer.  Matched lanes leave the live masks.
     template <FirstField F, bool SEEDED>
     __device__ __forceinline__ void finish(const uint64_t (&c)[K], const RuleRec& q,
                                            uint32_t idx) {
         const uint32_t plo = proto_lo(q.proto), pw = proto_w(q.proto);
         uint64_t m[K];
+        if constexpr (F == FirstField::Dst || F == FirstField::Src) {
+            uint64_t some = 0;
+#pragma unroll
+            for (int s = 0; s < K; ++s) {
+                m[s] = c[s] & live[s];
+                if constexpr (F == FirstField::Src)
+                    m[s] &= ballot(in_range(dst[s], q.dst_lo, q.dst_w));
+                else
+                    m[s] &= ballot(in_range(src[s], q.src_lo, q.src_w));
+                some |= m[s];
+            }
+            if (some == 0) return;
+        } else {
+#pragma unroll
+            for (int s = 0; s < K; ++s) m[s] = c[s] & live[s];
+        }
         uint64_t any = 0;
 #pragma unroll
         for (int s = 0; s < K; ++s) {
-            m[s] = c[s] & live[s];
-            if constexpr (F == FirstField::Src) m[s] &= ballot(in_range(dst[s], q.dst_lo, q.dst_w));
-            if constexpr (F == FirstField::Dst) m[s] &= ballot(in_range(src[s], q.src_lo, q.src_w));
             if constexpr (F == FirstField::Dst || F == FirstField::Src)
                 m[s] &= ballot(ports_in(pp[s], q.port_lo, q.port_w));
             if constexpr (F != FirstField::Proto) m[s] &= ballot(in_range(pr[s], plo, pw));
@@ -353,6 +369,9 @@ struct WaveScan {
         }
     }
 
+    // ADDRESSES false: a plan of rules with both addresses unspecified (only
+    // port- and protocol-first groups), whose address groups need no code.
+    template <bool ADDRESSES = true>
     __device__ __forceinline__ void scan_plan(const ScanPlan& plan) {
         seed_tail(plan);
         for (uint32_t g = 0; g < plan.n_groups; ++g) {
@@ -360,10 +379,12 @@ struct WaveScan {
             enter_group(G.recs[0].idx);
             switch (G.kind) {
                 case kFirstDst:
-                    scan<FirstField::Dst, true, true>(G.pairs, G.recs, G.count, 0u);
+                    if constexpr (ADDRESSES)
+                        scan<FirstField::Dst, true, true>(G.pairs, G.recs, G.count, 0u);
                     break;
                 case kFirstSrc:
-                    scan<FirstField::Src, true, true>(G.pairs, G.recs, G.count, 0u);
+                    if constexpr (ADDRESSES)
+                        scan<FirstField::Src, true, true>(G.pairs, G.recs, G.count, 0u);
                     break;
                 case kFirstPorts:
                     scan<FirstField::Ports, true, true>(G.pairs, G.recs, G.count, 0u);
