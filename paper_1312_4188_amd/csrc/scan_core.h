@@ -255,9 +255,9 @@ struct WaveScan {
             for (uint32_t u = 0; u < kPairBlock; ++u) cur[u] = first[u];
             for (; r + kPairBlock <= count; r += kPairBlock) {
                 uint2 nxt[kPairBlock];
-#pragma unroll
-                for (uint32_t u = 0; u < kPairBlock; ++u) nxt[u] = first[r + kPairBlock + u];
                 if constexpr (K == 1 && BATCH) {
+#pragma unroll
+                    for (uint32_t u = 0; u < kPairBlock; ++u) nxt[u] = first[r + kPairBlock + u];
                     // the block's eight first tests at once (they do not depend
                     // on which lanes are live), then one branch; a block with a
                     // passing lane goes rule by rule in order, as step() does
@@ -279,8 +279,16 @@ struct WaveScan {
                         }
                     }
                 } else {
+                    // the next block's pairs are requested after this block's
+                    // first rule: the wait for a block's pairs (at the copy
+                    // below) then finds them loaded behind seven rules of work,
+                    // where a request at the top of the block would be waited
+                    // for with the current block's own
+                    step<F, OWN_INDEX, SEEDED>(cur[0], rules, r, base);
 #pragma unroll
-                    for (uint32_t u = 0; u < kPairBlock; ++u)
+                    for (uint32_t u = 0; u < kPairBlock; ++u) nxt[u] = first[r + kPairBlock + u];
+#pragma unroll
+                    for (uint32_t u = 1; u < kPairBlock; ++u)
                         step<F, OWN_INDEX, SEEDED>(cur[u], rules, r + u, base);
                 }
                 if (live_any == 0) return false;
