@@ -349,6 +349,84 @@ def test_every_first_test_kind(catch_all_at):
         assert_same(got, want, f"kinds {catch_all_at} {kw}")
 
 
+def _address_filter_case(seed: int):
+    """Rules built so that many lanes pass one address while every lane fails the next test,
+    with the matching rules only in the last third of the list (long scans through them):
+    destination-first rules whose source (a /8 no packet uses) fails, source-first rules whose
+    destination fails, rules passing both addresses but failing on ports or on protocol, and
+    rules that match packets of one destination /24 on one port and protocol."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n, R = 20_000, 600
+    src_nets = (0x0A010000 + (np.arange(8, dtype=np.uint32) << 8)).astype(np.uint32)
+    dst_nets = (0xAC100000 + (np.arange(8, dtype=np.uint32) << 8)).astype(np.uint32)
+    ports = np.array([53, 80, 443, 8080], dtype=np.uint16)
+    pk = gen.Packets(
+        src_ip=(src_nets[rng.integers(0, 8, n)] | rng.integers(0, 256, n).astype(np.uint32)),
+        dst_ip=(dst_nets[rng.integers(0, 8, n)] | rng.integers(0, 256, n).astype(np.uint32)),
+        sport=rng.integers(1024, 65536, n).astype(np.uint16),
+        dport=ports[rng.integers(0, 4, n)],
+        proto=np.array([6, 17], dtype=np.uint8)[rng.integers(0, 2, n)])
+    kind = rng.integers(0, 4, R)
+    kind[2 * R // 3:] = rng.integers(0, 5, R - 2 * R // 3)      # matching rules: the last third
+    z8 = np.zeros(R, np.uint8)
+    rules = gen.Ruleset(
+        src_ip=src_nets[rng.integers(0, 8, R)].copy(), src_plen=np.full(R, 16, np.uint8),
+        dst_ip=dst_nets[rng.integers(0, 8, R)].copy(), dst_plen=np.full(R, 24, np.uint8),
+        sport_lo=np.zeros(R, np.uint16), sport_hi=np.full(R, 65535, np.uint16),
+        dport_lo=np.zeros(R, np.uint16), dport_hi=np.full(R, 65535, np.uint16),
+        proto=z8.copy(), proto_any=np.ones(R, np.uint8),
+        action=rng.integers(0, 2, R).astype(np.uint8))
+    d = kind == 0                                   # destination /24 passes, source /8 fails
+    rules.src_ip[d] = 0xC0000000
+    rules.src_plen[d] = 8
+    s_ = kind == 1                                  # source /24 passes, destination /8 fails
+    rules.src_plen[s_] = 24
+    rules.dst_ip[s_] = 0xC0000000
+    rules.dst_plen[s_] = 8
+    p_ = kind == 2                                  # both addresses pass, ports fail
+    rules.dport_lo[p_] = 1
+    rules.dport_hi[p_] = 52
+    q_ = kind == 3                                  # addresses and ports pass, protocol fails
+    rules.proto_any[q_] = 0
+    rules.proto[q_] = 1
+    m_ = kind == 4                                  # matches a destination /24, port, protocol
+    rules.dport_lo[m_] = rules.dport_hi[m_] = ports[rng.integers(0, 4, int(m_.sum()))]
+    rules.proto_any[m_] = 0
+    rules.proto[m_] = 6
+    return rules, pk
+
+
+@pytest.mark.parametrize("seed", [5, 6])
+def test_second_field_rejections(seed):
+    """Every path against the oracle where a rule's first address passes in many lanes and a
+    later field fails in all of them (the rule is left after that field's test)."""
+    import torch
+    fw = fwmod()
+    rules, pk = _address_filter_case(seed)
+    want = oracle.classify(rules, pk, threads=8)
+    assert (want[0] >= 0).mean() > 0.3 and (want[0] < 0).any()
+    for kw in SCAN_MODES:
+        say(f"second-field seed={seed} {kw}")
+        assert_same(classify_np(rules, pk, **kw), want, f"second-field {seed} {kw}")
+    with fw.Ruleset(rules) as rs:
+        dp = fw.DevicePackets.from_host(pk)
+        for K in (1, 2, 4):
+            for placement, tile in ((1, 0), (2, 256), (2, 1024), (3, 0), (4, 0)):
+                say(f"second-field seed={seed} multi K={K} placement={placement} tile={tile}")
+                oi = torch.full((len(pk),), 7, dtype=torch.int32, device="cuda")
+                oa = torch.full((len(pk),), 9, dtype=torch.uint8, device="cuda")
+                fw.classify_multi([(rs, dp, oi, oa)], packets_per_lane=K, placement=placement,
+                                  rule_tile=tile)
+                torch.cuda.synchronize()
+                assert_same((oi.cpu().numpy(), oa.cpu().numpy()), want,
+                            f"second-field {seed} multi K={K} placement={placement} tile={tile}")
+        say(f"second-field seed={seed} learned")
+        rs.build_learned_index(epochs1=200, epochs2=400)
+        idx, act = rs.classify(dp, mode="learned")
+        torch.cuda.synchronize()
+        assert_same((idx.cpu().numpy(), act.cpu().numpy()), want, f"second-field {seed} learned")
+
+
 def test_closed_loop_probe():
     """fw_closed_loop classifies each batch like fw_classify_ex (checked on its last batch,
     whose results are left in the output arrays), reports a positive time per batch, and
