@@ -31,8 +31,10 @@ struct ChainDesc {
     uint64_t n;
     uint32_t n_rules, dflt;  // view->n_rules, view->dflt
     uint32_t item_begin;
-    uint32_t has_index;      // view->has_index
+    uint32_t index;          // kChainIndexed: view->has_index; kChainBoundariesInLds: this
+                             // launch stages the index's image with its boundary arrays
 };
+constexpr uint32_t kChainIndexed = 1, kChainBoundariesInLds = 2;
 
 // Placements (fw_multi_opts.placement): grouped plan and learned index, or
 // the rule list in rule order through the scalar cache, LDS tiles or vector

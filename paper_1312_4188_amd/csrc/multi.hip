@@ -109,9 +109,10 @@ __device__ __forceinline__ PacketsDev packets_of(const ChainDesc& c) {
 // Default placement: work-groups of 16 waves take items of 1024*K packets.  A
 // chain with a learned index (and use_index set) goes through the learned
 // lookup: the work-group stages that index's LDS image when its previous item
-// was of another chain (B_LDS: the images with the boundary arrays, chosen
-// for a launch when every index's fits the LDS budget, as the single-chain
-// kernel chooses per index); the others through the grouped-plan wave scan,
+// was of another chain (B_LDS: the image with the boundary arrays, chosen per
+// chain when it fits the LDS budget, as the single-chain kernel chooses per
+// index; the launch's LDS is the largest image its chains use); the others
+// through the grouped-plan wave scan,
 // which needs no LDS.  Staging follows the two barriers of the item fetch, so
 // no wave still reads the image it replaces.
 // The two kinds of item as separate functions: each gets the kernel's whole
@@ -134,7 +135,7 @@ __device__ __attribute__((noinline)) void auto_scan_item(const ChainDesc& c, siz
     w.store(c.out_idx, c.out_act, c.n);
 }
 
-template <int K, bool B_LDS>
+template <int K>
 __global__ __launch_bounds__(kLearnedBlock, K >= 4 ? 4 : 8) void k_multi_auto(
     const ChainDesc* __restrict__ cd, uint32_t n_chains, uint32_t total_items,
     uint32_t* __restrict__ counter, uint32_t use_index) {
@@ -150,8 +151,11 @@ __global__ __launch_bounds__(kLearnedBlock, K >= 4 ? 4 : 8) void k_multi_auto(
         if (item >= total_items) break;
         const ChainDesc& c = cd[chain_of(cd, n_chains, item)];
         const size_t base = size_t(item - c.item_begin) * (size_t(kLearnedBlock) * K) + wave_off;
-        if (use_index && c.has_index) {
-            auto_learned_item<K, B_LDS>(c, base, smem, staged != c.view);
+        if (use_index && (c.index & kChainIndexed)) {
+            if (c.index & kChainBoundariesInLds)
+                auto_learned_item<K, true>(c, base, smem, staged != c.view);
+            else
+                auto_learned_item<K, false>(c, base, smem, staged != c.view);
             staged = c.view;
         } else if (base < c.n) {
             auto_scan_item<K>(c, base);
@@ -335,7 +339,8 @@ hipError_t multi_launch(const fw_chain_batch* b, uint32_t n_chains, MultiConfig 
         desc = local.data();
     }
     uint64_t items = 0;
-    uint32_t lds_b = 0, lds_nob = 0;   // largest learned image with / without the boundaries
+    const uint32_t cap = lds_cap_for(cfg.K);
+    size_t lds = 0;   // the largest learned image the launch's chains use
     for (uint32_t k = 0; k < nc; ++k) {
         const fw_chain_batch& cb = b[order[k]];
         ChainDesc& d = desc[k];
@@ -346,7 +351,7 @@ hipError_t multi_launch(const fw_chain_batch* b, uint32_t n_chains, MultiConfig 
         d.pairs = hv->pairs;
         d.n_rules = hv->n_rules;
         d.dflt = hv->dflt;
-        d.has_index = hv->has_index;
+        d.index = hv->has_index ? kChainIndexed : 0u;
         d.src = cb.pk.src_ip;
         d.dst = cb.pk.dst_ip;
         d.sport = cb.pk.src_port;
@@ -358,12 +363,11 @@ hipError_t multi_launch(const fw_chain_batch* b, uint32_t n_chains, MultiConfig 
         d.item_begin = uint32_t(items);
         items += (cb.n + per_item - 1) / per_item;
         if (cfg.placement == kPlaceAuto && cfg.use_index && hv->has_index) {
-            lds_b = std::max(lds_b, hv->lds_b);
-            lds_nob = std::max(lds_nob, hv->lds_nob);
+            const bool b_lds = hv->lds_b <= cap;
+            if (b_lds) d.index |= kChainBoundariesInLds;
+            lds = std::max<size_t>(lds, b_lds ? hv->lds_b : hv->lds_nob);
         }
     }
-    const bool b_lds = lds_b <= lds_cap_for(cfg.K);
-    const size_t lds = b_lds ? lds_b : lds_nob;
     if (items >= 0xFFFFFFFFull) return hipErrorInvalidValue;
     void* mem = scratch_mem;
     hipError_t e = hipSuccess;
@@ -400,27 +404,21 @@ hipError_t multi_launch(const fw_chain_batch* b, uint32_t n_chains, MultiConfig 
             e = hipGetLastError();                                                          \
         }                                                                                   \
     } while (0)
-#define FW_MULTI_AUTO(KK, BL)                                                               \
+#define FW_MULTI_AUTO(KK)                                                                   \
     do {                                                                                    \
         if (e == hipSuccess)                                                                \
-            e = persistent_grid(k_multi_auto<KK, BL>, kLearnedBlock, lds, total, &grid);    \
+            e = persistent_grid(k_multi_auto<KK>, kLearnedBlock, lds, total, &grid);        \
         if (e == hipSuccess) {                                                              \
-            hipLaunchKernelGGL((k_multi_auto<KK, BL>), dim3(grid), dim3(kLearnedBlock), lds, \
+            hipLaunchKernelGGL((k_multi_auto<KK>), dim3(grid), dim3(kLearnedBlock), lds,    \
                                s, table, nc, total, counter, uint32_t(cfg.use_index));      \
             e = hipGetLastError();                                                          \
         }                                                                                   \
     } while (0)
     switch (cfg.placement) {
         case kPlaceAuto:
-            if (b_lds) {
-                if (cfg.K == 1) FW_MULTI_AUTO(1, true);
-                else if (cfg.K == 2) FW_MULTI_AUTO(2, true);
-                else FW_MULTI_AUTO(4, true);
-            } else {
-                if (cfg.K == 1) FW_MULTI_AUTO(1, false);
-                else if (cfg.K == 2) FW_MULTI_AUTO(2, false);
-                else FW_MULTI_AUTO(4, false);
-            }
+            if (cfg.K == 1) FW_MULTI_AUTO(1);
+            else if (cfg.K == 2) FW_MULTI_AUTO(2);
+            else FW_MULTI_AUTO(4);
             break;
         case kPlaceVector:
             if (cfg.K == 1) FW_MULTI(k_multi_vector<1>);

@@ -85,8 +85,8 @@ def test_learned_and_scanned_chains_in_one_launch(K, big_index):
     """Placement 4 routes chains with a learned index through the learned lookup (their LDS
     images staged as work-groups move between chains) and the rest through the grouped-plan
     scan, in one launch.  With big_index one chain's boundary array is too large for LDS, so
-    every index in the launch is searched in global memory.  Each chain against the oracle,
-    and again on a second call with fewer chains."""
+    that index is searched in global memory while the others keep theirs in LDS, in the same
+    launch.  Each chain against the oracle, and again on a second call with fewer chains."""
     import torch
     fw = fwmod()
     work = []
