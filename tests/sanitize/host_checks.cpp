@@ -159,6 +159,12 @@ void check_lists(const std::vector<RuleRec>& rules, Rng& g, const char* what) {
     fw::build_port_table(hl.Gw, &pt, &count, &steps_s, &steps_d, &rest);
     CHECK(count <= fw::kPtRules && count + rest.size() == hl.Gw.size(), "%s: port table split",
           what);
+    // the lookup scans the rules past the table without address tests: grouped,
+    // they form port- and protocol-first groups only
+    fw::PlanGroups rg;
+    fw::group_rules(rest.data(), uint32_t(rest.size()), &rg);
+    CHECK(rg.grp[fw::kFirstDst].empty() && rg.grp[fw::kFirstSrc].empty(),
+          "%s: an address-first group past the port table", what);
     std::vector<uint16_t> bucket;
     uint32_t bits = 0, bsteps = 0;
     fw::build_bucket_table(hl.Bs, &bucket, &bits, &bsteps);
