@@ -163,6 +163,48 @@ __global__ __launch_bounds__(kLearnedBlock, K >= 4 ? 4 : 8) void k_multi_auto(
     }
 }
 
+// The default placement when every chain of the launch has a learned index
+// (and use_index is set): the same items and staging as k_multi_auto, with
+// the learned tile inlined into the kernel (no scan item beside it, so no
+// call and none of its register spills).  BL: every chain's boundary arrays
+// in LDS (kBlAll), none (kBlNone), or chosen per chain (kBlMixed, both
+// variants of the tile in one body).
+constexpr int kBlNone = 0, kBlAll = 1, kBlMixed = 2;
+
+template <int K, int BL>
+__global__ __launch_bounds__(kLearnedBlock, K >= 4 ? 4 : 8) void k_multi_learned(
+    const ChainDesc* __restrict__ cd, uint32_t n_chains, uint32_t total_items,
+    uint32_t* __restrict__ counter) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ uint32_t s_item;
+    const size_t wave_off = size_t(wave_in_group()) * 64u * K;
+    const ChainView* staged = nullptr;   // whose image is in LDS (work-group uniform)
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
+        __syncthreads();
+        const uint32_t item = s_item;
+        __syncthreads();
+        if (item >= total_items) break;
+        const ChainDesc& c = cd[chain_of(cd, n_chains, item)];
+        const size_t base = size_t(item - c.item_begin) * (size_t(kLearnedBlock) * K) + wave_off;
+        const ChainView& v = *c.view;
+        const bool stage = staged != c.view;
+        staged = c.view;
+        if (BL == kBlAll || (BL == kBlMixed && (c.index & kChainBoundariesInLds))) {
+            const IndexView iv = stage ? stage_index<true>(v.la, smem) : index_view<true>(v.la, smem);
+            if (base < c.n)
+                learned_tile<K, true>(v.la, iv, packets_of(c), base, c.n, c.out_idx, c.out_act,
+                                      v.dflt);
+        } else {
+            const IndexView iv =
+                stage ? stage_index<false>(v.la, smem) : index_view<false>(v.la, smem);
+            if (base < c.n)
+                learned_tile<K, true>(v.la, iv, packets_of(c), base, c.n, c.out_idx, c.out_act,
+                                      v.dflt);
+        }
+    }
+}
+
 // Scalar placement: each wave takes 64*K-packet items on its own.
 template <int K>
 __global__ __launch_bounds__(256) void k_multi_scalar(const ChainDesc* __restrict__ cd,
@@ -341,6 +383,8 @@ hipError_t multi_launch(const fw_chain_batch* b, uint32_t n_chains, MultiConfig 
     uint64_t items = 0;
     const uint32_t cap = lds_cap_for(cfg.K);
     size_t lds = 0;   // the largest learned image the launch's chains use
+    bool all_learned = cfg.placement == kPlaceAuto && cfg.use_index;
+    uint32_t n_in_lds = 0, n_indexed = 0;   // chains whose boundary arrays go to LDS / all
     for (uint32_t k = 0; k < nc; ++k) {
         const fw_chain_batch& cb = b[order[k]];
         ChainDesc& d = desc[k];
@@ -362,9 +406,12 @@ hipError_t multi_launch(const fw_chain_batch* b, uint32_t n_chains, MultiConfig 
         d.n = cb.n;
         d.item_begin = uint32_t(items);
         items += (cb.n + per_item - 1) / per_item;
+        if (!hv->has_index) all_learned = false;
         if (cfg.placement == kPlaceAuto && cfg.use_index && hv->has_index) {
             const bool b_lds = hv->lds_b <= cap;
             if (b_lds) d.index |= kChainBoundariesInLds;
+            n_in_lds += b_lds ? 1u : 0u;
+            ++n_indexed;
             lds = std::max<size_t>(lds, b_lds ? hv->lds_b : hv->lds_nob);
         }
     }
@@ -404,14 +451,33 @@ hipError_t multi_launch(const fw_chain_batch* b, uint32_t n_chains, MultiConfig 
             e = hipGetLastError();                                                          \
         }                                                                                   \
     } while (0)
-#define FW_MULTI_AUTO(KK)                                                                   \
+#define FW_MULTI_LEARNED(KK, BL)                                                            \
     do {                                                                                    \
         if (e == hipSuccess)                                                                \
-            e = persistent_grid(k_multi_auto<KK>, kLearnedBlock, lds, total, &grid);        \
+            e = persistent_grid(k_multi_learned<KK, BL>, kLearnedBlock, lds, total, &grid); \
         if (e == hipSuccess) {                                                              \
-            hipLaunchKernelGGL((k_multi_auto<KK>), dim3(grid), dim3(kLearnedBlock), lds,    \
-                               s, table, nc, total, counter, uint32_t(cfg.use_index));      \
+            hipLaunchKernelGGL((k_multi_learned<KK, BL>), dim3(grid), dim3(kLearnedBlock),  \
+                               lds, s, table, nc, total, counter);                          \
             e = hipGetLastError();                                                          \
+        }                                                                                   \
+    } while (0)
+#define FW_MULTI_AUTO(KK)                                                                   \
+    do {                                                                                    \
+        if (all_learned && n_in_lds == n_indexed) {                                         \
+            FW_MULTI_LEARNED(KK, kBlAll);                                                   \
+        } else if (all_learned && n_in_lds == 0) {                                          \
+            FW_MULTI_LEARNED(KK, kBlNone);                                                  \
+        } else if (all_learned) {                                                           \
+            FW_MULTI_LEARNED(KK, kBlMixed);                                                 \
+        } else {                                                                            \
+            if (e == hipSuccess)                                                            \
+                e = persistent_grid(k_multi_auto<KK>, kLearnedBlock, lds, total, &grid);    \
+            if (e == hipSuccess) {                                                          \
+                hipLaunchKernelGGL((k_multi_auto<KK>), dim3(grid), dim3(kLearnedBlock),     \
+                                   lds, s, table, nc, total, counter,                       \
+                                   uint32_t(cfg.use_index));                                \
+                e = hipGetLastError();                                                      \
+            }                                                                               \
         }                                                                                   \
     } while (0)
     switch (cfg.placement) {
@@ -443,6 +509,7 @@ hipError_t multi_launch(const fw_chain_batch* b, uint32_t n_chains, MultiConfig 
             break;
     }
 #undef FW_MULTI_AUTO
+#undef FW_MULTI_LEARNED
 #undef FW_MULTI
     if (scratch_mem) return e;
     release_on_throw.dismiss();

@@ -120,3 +120,38 @@ def test_learned_and_scanned_chains_in_one_launch(K, big_index):
         _check([work[i] for i in pick], sub, f"K={K} {what}")
     for rs in rss:
         rs.close()
+
+
+@pytest.mark.parametrize("K", [1, 2, 4])
+def test_every_chain_indexed_boundary_placements(K):
+    """Every chain with a learned index (the launch without scan items): the boundary arrays of
+    all chains in LDS, of none (one index too large for LDS alone), and of some (that index
+    beside small ones); each chain against the oracle."""
+    import torch
+    fw = fwmod()
+    work = []
+    for c, (R, n) in enumerate([(3_000, 60_000), (800, 20_000), (6_000, 90_000)]):
+        rules = gen.make_rules(R, 700 + c, skew=True)
+        work.append((rules, gen.make_packets(rules, n, 700 + c)))
+    big = gen.make_rules(30_000, 799, skew=True)
+    big.dst_plen[big.dst_plen == 0] = 24
+    work.append((big, gen.make_packets(big, 50_000, 799)))
+    items = []
+    for c, (rules, pk) in enumerate(work):
+        rs = fw.Ruleset(rules)
+        rs.build_learned_index(epochs1=300, epochs2=600, seed=c)
+        n = len(pk)
+        items.append((rs, fw.DevicePackets.from_host(pk),
+                      torch.full((n,), 7, dtype=torch.int32, device="cuda"),
+                      torch.full((n,), 9, dtype=torch.uint8, device="cuda")))
+    torch.cuda.synchronize()
+    for what, pick in (("all in LDS", [0, 1, 2]), ("none in LDS", [3]), ("mixed", [0, 1, 2, 3])):
+        say(f"every chain indexed K={K}: {what}")
+        sub = [items[i] for i in pick]
+        for _, _, oi, oa in sub:
+            oi.fill_(7)
+            oa.fill_(9)
+        fw.classify_multi(sub, packets_per_lane=K, placement=4)
+        _check([work[i] for i in pick], sub, f"K={K} {what}")
+    for rs, _, _, _ in items:
+        rs.close()
