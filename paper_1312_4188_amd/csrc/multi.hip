@@ -205,6 +205,32 @@ __global__ __launch_bounds__(kLearnedBlock, K >= 4 ? 4 : 8) void k_multi_learned
     }
 }
 
+// The default placement when no chain of the launch is looked up through a
+// learned index: the same items with the grouped-plan wave scan inlined (no
+// call, no LDS).
+template <int K>
+__global__ __launch_bounds__(kLearnedBlock, K >= 4 ? 4 : 8) void k_multi_scan(
+    const ChainDesc* __restrict__ cd, uint32_t n_chains, uint32_t total_items,
+    uint32_t* __restrict__ counter) {
+    __shared__ uint32_t s_item;
+    const size_t wave_off = size_t(wave_in_group()) * 64u * K;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
+        __syncthreads();
+        const uint32_t item = s_item;
+        __syncthreads();
+        if (item >= total_items) break;
+        const ChainDesc& c = cd[chain_of(cd, n_chains, item)];
+        const size_t base = size_t(item - c.item_begin) * (size_t(kLearnedBlock) * K) + wave_off;
+        if (base < c.n) {
+            WaveScan<K> w;
+            w.init(packets_of(c), base, c.n, c.dflt);
+            w.scan_plan(c.view->plan);
+            w.store(c.out_idx, c.out_act, c.n);
+        }
+    }
+}
+
 // Scalar placement: each wave takes 64*K-packet items on its own.
 template <int K>
 __global__ __launch_bounds__(256) void k_multi_scalar(const ChainDesc* __restrict__ cd,
@@ -384,7 +410,9 @@ hipError_t multi_launch(const fw_chain_batch* b, uint32_t n_chains, MultiConfig 
     const uint32_t cap = lds_cap_for(cfg.K);
     size_t lds = 0;   // the largest learned image the launch's chains use
     bool all_learned = cfg.placement == kPlaceAuto && cfg.use_index;
-    uint32_t n_in_lds = 0, n_indexed = 0;   // chains whose boundary arrays go to LDS / all
+    // chains looked up through their index (none unless the default placement
+    // takes indexes), and those of them whose boundary arrays go to LDS
+    uint32_t n_in_lds = 0, n_indexed = 0;
     for (uint32_t k = 0; k < nc; ++k) {
         const fw_chain_batch& cb = b[order[k]];
         ChainDesc& d = desc[k];
@@ -469,6 +497,14 @@ hipError_t multi_launch(const fw_chain_batch* b, uint32_t n_chains, MultiConfig 
             FW_MULTI_LEARNED(KK, kBlNone);                                                  \
         } else if (all_learned) {                                                           \
             FW_MULTI_LEARNED(KK, kBlMixed);                                                 \
+        } else if (n_indexed == 0) {                                                        \
+            if (e == hipSuccess)                                                            \
+                e = persistent_grid(k_multi_scan<KK>, kLearnedBlock, 0, total, &grid);      \
+            if (e == hipSuccess) {                                                          \
+                hipLaunchKernelGGL((k_multi_scan<KK>), dim3(grid), dim3(kLearnedBlock), 0,  \
+                                   s, table, nc, total, counter);                           \
+                e = hipGetLastError();                                                      \
+            }                                                                               \
         } else {                                                                            \
             if (e == hipSuccess)                                                            \
                 e = persistent_grid(k_multi_auto<KK>, kLearnedBlock, lds, total, &grid);    \
